@@ -1,0 +1,36 @@
+// Launch helpers for the per-class kernels (one translation unit per class).
+#include "hfx_internal.h"
+#include "generated/eri_classes.h"
+
+#define HFX_DECL(cid)                                        \
+    extern "C" const void* hfx_class_kernel_##cid(int);      \
+    extern "C" const void* hfx_schwarz_kernel_##cid(void);
+HFX_FOR_EACH_CID(HFX_DECL)
+
+#define HFX_KPTR(cid) hfx_class_kernel_##cid,
+#define HFX_SPTR(cid) hfx_schwarz_kernel_##cid,
+static const void* (*const kClassLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_KPTR)};
+static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPTR)};
+
+#define HFX_WG 256
+
+extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_bytes,
+                                       hipStream_t stream, const ClassArgs* args) {
+    if (ntask <= 0) return hipSuccess;
+    const void* fn = kClassLookup[cid](mode * 2 + mixed);
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    void* kargs[] = {(void*)args};
+    return hipLaunchKernel(fn, dim3(ntask), dim3(HFX_WG), kargs, lds_bytes, stream);
+}
+
+extern "C" hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim,
+                                         const double* boys, const double* cscale, double* Q,
+                                         hipStream_t stream) {
+    if (npairs <= 0) return hipSuccess;
+    const void* fn = kSchwarzLookup[cid]();
+    void* kargs[] = {(void*)&pairs, (void*)&npairs, (void*)&prim, (void*)&boys, (void*)&cscale, (void*)&Q};
+    return hipLaunchKernel(fn, dim3((npairs + HFX_WG - 1) / HFX_WG), dim3(HFX_WG), kargs, 0, stream);
+}

@@ -1,0 +1,379 @@
+// Direct J/K digestion kernels: one launch per canonical quartet class.
+//
+// Work decomposition (the paper's algorithm 3 re-expressed for one GPU):
+// pairs of a class are sorted by Schwarz bound Q, so for a bra pair r the
+// kets that survive screening Q_r Q_s >= tau are a prefix of the ket list
+// (for bra and ket of the same class, additionally s <= r keeps each
+// unordered quartet once).  A workgroup task is one bra pair and up to
+// task_quartets consecutive kets of its prefix; lanes take one quartet each.
+//
+// Digestion (section 4.1, eq. 2) accumulates W with
+//   W_ab += 2 cj g D_cd,  W_cd += 2 cj g D_ab,
+//   W_ac -= ck g D_bd,    W_bd -= ck g D_ac,  W_ad -= ck g D_bc,  W_bc -= ck g D_ad,
+// g = s (ab|cd), s the number of distinct permutations of the unique quartet,
+// and the two-electron Fock part is (W + W^T)/8 = cj J - ck K.
+//
+// MODE 0 (LDS-staged): like algorithm 3's private F_I / F_J buffers, the two
+// bra rows a and b of W live in LDS for the whole task: the bra block W_ab
+// is summed in registers, W_ac/W_ad/W_bc/W_bd go to LDS with ds_add_f64, and
+// only the ket block W_cd goes straight to HBM with global atomics.  At the
+// end of the task the LDS rows are flushed with one atomic per touched
+// element.  MODE 1 (shared global): every update is a global atomic.
+#pragma once
+#include "hfx_internal.h"
+
+#define HFX_WG 256
+// integral blocks at least this large are digested with rolled loops
+#define HFX_ROLLED_DIGEST_MIN 600
+
+
+
+template <int MODE>
+__device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, int col, int N, double v) {
+    if constexpr (MODE == 0) {
+        atomicAdd(lds_row + col, v);
+    } else {
+        atomicAdd(W + (size_t)grow * N + col, v);
+    }
+}
+
+template <int NA, int NB, int NC, int ND, int MODE>
+__device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
+                                       const PairInfo& ket, const double* dab, double* jab, double* FI,
+                                       double* FJ) {
+    const int N = a.nbf;
+    const double* __restrict__ D = a.D;
+    double* __restrict__ W = a.W;
+    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+    const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
+    // J, bra block: per-lane running sums over the task (reduced at the end)
+    {
+        double dcd[NC * ND];
+#pragma unroll
+        for (int l = 0; l < NC; ++l)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) dcd[l * ND + s] = D[(size_t)(fc + l) * N + fd + s];
+#pragma unroll
+        for (int mn = 0; mn < NA * NB; ++mn) {
+            double v = 0.0;
+#pragma unroll
+            for (int ls = 0; ls < NC * ND; ++ls) v += I[mn * NC * ND + ls] * dcd[ls];
+            jab[mn] += g * v;
+        }
+    }
+    // J, ket block: global atomics
+#pragma unroll
+    for (int l = 0; l < NC; ++l)
+#pragma unroll
+        for (int s = 0; s < ND; ++s) {
+            double v = 0.0;
+#pragma unroll
+            for (int mn = 0; mn < NA * NB; ++mn) v += I[mn * NC * ND + l * ND + s] * dab[mn];
+            atomicAdd(W + (size_t)(fc + l) * N + fd + s, cj2 * v);
+        }
+    // K: W_ac -= ck g sum_{nu sigma} I D_bd
+    {
+        double dbd[NB * ND];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) dbd[n * ND + s] = D[(size_t)(fb + n) * N + fd + s];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) {
+                double v = 0.0;
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dbd[n * ND + s];
+                row_add<MODE>(FI + m * N, W, fa + m, fc + l, N, ckg * v);
+            }
+    }
+    // K: W_bd -= ck g sum_{mu lambda} I D_ac
+    {
+        double dac[NA * NC];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) dac[m * NC + l] = D[(size_t)(fa + m) * N + fc + l];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < NA; ++m)
+#pragma unroll
+                    for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dac[m * NC + l];
+                row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v);
+            }
+    }
+    // K: W_ad -= ck g sum_{nu lambda} I D_bc
+    {
+        double dbc[NB * NC];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) dbc[n * NC + l] = D[(size_t)(fb + n) * N + fc + l];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) {
+                double v = 0.0;
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dbc[n * NC + l];
+                row_add<MODE>(FI + m * N, W, fa + m, fd + s, N, ckg * v);
+            }
+    }
+    // K: W_bc -= ck g sum_{mu sigma} I D_ad
+    {
+        double dad[NA * ND];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) dad[m * ND + s] = D[(size_t)(fa + m) * N + fd + s];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < NA; ++m)
+#pragma unroll
+                    for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dad[m * ND + s];
+                row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v);
+            }
+    }
+}
+
+// Same updates with rolled loops, for classes whose integral block is too
+// large to keep in registers (the block then lives in scratch).
+template <int NA, int NB, int NC, int ND, int MODE>
+__device__ __forceinline__ void digest_rolled(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
+                                              const PairInfo& ket, const double* dab, double* jab, double* FI,
+                                              double* FJ) {
+    const int N = a.nbf;
+    const double* __restrict__ D = a.D;
+    double* __restrict__ W = a.W;
+    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+    const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
+#pragma unroll 1
+    for (int mn = 0; mn < NA * NB; ++mn) {
+        double v = 0.0;
+#pragma unroll 1
+        for (int ls = 0; ls < NC * ND; ++ls)
+            v += I[mn * NC * ND + ls] * D[(size_t)(fc + ls / ND) * N + fd + ls % ND];
+        jab[mn] += g * v;
+    }
+#pragma unroll 1
+    for (int ls = 0; ls < NC * ND; ++ls) {
+        double v = 0.0;
+#pragma unroll 1
+        for (int mn = 0; mn < NA * NB; ++mn) v += I[mn * NC * ND + ls] * dab[mn];
+        atomicAdd(W + (size_t)(fc + ls / ND) * N + fd + ls % ND, cj2 * v);
+    }
+#pragma unroll 1
+    for (int m = 0; m < NA; ++m)
+#pragma unroll 1
+        for (int l = 0; l < NC; ++l) {
+            double v1 = 0.0;
+#pragma unroll 1
+            for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+                for (int s = 0; s < ND; ++s)
+                    v1 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
+            row_add<MODE>(FI + m * N, W, fa + m, fc + l, N, ckg * v1);
+        }
+#pragma unroll 1
+    for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+        for (int s = 0; s < ND; ++s) {
+            double v2 = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < NA; ++m)
+#pragma unroll 1
+                for (int l = 0; l < NC; ++l)
+                    v2 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fc + l];
+            row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v2);
+        }
+#pragma unroll 1
+    for (int m = 0; m < NA; ++m)
+#pragma unroll 1
+        for (int s = 0; s < ND; ++s) {
+            double v3 = 0.0;
+#pragma unroll 1
+            for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+                for (int l = 0; l < NC; ++l)
+                    v3 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
+            row_add<MODE>(FI + m * N, W, fa + m, fd + s, N, ckg * v3);
+        }
+#pragma unroll 1
+    for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+        for (int l = 0; l < NC; ++l) {
+            double v4 = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < NA; ++m)
+#pragma unroll 1
+                for (int s = 0; s < ND; ++s)
+                    v4 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fd + s];
+            row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v4);
+        }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One class, one digestion mode, one precision policy (MIXED = 1: kets at or
+// beyond split[r] are evaluated in FP32 and widened before digestion).
+template <class E, int MODE, int MIXED>
+__global__ __launch_bounds__(HFX_WG) void k_class(const ClassArgs a) {
+    constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
+    constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
+    extern __shared__ double lds[];
+    const int N = a.nbf;
+    const int2 task = a.tasks[blockIdx.x];
+    const int r = task.x, s0 = task.y;
+    const PairInfo bra = a.bra[r];
+    const int nk = a.nket[r];
+    const int send = min(s0 + a.task_quartets, nk);
+    const int split = MIXED ? a.split[r] : nk;
+    double* FI = lds;
+    double* FJ = lds + NA * N;
+    if constexpr (MODE == 0) {
+        for (int i = threadIdx.x; i < (NA + NB) * N; i += HFX_WG) lds[i] = 0.0;
+        __syncthreads();
+    }
+    double dab[NAB], jab[NAB];
+#pragma unroll
+    for (int m = 0; m < NA; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            dab[m * NB + n] = a.D[(size_t)(bra.bfa + m) * N + bra.bfb + n];
+            jab[m * NB + n] = 0.0;
+        }
+    const double sbra = bra.a != bra.b ? 2.0 : 1.0;
+    unsigned n64 = 0, n32 = 0;
+    for (int s = s0 + (int)threadIdx.x; s < send; s += HFX_WG) {
+        const PairInfo ket = a.ket[s];
+        double I[NI];
+        if (!MIXED || s < split) {
+            E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.prim + ket.prim_off, ket.nprim, bra.AB,
+                                    ket.AB, a.boys64, I);
+            ++n64;
+        } else {
+            float If[NI];
+            E::template run<float>(a.prim + bra.prim_off, bra.nprim, a.prim + ket.prim_off, ket.nprim, bra.AB,
+                                   ket.AB, a.boys32, If);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
+            ++n32;
+        }
+        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((a.same_class && s == r) ? 1.0 : 2.0);
+        if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ);
+        else
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ);
+    }
+    // bra J block: wave reduction, one add per wave
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int mn = 0; mn < NAB; ++mn) {
+        const double v = wave_sum(jab[mn]);
+        if (lane == 0) {
+            const int m = mn / NB, n = mn % NB;
+            row_add<MODE>(FI + m * N, a.W, bra.bfa + m, bra.bfb + n, N, 2.0 * a.cj * v);
+        }
+    }
+    // quartet counters (one atomic per wave)
+    {
+        unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
+        unsigned long long c32 = (unsigned long long)wave_sum((double)n32);
+        if (lane == 0 && a.counters) {
+            if (c64) atomicAdd(a.counters + 0, c64);
+            if (c32) atomicAdd(a.counters + 1, c32);
+        }
+    }
+    if constexpr (MODE == 0) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < (NA + NB) * N; i += HFX_WG) {
+            const double v = lds[i];
+            if (v != 0.0) {
+                const int row = i < NA * N ? bra.bfa + i / N : bra.bfb + (i - NA * N) / N;
+                const int col = i < NA * N ? i % N : (i - NA * N) % N;
+                atomicAdd(a.W + (size_t)row * N + col, v);
+            }
+        }
+    }
+}
+
+// Schwarz bound of every pair of one pair class: Q = sqrt(max (mn|mn)) with
+// the component normalisation s_m s_n applied (always FP64).
+template <class E>
+__global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__ pairs, int npairs,
+                                                     const PrimPair* __restrict__ prim,
+                                                     const double* __restrict__ boys,
+                                                     const double* __restrict__ cscale, double* __restrict__ Q) {
+    constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB);
+    const int i = blockIdx.x * HFX_WG + threadIdx.x;
+    if (i >= npairs) return;
+    const PairInfo pr = pairs[i];
+    double I[NA * NB * NA * NB];
+    E::template run<double>(prim + pr.prim_off, pr.nprim, prim + pr.prim_off, pr.nprim, pr.AB, pr.AB, boys, I);
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < NA; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const double s = cscale[pr.bfa + m] * cscale[pr.bfb + n];
+            const double v = I[(m * NB + n) * NA * NB + m * NB + n] * s * s;
+            mx = v > mx ? v : mx;
+        }
+    Q[i] = sqrt(mx);
+}
+
+
+// Kernel variants of one class: digestion mode x precision policy.  Classes
+// with integral blocks of HFX_ROLLED_DIGEST_MIN or more (d-d bra with a d-d or
+// d-p ket) exist only as the FP64 global-atomic kernel: their register
+// allocation is the build-time bottleneck and they carry a negligible share
+// of the quartets, so MIXED and LDS requests run that kernel (FP64 is the
+// more accurate choice).
+template <class E>
+struct ClassKernels {
+    static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
+    static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
+    static const void* get(int variant) {
+        if constexpr (kOnlyFp64Global) {
+            (void)variant;
+            return (const void*)k_class<E, 1, 0>;
+        } else {
+            static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 0, 1>,
+                                       (const void*)k_class<E, 1, 0>, (const void*)k_class<E, 1, 1>};
+            return t[variant];
+        }
+    }
+};
+
+// Per-class translation unit: evaluator wrapper, the four kernel variants
+// (digestion mode x precision policy), the Schwarz kernel and C lookups.
+#define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_)                                                      \
+    struct Eval##cid {                                                                                 \
+        static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_;                                   \
+        template <typename R>                                                                          \
+        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const PrimPair* kp,    \
+                                                   int nkp, const double* ab, const double* cd,        \
+                                                   const R* tab, R* out) {                             \
+            fname<R>(bp, nbp, kp, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]), R(cd[2]),    \
+                     tab, out);                                                                        \
+        }                                                                                              \
+    };                                                                                                 \
+    extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \
+    extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }

@@ -1,0 +1,268 @@
+"""Generate the per-class electron-repulsion-integral device functions.
+
+For each of the 21 canonical quartet classes (l_a l_b | l_c l_d) with
+l_a >= l_b, l_c >= l_d and bra pair class >= ket pair class (s, p and
+Cartesian d shells), emit a straight-line HIP device function that
+
+1. loops over the primitive pairs of the bra and the ket,
+2. evaluates the Boys function F_m(T), m = 0..L,
+3. runs the Obara-Saika vertical recurrence to [e0|f0]^(0) for
+   l_a <= |e| <= l_a+l_b and l_c <= |f| <= l_c+l_d and accumulates those
+   over the primitives (contraction before transfer, Head-Gordon-Pople),
+4. applies the horizontal recurrence on the bra, then on the ket,
+   (a, b+1_i| = (a+1_i, b| + AB_i (a, b|, to produce the contracted
+   (ab|cd) block over raw Cartesian components.
+
+The recurrences (Obara & Saika, J. Chem. Phys. 84, 3963 (1986);
+Head-Gordon & Pople, J. Chem. Phys. 89, 5777 (1988)):
+
+  [e+1_i|f]^(m) = PA_i [e|f]^(m) + WP_i [e|f]^(m+1)
+                 + e_i/(2p) ([e-1_i|f]^(m) - rho/p [e-1_i|f]^(m+1))
+                 + f_i/(2(p+q)) [e|f-1_i]^(m+1)
+  [e|f+1_i]^(m) = QC_i [e|f]^(m) + WQ_i [e|f]^(m+1)
+                 + f_i/(2q) ([e|f-1_i]^(m) - rho/q [e|f-1_i]^(m+1))
+                 + e_i/(2(p+q)) [e-1_i|f]^(m+1)
+  [0|0]^(m)     = K_ab K_cd 2 pi^{5/2} / (p q sqrt(p+q)) F_m(rho |PQ|^2)
+
+The functions are templated on the real type (double or float) so the same
+text yields the FP64 and FP32 evaluators.  The bra is built first (f = 0),
+then the ket; the recursion direction is the axis with the smallest
+non-zero exponent (fewest terms).
+
+Usage: python gen_eri.py OUT_DIR
+"""
+from __future__ import annotations
+
+import sys
+
+PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+PAIR_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd"]
+CLASSES = [(B, K) for B in range(6) for K in range(B + 1)]
+
+
+def cart(l):
+    return [(x, y, l - x - y) for x in range(l, -1, -1) for y in range(l - x, -1, -1)]
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def sub(v, i):
+    t = list(v)
+    t[i] -= 1
+    return tuple(t)
+
+
+def add(v, i):
+    t = list(v)
+    t[i] += 1
+    return tuple(t)
+
+
+def direction(v):
+    best = None
+    for i in range(3):
+        if v[i] > 0 and (best is None or v[i] < v[best]):
+            best = i
+    return best
+
+
+class ClassGen:
+    def __init__(self, la, lb, lc, ld):
+        self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
+        self.L = la + lb + lc + ld
+        self.vrr_nodes = {}
+        self.vrr_code = []
+        self.base_used = set()
+        self.nv = 0
+        self.flops = 0
+
+    # ---- vertical recurrence (inside the primitive loop) ----
+    def vrr(self, e, f, m):
+        key = (e, f, m)
+        if key in self.vrr_nodes:
+            return self.vrr_nodes[key]
+        if sum(e) == 0 and sum(f) == 0:
+            self.base_used.add(m)
+            name = f"b{m}"
+            self.vrr_nodes[key] = name
+            return name
+        if sum(f) == 0:
+            i = direction(e)
+            e1 = sub(e, i)
+            t = [f"PA{i} * {self.vrr(e1, f, m)}", f"WP{i} * {self.vrr(e1, f, m + 1)}"]
+            fl = 3
+            if e1[i] > 0:
+                e2 = sub(e1, i)
+                t.append(f"R({e1[i]}) * i2p * ({self.vrr(e2, f, m)} - rp * {self.vrr(e2, f, m + 1)})")
+                fl += 4
+        else:
+            i = direction(f)
+            f1 = sub(f, i)
+            t = [f"QC{i} * {self.vrr(e, f1, m)}", f"WQ{i} * {self.vrr(e, f1, m + 1)}"]
+            fl = 3
+            if f1[i] > 0:
+                f2 = sub(f1, i)
+                t.append(f"R({f1[i]}) * i2q * ({self.vrr(e, f2, m)} - rq * {self.vrr(e, f2, m + 1)})")
+                fl += 4
+            if e[i] > 0:
+                t.append(f"R({e[i]}) * i2pq * {self.vrr(sub(e, i), f1, m + 1)}")
+                fl += 2
+        name = f"v{self.nv}"
+        self.nv += 1
+        self.flops += fl
+        self.vrr_code.append(f"const R {name} = {' + '.join(t)};")
+        self.vrr_nodes[key] = name
+        return name
+
+    def targets(self):
+        es = [e for n in range(self.la, self.la + self.lb + 1) for e in cart(n)]
+        fs = [f for n in range(self.lc, self.lc + self.ld + 1) for f in cart(n)]
+        return es, fs
+
+    # ---- horizontal recurrences (after contraction) ----
+    def emit(self, fname):
+        es, fs = self.targets()
+        acc_name = {}
+        for e in es:
+            for f in fs:
+                acc_name[(e, f)] = f"c_{len(acc_name)}"
+                self.vrr(e, f, 0)
+        lines = []
+        L = self.L
+        lines.append(f"template <typename R>\n__device__ __forceinline__ void {fname}(")
+        lines.append("    const PrimPair* __restrict__ bp, int nbp, const PrimPair* __restrict__ kp, int nkp,")
+        lines.append("    const R AB0, const R AB1, const R AB2, const R CD0, const R CD1, const R CD2,")
+        lines.append("    const R* __restrict__ boys_tab, R* __restrict__ out) {")
+        for a in acc_name.values():
+            lines.append(f"  R {a} = R(0);")
+        lines.append("  for (int ib = 0; ib < nbp; ++ib) {")
+        lines.append("    const PrimPair& B = bp[ib];")
+        lines.append("    const R p = R(B.p), i2p = R(B.inv2p), Kb = R(B.K);")
+        lines.append("    const R P0 = R(B.P[0]), P1 = R(B.P[1]), P2 = R(B.P[2]);")
+        lines.append("    const R PA0 = R(B.PA[0]), PA1 = R(B.PA[1]), PA2 = R(B.PA[2]);")
+        lines.append("    for (int ik = 0; ik < nkp; ++ik) {")
+        lines.append("      const PrimPair& Kq = kp[ik];")
+        lines.append("      const R q = R(Kq.p), i2q = R(Kq.inv2p);")
+        lines.append("      const R QC0 = R(Kq.PA[0]), QC1 = R(Kq.PA[1]), QC2 = R(Kq.PA[2]);")
+        lines.append("      const R PQ0 = P0 - R(Kq.P[0]), PQ1 = P1 - R(Kq.P[1]), PQ2 = P2 - R(Kq.P[2]);")
+        lines.append("      const R ipq = R(1) / (p + q);")
+        lines.append("      const R rho = p * q * ipq;")
+        lines.append("      const R T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);")
+        lines.append("      const R pref = Kb * R(Kq.K) * hfx_sqrt(ipq);")
+        lines.append(f"      R F[{L + 1}];")
+        lines.append(f"      boys_eval<R, {L}>(T, F, boys_tab);")
+        body = list(self.vrr_code)
+        base = [f"const R b{m} = pref * F[{m}];" for m in sorted(self.base_used)]
+        if L > 0:
+            lines.append("      const R WP0 = -q * ipq * PQ0, WP1 = -q * ipq * PQ1, WP2 = -q * ipq * PQ2;")
+            lines.append("      const R WQ0 = p * ipq * PQ0, WQ1 = p * ipq * PQ1, WQ2 = p * ipq * PQ2;")
+            lines.append("      const R rp = q * ipq, rq = p * ipq, i2pq = R(0.5) * ipq;")
+            lines.append("      (void)WP0; (void)WP1; (void)WP2; (void)WQ0; (void)WQ1; (void)WQ2;")
+            lines.append("      (void)rp; (void)rq; (void)i2pq; (void)i2p; (void)i2q;")
+            lines.append("      (void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;")
+        else:
+            lines.append("      (void)i2p; (void)i2q; (void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;")
+        for s in base + body:
+            lines.append("      " + s)
+        for (e, f), a in acc_name.items():
+            lines.append(f"      {a} += {self.vrr_nodes[(e, f, 0)]};")
+        lines.append("    }")
+        lines.append("  }")
+        # bra HRR on the contracted [e0|f0]
+        hnodes = {}
+        hcode = []
+        nh = [0]
+        hfl = [0]
+
+        def hb(a, b, f):
+            key = (a, b, f)
+            if key in hnodes:
+                return hnodes[key]
+            if sum(b) == 0:
+                hnodes[key] = acc_name[(a, f)]
+                return hnodes[key]
+            i = direction(b)
+            b1 = sub(b, i)
+            x1 = hb(add(a, i), b1, f)
+            x2 = hb(a, b1, f)
+            name = f"h{nh[0]}"
+            nh[0] += 1
+            hfl[0] += 2
+            hcode.append(f"  const R {name} = {x1} + AB{i} * {x2};")
+            hnodes[key] = name
+            return name
+
+        knodes = {}
+
+        def hk(a, b, c, d):
+            key = (a, b, c, d)
+            if key in knodes:
+                return knodes[key]
+            if sum(d) == 0:
+                knodes[key] = hb(a, b, c)
+                return knodes[key]
+            i = direction(d)
+            d1 = sub(d, i)
+            x1 = hk(a, b, add(c, i), d1)
+            x2 = hk(a, b, c, d1)
+            name = f"h{nh[0]}"
+            nh[0] += 1
+            hfl[0] += 2
+            hcode.append(f"  const R {name} = {x1} + CD{i} * {x2};")
+            knodes[key] = name
+            return name
+
+        outs = []
+        idx = 0
+        for a in cart(self.la):
+            for b in cart(self.lb):
+                for c in cart(self.lc):
+                    for d in cart(self.ld):
+                        outs.append(f"  out[{idx}] = {hk(a, b, c, d)};")
+                        idx += 1
+        lines.append("  (void)AB0; (void)AB1; (void)AB2; (void)CD0; (void)CD1; (void)CD2;")
+        lines.extend(hcode)
+        lines.extend(outs)
+        lines.append("}")
+        self.hrr_flops = hfl[0]
+        return "\n".join(lines)
+
+
+def main(out_dir):
+    import os
+    os.makedirs(out_dir, exist_ok=True)
+    table = []
+    for cid, (B, K) in enumerate(CLASSES):
+        la, lb = PAIR_CLASSES[B]
+        lc, ld = PAIR_CLASSES[K]
+        g = ClassGen(la, lb, lc, ld)
+        fname = f"eri_{PAIR_NAMES[B]}_{PAIR_NAMES[K]}"
+        body = g.emit(fname)
+        hdr = ["// Generated by gen_eri.py: Obara-Saika / Head-Gordon-Pople evaluator.",
+               f"// class {cid}: ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}), L = {g.L}", "#pragma once",
+               '#include "../hfx_internal.h"', "", body, ""]
+        with open(os.path.join(out_dir, f"eri_class_{cid:02d}.h"), "w") as fh:
+            fh.write("\n".join(hdr))
+        tu = [f"// Generated by gen_eri.py: kernels of class {cid} ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}).",
+              f'#include "eri_class_{cid:02d}.h"', '#include "../eri_impl.h"', "",
+              f"HFX_CLASS_TU({cid}, {fname}, {la}, {lb}, {lc}, {ld})", ""]
+        with open(os.path.join(out_dir, f"eri_class_{cid:02d}.hip"), "w") as fh:
+            fh.write("\n".join(tu))
+        table.append((cid, B, K, la, lb, lc, ld, g.flops, g.hrr_flops, fname))
+    parts = ["// Generated by gen_eri.py: class table.", "#pragma once", "",
+             "struct EriClassInfo { int B, K, la, lb, lc, ld, vrr_flops_per_prim, hrr_flops; };",
+             "static const EriClassInfo kEriClassInfo[21] = {"]
+    for (cid, B, K, la, lb, lc, ld, fl, hfl, fname) in table:
+        parts.append(f"  {{{B}, {K}, {la}, {lb}, {lc}, {ld}, {fl}, {hfl}}},  // {fname}")
+    parts.append("};")
+    parts.append("")
+    parts.append("#define HFX_FOR_EACH_CID(X) " + " ".join(f"X({cid})" for cid in range(21)))
+    parts.append("")
+    with open(os.path.join(out_dir, "eri_classes.h"), "w") as fh:
+        fh.write("\n".join(parts))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

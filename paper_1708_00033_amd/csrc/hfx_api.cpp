@@ -1,0 +1,675 @@
+// C ABI of the library: context, system loading (normalisation, shell pairs,
+// Schwarz bounds, screened quartet plan, one-electron integrals) and the
+// direct Fock build.  The SCF driver lives in scf.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hfx_ctx.h"
+
+// ---- errors ---------------------------------------------------------------------
+
+hfx_status hfx_fail(hfx_ctx* c, hfx_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+hfx_status hfx_hip_check(hfx_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return HFX_OK;
+    return hfx_fail(c, e == hipErrorOutOfMemory ? HFX_ERR_OOM : HFX_ERR_DEVICE,
+                    std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCK(call)                                                      \
+    do {                                                                 \
+        hfx_status _s = hfx_hip_check(c, (call), #call);                 \
+        if (_s != HFX_OK) return _s;                                     \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <typename T>
+static void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+static int pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }   // la >= lb
+static int class_id(int B, int K) { return B * (B + 1) / 2 + K; }           // B >= K
+
+static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+
+// ---- options -----------------------------------------------------------------------
+
+extern "C" hfx_status hfx_default_options(hfx_options* o) {
+    if (!o) return HFX_ERR_INVALID_ARG;
+    o->device = 0;
+    o->schwarz_tau = 1e-10;
+    o->precision = HFX_PREC_FP64;
+    o->fp32_tau = 1e-7;
+    o->digest = HFX_DIGEST_LDS;
+    o->task_quartets = 2048;
+    o->log_level = 0;
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_default_scf_options(hfx_scf_options* o) {
+    if (!o) return HFX_ERR_INVALID_ARG;
+    o->max_iter = 100;
+    o->e_tol = 1e-8;
+    o->d_rms_tol = 1e-7;
+    o->diis_max = 8;
+    o->guess = HFX_GUESS_SAD;
+    o->D0 = nullptr;
+    o->lindep = 1e-7;
+    return HFX_OK;
+}
+
+static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
+    if (!(o->schwarz_tau >= 0.0) || !std::isfinite(o->schwarz_tau))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "schwarz_tau must be finite and >= 0");
+    if (o->precision != HFX_PREC_FP64 && o->precision != HFX_PREC_MIXED)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "precision must be HFX_PREC_FP64 or HFX_PREC_MIXED");
+    if (!(o->fp32_tau >= 0.0) || !std::isfinite(o->fp32_tau))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "fp32_tau must be finite and >= 0");
+    if (o->digest != HFX_DIGEST_LDS && o->digest != HFX_DIGEST_GLOBAL)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL");
+    if (o->task_quartets < 256 || o->task_quartets % 256 != 0 || o->task_quartets > (1 << 24))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be a multiple of 256 in [256, 2^24]");
+    return HFX_OK;
+}
+
+// ---- lifetime ------------------------------------------------------------------------
+
+static void release_system(hfx_ctx* c) {
+    dfree(c->d_prim);
+    for (int k = 0; k < 6; ++k) {
+        dfree(c->d_pairs[k]);
+        dfree(c->d_pairq[k]);
+        c->npair[k] = 0;
+    }
+    for (auto& p : c->plan) {
+        dfree(p.d_nket);
+        dfree(p.d_split);
+        dfree(p.d_tasks);
+        p = ClassPlan();
+    }
+    dfree(c->d_cscale);
+    dfree(c->d_S);
+    dfree(c->d_H);
+    dfree(c->d_W);
+    dfree(c->d_Dp);
+    dfree(c->d_tmpD);
+    dfree(c->d_tmpF);
+    c->loaded = false;
+}
+
+extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
+    if (!out) return HFX_ERR_INVALID_ARG;
+    hfx_ctx* c = new (std::nothrow) hfx_ctx();
+    if (!c) return HFX_ERR_OOM;
+    if (opt) c->opt = *opt; else hfx_default_options(&c->opt);
+    hfx_status s = check_options(c, &c->opt);
+    if (s != HFX_OK) { delete c; return s; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0 || c->opt.device < 0 || c->opt.device >= ndev) {
+        delete c;
+        return HFX_ERR_DEVICE;
+    }
+    if (hipSetDevice(c->opt.device) != hipSuccess) { delete c; return HFX_ERR_DEVICE; }
+    std::vector<double> tab((size_t)BOYS_NT * BOYS_NM);
+    hfx_boys_table(tab.data());
+    std::vector<float> tab32(tab.begin(), tab.end());
+    if (dalloc(&c->d_boys64, tab.size()) != hipSuccess || dalloc(&c->d_boys32, tab.size()) != hipSuccess ||
+        dalloc(&c->d_dmax, 1) != hipSuccess || dalloc(&c->d_counters, 43) != hipSuccess) {
+        hfx_destroy(c);
+        return HFX_ERR_OOM;
+    }
+    if (hipMemcpy(c->d_boys64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_boys32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hfx_destroy(c);
+        return HFX_ERR_DEVICE;
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        hfx_destroy(c);
+        return HFX_ERR_DEVICE;
+    }
+    c->d_bad = (int*)(c->d_counters + 42);
+    *out = c;
+    return HFX_OK;
+}
+
+extern "C" void hfx_destroy(hfx_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->opt.device);
+    release_system(c);
+    dfree(c->d_boys64);
+    dfree(c->d_boys32);
+    dfree(c->d_dmax);
+    dfree(c->d_counters);
+    c->d_bad = nullptr;
+    for (int k = 0; k < 21; ++k) {
+        if (c->ev_start[k]) (void)hipEventDestroy(c->ev_start[k]);
+        if (c->ev_stop[k]) (void)hipEventDestroy(c->ev_stop[k]);
+    }
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    delete c;
+}
+
+extern "C" const char* hfx_last_error(const hfx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" hfx_status hfx_configure(hfx_ctx* c, const hfx_options* o) {
+    if (!c || !o) return HFX_ERR_INVALID_ARG;
+    hfx_status s = check_options(c, o);
+    if (s != HFX_OK) return s;
+    if (o->device != c->opt.device || o->schwarz_tau != c->opt.schwarz_tau)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "device and schwarz_tau cannot change after hfx_create");
+    const bool replan = o->task_quartets != c->opt.task_quartets;
+    c->opt = *o;
+    if (!replan || !c->loaded) {
+        // digestion mode may change without a new plan
+        for (auto& p : c->plan)
+            p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024 && !p.fp64_global_only) ? 0 : 1;
+        return HFX_OK;
+    }
+    return hfx_fail(c, HFX_ERR_STATE, "task_quartets changed: call hfx_load again");
+}
+
+// ---- loading ----------------------------------------------------------------------------
+
+static double dfact_odd(int n) {   // (2n-1)!!
+    double r = 1.0;
+    for (int k = 2 * n - 1; k > 1; k -= 2) r *= k;
+    return r;
+}
+
+// Plan one class: per-bra screened ket counts, workgroup tasks, counts.
+static hfx_status plan_class(hfx_ctx* c, int B, int K, const std::vector<std::vector<PairInfo>>& lists) {
+    ClassPlan& P = c->plan[class_id(B, K)];
+    P = ClassPlan();
+    P.B = B;
+    P.K = K;
+    const auto& bras = lists[B];
+    const auto& kets = lists[K];
+    const double tau = c->opt.schwarz_tau;
+    const int TQ = c->opt.task_quartets;
+    std::vector<int> nket(bras.size(), 0);
+    std::vector<long long> kprim_prefix(kets.size() + 1, 0);
+    for (size_t s = 0; s < kets.size(); ++s) kprim_prefix[s + 1] = kprim_prefix[s] + kets[s].nprim;
+    int nbra = 0;
+    for (size_t r = 0; r < bras.size(); ++r) {
+        const double qr = bras[r].Q;
+        // kets with Q_s * Q_r >= tau form a prefix of the Q-descending list
+        size_t lo = 0, hi = kets.size();
+        while (lo < hi) {
+            size_t mid = (lo + hi) / 2;
+            if (kets[mid].Q * qr >= tau) lo = mid + 1; else hi = mid;
+        }
+        size_t n = lo;
+        if (B == K) n = std::min(n, r + 1);
+        nket[r] = (int)n;
+        if (n > 0) nbra = (int)r + 1;
+        P.quartets += (long long)n;
+        P.prim += (long long)bras[r].nprim * kprim_prefix[n];
+    }
+    const int nint = ncart(kPairL[B][0]) * ncart(kPairL[B][1]) * ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
+    P.integrals = P.quartets * nint;
+    std::vector<int2> tasks;
+    for (int r = 0; r < nbra; ++r)
+        for (int s0 = 0; s0 < nket[r]; s0 += TQ) tasks.push_back(make_int2(r, s0));
+    if (tasks.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many tasks for one launch");
+    P.nbra = nbra;
+    P.nket_list = (int)kets.size();
+    P.ntask = (int)tasks.size();
+    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->nbf * sizeof(double);
+    P.fp64_global_only = nint >= 600;   // see ClassKernels in eri_impl.h
+    P.mode = (c->opt.digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024 && !P.fp64_global_only) ? 0 : 1;
+    HIPCK(dalloc(&P.d_nket, nbra));
+    HIPCK(dalloc(&P.d_split, nbra));
+    HIPCK(dalloc(&P.d_tasks, tasks.size()));
+    if (nbra) HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
+    if (!tasks.empty()) HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double* xyz, int nshell,
+                               const hfx_shell* sh, int charge) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (natom <= 0 || !Z || !xyz || nshell <= 0 || !sh)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: empty system or null pointer");
+    for (int a = 0; a < natom; ++a) {
+        if (Z[a] < 0 || Z[a] > 118) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nuclear charge out of range");
+        for (int x = 0; x < 3; ++x)
+            if (!std::isfinite(xyz[3 * a + x])) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: non-finite coordinate");
+    }
+    for (int s = 0; s < nshell; ++s) {
+        if (sh[s].atom < 0 || sh[s].atom >= natom) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: shell atom index");
+        if (sh[s].l < 0 || sh[s].l > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: only s, p, d shells (l <= 2)");
+        if (sh[s].nprim < 1 || sh[s].nprim > 16 || !sh[s].exps || !sh[s].coefs)
+            return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nprim must be in [1, 16]");
+        for (int k = 0; k < sh[s].nprim; ++k)
+            if (!(sh[s].exps[k] > 0.0) || !std::isfinite(sh[s].exps[k]) || !std::isfinite(sh[s].coefs[k]))
+                return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: exponents must be finite and > 0");
+    }
+    long long nelec = -charge;
+    for (int a = 0; a < natom; ++a) nelec += Z[a];
+    if (nelec < 0 || nelec % 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: closed shell needs an even electron count");
+    HIPCK(hipSetDevice(c->opt.device));
+    release_system(c);
+
+    c->natom = natom;
+    c->nshell = nshell;
+    c->nelec = (int)nelec;
+    c->nocc = (int)(nelec / 2);
+    c->Z.assign(Z, Z + natom);
+    c->axyz.assign(xyz, xyz + 3 * natom);
+    c->shells.clear();
+    c->exps.clear();
+    c->coefs.clear();
+    c->cscale.clear();
+    c->raw_exps.clear();
+    c->raw_coefs.clear();
+    c->shell_atom.clear();
+    c->shell_exps_l.clear();
+    int nbf = 0;
+    for (int s = 0; s < nshell; ++s) {
+        const int l = sh[s].l, np = sh[s].nprim;
+        ShellHost h;
+        h.x = xyz[3 * sh[s].atom];
+        h.y = xyz[3 * sh[s].atom + 1];
+        h.z = xyz[3 * sh[s].atom + 2];
+        h.l = l;
+        h.nprim = np;
+        h.prim_off = (int)c->exps.size();
+        h.bf = nbf;
+        // unit-normalised primitives: (2a/pi)^{3/4} (4a)^{l/2} for the x^l
+        // component; contraction renormalised to unit self-overlap.
+        std::vector<double> nc(np);
+        for (int k = 0; k < np; ++k)
+            nc[k] = sh[s].coefs[k] * std::pow(2.0 * sh[s].exps[k] / M_PI, 0.75) * std::pow(4.0 * sh[s].exps[k], 0.5 * l);
+        double self = 0.0;
+        for (int i = 0; i < np; ++i)
+            for (int j = 0; j < np; ++j) {
+                const double p = sh[s].exps[i] + sh[s].exps[j];
+                self += nc[i] * nc[j] * std::pow(M_PI / p, 1.5) / std::pow(2.0 * p, l);
+            }
+        const double rn = 1.0 / std::sqrt(self);
+        for (int k = 0; k < np; ++k) {
+            c->exps.push_back(sh[s].exps[k]);
+            c->coefs.push_back(nc[k] * rn);
+        }
+        for (int x = l; x >= 0; --x)
+            for (int y = l - x; y >= 0; --y) {
+                const int z = l - x - y;
+                c->cscale.push_back(1.0 / std::sqrt(dfact_odd(x) * dfact_odd(y) * dfact_odd(z)));
+            }
+        nbf += ncart(l);
+        c->shells.push_back(h);
+        c->raw_exps.emplace_back(sh[s].exps, sh[s].exps + np);
+        c->raw_coefs.emplace_back(sh[s].coefs, sh[s].coefs + np);
+        c->shell_atom.push_back(sh[s].atom);
+        c->shell_exps_l.push_back(l);
+    }
+    c->nbf = nbf;
+    double e = 0.0;
+    for (int a = 0; a < natom; ++a)
+        for (int b = 0; b < a; ++b) {
+            const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
+                         dz = xyz[3 * a + 2] - xyz[3 * b + 2];
+            const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+            if (r == 0.0 && Z[a] * Z[b] != 0) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: coincident nuclei");
+            if (r > 0.0) e += (double)Z[a] * Z[b] / r;
+        }
+    c->enuc = e;
+    const size_t nn = (size_t)nbf * nbf;
+    HIPCK(dalloc(&c->d_cscale, nbf));
+    HIPCK(hipMemcpy(c->d_cscale, c->cscale.data(), nbf * sizeof(double), hipMemcpyHostToDevice));
+
+    // ---- all shell pairs in canonical orientation, primitive-pair data ----
+    std::vector<PrimPair> prim;
+    std::vector<std::vector<PairInfo>> all(6);
+    for (int a = 0; a < nshell; ++a)
+        for (int b = 0; b <= a; ++b) {
+            int A = a, Bs = b;
+            if (c->shells[b].l > c->shells[a].l) std::swap(A, Bs);
+            const ShellHost& SA = c->shells[A];
+            const ShellHost& SB = c->shells[Bs];
+            PairInfo pi;
+            pi.a = A;
+            pi.b = Bs;
+            pi.bfa = SA.bf;
+            pi.bfb = SB.bf;
+            pi.AB[0] = SA.x - SB.x;
+            pi.AB[1] = SA.y - SB.y;
+            pi.AB[2] = SA.z - SB.z;
+            pi.Q = 0.0;
+            pi.pad = 0.0;
+            const double ab2 = pi.AB[0] * pi.AB[0] + pi.AB[1] * pi.AB[1] + pi.AB[2] * pi.AB[2];
+            pi.prim_off = (int)prim.size();
+            int np = 0;
+            double kmax = 0.0;
+            for (int i = 0; i < SA.nprim; ++i)
+                for (int j = 0; j < SB.nprim; ++j) {
+                    const double al = c->exps[SA.prim_off + i], be = c->exps[SB.prim_off + j];
+                    const double p = al + be, mu = al * be / p;
+                    PrimPair pp;
+                    pp.p = p;
+                    pp.inv2p = 0.5 / p;
+                    pp.P[0] = (al * SA.x + be * SB.x) / p;
+                    pp.P[1] = (al * SA.y + be * SB.y) / p;
+                    pp.P[2] = (al * SA.z + be * SB.z) / p;
+                    pp.PA[0] = pp.P[0] - SA.x;
+                    pp.PA[1] = pp.P[1] - SA.y;
+                    pp.PA[2] = pp.P[2] - SA.z;
+                    const double ek = std::exp(-mu * ab2);
+                    // sqrt(2 pi^{5/2}) = sqrt(2) pi^{5/4}
+                    pp.K = c->coefs[SA.prim_off + i] * c->coefs[SB.prim_off + j] * ek * 1.4142135623730951 *
+                           std::pow(M_PI, 1.25) / p;
+                    pp.pad = 0.0;
+                    kmax = std::max(kmax, ek);
+                    prim.push_back(pp);
+                    ++np;
+                }
+            pi.nprim = np;
+            if (kmax < 1e-40) {   // Gaussian overlap exp(-mu R^2) < 1e-40 for every primitive pair
+                prim.resize(pi.prim_off);
+                continue;
+            }
+            all[pair_class(SA.l, SB.l)].push_back(pi);
+        }
+    if (prim.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many primitive pairs");
+    HIPCK(dalloc(&c->d_prim, prim.size()));
+    HIPCK(hipMemcpy(c->d_prim, prim.data(), prim.size() * sizeof(PrimPair), hipMemcpyHostToDevice));
+
+    // ---- Schwarz bounds on the GPU (FP64 class kernels on (ab|ab)) ----
+    c->Qshell.assign((size_t)nshell * nshell, 0.0);
+    double qmax = 0.0;
+    for (int B = 0; B < 6; ++B) {
+        auto& L = all[B];
+        if (L.empty()) continue;
+        PairInfo* dp = nullptr;
+        double* dq = nullptr;
+        HIPCK(dalloc(&dp, L.size()));
+        HIPCK(dalloc(&dq, L.size()));
+        HIPCK(hipMemcpy(dp, L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
+        HIPCK(hfx_launch_schwarz(class_id(B, B), dp, (int)L.size(), c->d_prim, c->d_boys64, c->d_cscale, dq, 0));
+        std::vector<double> q(L.size());
+        HIPCK(hipMemcpy(q.data(), dq, q.size() * sizeof(double), hipMemcpyDeviceToHost));
+        dfree(dp);
+        dfree(dq);
+        for (size_t i = 0; i < L.size(); ++i) {
+            if (!std::isfinite(q[i])) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite Schwarz bound");
+            L[i].Q = q[i];
+            qmax = std::max(qmax, q[i]);
+            c->Qshell[(size_t)L[i].a * nshell + L[i].b] = q[i];
+            c->Qshell[(size_t)L[i].b * nshell + L[i].a] = q[i];
+        }
+    }
+    // ---- significant pairs, sorted by Q descending ----
+    const double tau = c->opt.schwarz_tau;
+    for (int B = 0; B < 6; ++B) {
+        auto& L = all[B];
+        std::vector<PairInfo> keep;
+        keep.reserve(L.size());
+        for (auto& p : L)
+            if (p.Q * qmax >= tau) keep.push_back(p);
+        std::stable_sort(keep.begin(), keep.end(), [](const PairInfo& x, const PairInfo& y) { return x.Q > y.Q; });
+        L.swap(keep);
+        c->npair[B] = (int)L.size();
+        std::vector<double> q(L.size());
+        for (size_t i = 0; i < L.size(); ++i) q[i] = L[i].Q;
+        HIPCK(dalloc(&c->d_pairs[B], L.size()));
+        HIPCK(dalloc(&c->d_pairq[B], L.size()));
+        if (!L.empty()) {
+            HIPCK(hipMemcpy(c->d_pairs[B], L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(c->d_pairq[B], q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+    }
+    for (int B = 0; B < 6; ++B)
+        for (int K = 0; K <= B; ++K) {
+            hfx_status s = plan_class(c, B, K, all);
+            if (s != HFX_OK) return s;
+        }
+
+    // ---- one-electron integrals ----
+    std::vector<double> atoms(4 * (size_t)natom);
+    for (int a = 0; a < natom; ++a) {
+        atoms[4 * a] = xyz[3 * a];
+        atoms[4 * a + 1] = xyz[3 * a + 1];
+        atoms[4 * a + 2] = xyz[3 * a + 2];
+        atoms[4 * a + 3] = Z[a];
+    }
+    ShellHost* dsh = nullptr;
+    double *dexp = nullptr, *dcoef = nullptr, *datoms = nullptr, *dT = nullptr, *dV = nullptr;
+    HIPCK(dalloc(&dsh, nshell));
+    HIPCK(dalloc(&dexp, c->exps.size()));
+    HIPCK(dalloc(&dcoef, c->coefs.size()));
+    HIPCK(dalloc(&datoms, atoms.size()));
+    HIPCK(dalloc(&c->d_S, nn));
+    HIPCK(dalloc(&dT, nn));
+    HIPCK(dalloc(&dV, nn));
+    HIPCK(hipMemcpy(dsh, c->shells.data(), nshell * sizeof(ShellHost), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(dexp, c->exps.data(), c->exps.size() * 8, hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(dcoef, c->coefs.data(), c->coefs.size() * 8, hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(datoms, atoms.data(), atoms.size() * 8, hipMemcpyHostToDevice));
+    HIPCK(hfx_one_electron(dsh, nshell, dexp, dcoef, datoms, natom, c->d_cscale, c->d_boys64, nbf, c->d_S, dT, dV, 0));
+    // H = T + V (reuse the assemble-free path: simple host-free add via fill + axpy with rocBLAS)
+    HIPCK(dalloc(&c->d_H, nn));
+    HIPCK(hipMemcpy(c->d_H, dT, nn * 8, hipMemcpyDeviceToDevice));
+    {
+        const double one = 1.0;
+        rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host);
+        rocblas_set_stream(c->blas, 0);
+        if (rocblas_daxpy(c->blas, (rocblas_int)nn, &one, dV, 1, c->d_H, 1) != rocblas_status_success)
+            return hfx_fail(c, HFX_ERR_DEVICE, "rocblas_daxpy failed");
+    }
+    HIPCK(hipDeviceSynchronize());
+    dfree(dsh);
+    dfree(dexp);
+    dfree(dcoef);
+    dfree(datoms);
+    dfree(dT);
+    dfree(dV);
+    HIPCK(dalloc(&c->d_W, nn));
+    HIPCK(dalloc(&c->d_Dp, nn));
+    c->loaded = true;
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_dims(const hfx_ctx* c, int* nbf, int* nocc, int* nshell) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return HFX_ERR_STATE;
+    if (nbf) *nbf = c->nbf;
+    if (nocc) *nocc = c->nocc;
+    if (nshell) *nshell = c->nshell;
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_core(hfx_ctx* c, double* S, double* H, double* enuc) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_core: nothing loaded");
+    HIPCK(hipSetDevice(c->opt.device));
+    const size_t nn = (size_t)c->nbf * c->nbf;
+    if (S) HIPCK(hipMemcpy(S, c->d_S, nn * 8, hipMemcpyDeviceToHost));
+    if (H) HIPCK(hipMemcpy(H, c->d_H, nn * 8, hipMemcpyDeviceToHost));
+    if (enuc) *enuc = c->enuc;
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_schwarz(hfx_ctx* c, double* Q) {
+    if (!c || !Q) return HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_schwarz: nothing loaded");
+    std::memcpy(Q, c->Qshell.data(), c->Qshell.size() * sizeof(double));
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_class_counts(const hfx_ctx* c, long long* counts) {
+    if (!c || !counts) return HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return HFX_ERR_STATE;
+    for (int k = 0; k < 21; ++k) {
+        counts[4 * k] = c->plan[k].quartets;
+        counts[4 * k + 1] = c->plan[k].integrals;
+        counts[4 * k + 2] = c->plan[k].prim;
+        counts[4 * k + 3] = c->plan[k].ntask;
+    }
+    return HFX_OK;
+}
+
+// ---- kernel timing ---------------------------------------------------------------------
+
+static void collect_timing(hfx_ctx* c) {
+    for (int k = 0; k < 21; ++k)
+        if (c->ev_pending[k]) {
+            (void)hipEventSynchronize(c->ev_stop[k]);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]) == hipSuccess) {
+                c->class_ms[k] += ms;
+                c->class_launches[k] += 1;
+            }
+            c->ev_pending[k] = false;
+        }
+}
+
+extern "C" hfx_status hfx_kernel_timing(hfx_ctx* c, int enable) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    collect_timing(c);
+    c->timing = enable != 0;
+    for (int k = 0; k < 21; ++k) {
+        c->class_ms[k] = 0.0;
+        c->class_launches[k] = 0;
+        if (c->timing && !c->ev_start[k]) {
+            HIPCK(hipEventCreate(&c->ev_start[k]));
+            HIPCK(hipEventCreate(&c->ev_stop[k]));
+        }
+    }
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_kernel_times(hfx_ctx* c, double* ms, long long* launches) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    collect_timing(c);
+    for (int k = 0; k < 21; ++k) {
+        if (ms) ms[k] = c->class_ms[k];
+        if (launches) launches[k] = c->class_launches[k];
+    }
+    return HFX_OK;
+}
+
+// ---- the Fock build -------------------------------------------------------------------
+
+hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
+                              hipStream_t st, hfx_fock_stats* stats) {
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "build: nothing loaded");
+    const int n = c->nbf;
+    const size_t nn = (size_t)n * n;
+    const bool mixed = c->opt.precision == HFX_PREC_MIXED;
+    auto t0 = std::chrono::steady_clock::now();
+    if (c->timing) collect_timing(c);
+    HIPCK(hfx_fill_u64(c->d_dmax, 1, st));
+    HIPCK(hfx_fill_u64(c->d_counters, 43, st));   // 42 quartet counters + the non-finite flag
+    HIPCK(hfx_prepare_density(dD, c->d_cscale, n, c->d_Dp, c->d_dmax, st));
+    HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
+    // largest classes first
+    static const int order[21] = {0, 1, 2, 6, 7, 3, 8, 9, 4, 10, 11, 13, 12, 5, 15, 16, 14, 18, 17, 19, 20};
+    for (int oi = 0; oi < 21; ++oi) {
+        const int cid = order[oi];
+        ClassPlan& P = c->plan[cid];
+        if (P.ntask == 0) continue;
+        if (mixed && !P.fp64_global_only)
+            HIPCK(hfx_split(c->d_pairs[P.B], c->d_pairq[P.K], P.nket_list, P.d_nket, P.nbra, c->opt.fp32_tau,
+                            c->d_dmax, P.d_split, st));
+        ClassArgs a;
+        a.bra = c->d_pairs[P.B];
+        a.ket = c->d_pairs[P.K];
+        a.prim = c->d_prim;
+        a.nket = P.d_nket;
+        a.split = P.d_split;
+        a.tasks = P.d_tasks;
+        a.boys64 = c->d_boys64;
+        a.boys32 = c->d_boys32;
+        a.D = c->d_Dp;
+        a.W = c->d_W;
+        a.counters = c->d_counters + 2 * cid;
+        a.nbf = n;
+        a.same_class = P.B == P.K;
+        a.task_quartets = c->opt.task_quartets;
+        a.cj = cj;
+        a.ck = ck;
+        if (c->timing) HIPCK(hipEventRecord(c->ev_start[cid], st));
+        HIPCK(hfx_launch_class(cid, P.mode, (mixed && !P.fp64_global_only) ? 1 : 0, P.ntask,
+                               P.mode == 0 ? P.lds_bytes : 0, st, &a));
+        if (c->timing) {
+            HIPCK(hipEventRecord(c->ev_stop[cid], st));
+            c->ev_pending[cid] = true;
+        }
+    }
+    HIPCK(hfx_assemble(dH, c->d_W, c->d_cscale, n, dOut, c->d_bad, st));
+    c->last_stream = st;
+    if (stats) {
+        HIPCK(hipStreamSynchronize(st));
+        unsigned long long cnt[42];
+        int bad = 0;
+        HIPCK(hipMemcpy(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost));
+        stats->quartets_fp64 = stats->quartets_fp32 = stats->integrals = stats->prim_quartets = 0;
+        for (int k = 0; k < 21; ++k) {
+            stats->quartets_fp64 += (long long)cnt[2 * k];
+            stats->quartets_fp32 += (long long)cnt[2 * k + 1];
+            stats->integrals += c->plan[k].integrals;
+            stats->prim_quartets += c->plan[k].prim;
+        }
+        stats->t_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (bad) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite value in the Fock matrix");
+    }
+    return HFX_OK;
+}
+
+static bool finite_host(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+extern "C" hfx_status hfx_build_fock_dev(hfx_ctx* c, const double* dD, double* dF, void* stream,
+                                         hfx_fock_stats* stats) {
+    if (!c || !dD || !dF) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    HIPCK(hipSetDevice(c->opt.device));
+    return hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, (hipStream_t)stream, stats);
+}
+
+extern "C" hfx_status hfx_build_2e_dev(hfx_ctx* c, const double* dD, double cj, double ck, double* dG, void* stream,
+                                       hfx_fock_stats* stats) {
+    if (!c || !dD || !dG) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    if (!std::isfinite(cj) || !std::isfinite(ck)) return hfx_fail(c, HFX_ERR_INVALID_ARG, "non-finite cj/ck");
+    HIPCK(hipSetDevice(c->opt.device));
+    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, stats);
+}
+
+extern "C" hfx_status hfx_build_fock(hfx_ctx* c, const double* D, double* F, hfx_fock_stats* stats) {
+    if (!c || !D || !F) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_build_fock: nothing loaded");
+    const size_t nn = (size_t)c->nbf * c->nbf;
+    if (!finite_host(D, nn)) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite density");
+    HIPCK(hipSetDevice(c->opt.device));
+    if (!c->d_tmpD) HIPCK(dalloc(&c->d_tmpD, nn));
+    if (!c->d_tmpF) HIPCK(dalloc(&c->d_tmpF, nn));
+    HIPCK(hipMemcpy(c->d_tmpD, D, nn * 8, hipMemcpyHostToDevice));
+    hfx_fock_stats local;
+    hfx_status s = hfx_build_internal(c, c->d_tmpD, 2.0, 1.0, c->d_H, c->d_tmpF, 0, stats ? stats : &local);
+    if (s != HFX_OK) return s;
+    HIPCK(hipMemcpy(F, c->d_tmpF, nn * 8, hipMemcpyDeviceToHost));
+    return HFX_OK;
+}

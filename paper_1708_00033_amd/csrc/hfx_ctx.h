@@ -1,0 +1,107 @@
+// Host-side context of the library (shared by the API and SCF sources).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <string>
+#include <vector>
+
+#include "hfx.h"
+#include "hfx_internal.h"
+
+struct ShellHost {
+    double x, y, z;
+    int l, nprim, prim_off, bf;
+};
+
+struct ClassPlan {
+    int B = 0, K = 0;
+    int nbra = 0;             // bras with at least one ket
+    int nket_list = 0;        // size of the ket list (pairs of class K)
+    int ntask = 0;
+    int* d_nket = nullptr;
+    int* d_split = nullptr;
+    int2* d_tasks = nullptr;
+    long long quartets = 0, integrals = 0, prim = 0;
+    size_t lds_bytes = 0;
+    int mode = 0;             // digestion actually used (LDS may fall back to global)
+    bool fp64_global_only = false;   // class built only as the FP64 global-atomic kernel
+};
+
+struct hfx_ctx {
+    hfx_options opt{};
+    std::string err;
+    bool loaded = false;
+    // system
+    int natom = 0, nshell = 0, nbf = 0, nelec = 0, nocc = 0;
+    double enuc = 0.0;
+    std::vector<int> Z;
+    std::vector<double> axyz;
+    std::vector<ShellHost> shells;
+    std::vector<double> exps, coefs;   // normalised coefficients
+    std::vector<double> cscale;        // per basis function component factor
+    std::vector<int> shell_exps_l;     // shell angular momenta (input order)
+    std::vector<std::vector<double>> raw_exps, raw_coefs;  // input copies (for SAD)
+    std::vector<int> shell_atom;
+    // device data
+    PrimPair* d_prim = nullptr;
+    PairInfo* d_pairs[6] = {nullptr};   // significant pairs per pair class, Q descending
+    double* d_pairq[6] = {nullptr};
+    int npair[6] = {0};
+    std::vector<double> Qshell;         // nshell x nshell Schwarz bounds (host)
+    ClassPlan plan[21];
+    double* d_boys64 = nullptr;
+    float* d_boys32 = nullptr;
+    double* d_cscale = nullptr;
+    double* d_S = nullptr;
+    double* d_H = nullptr;
+    double* d_W = nullptr;
+    double* d_Dp = nullptr;
+    double* d_tmpD = nullptr;   // host-variant staging
+    double* d_tmpF = nullptr;
+    unsigned long long* d_dmax = nullptr;
+    unsigned long long* d_counters = nullptr;  // 2 per class
+    int* d_bad = nullptr;
+    rocblas_handle blas = nullptr;
+    // timing
+    bool timing = false;
+    hipEvent_t ev_start[21] = {nullptr}, ev_stop[21] = {nullptr};
+    bool ev_pending[21] = {false};
+    double class_ms[21] = {0};
+    long long class_launches[21] = {0};
+    hipStream_t last_stream = nullptr;
+};
+
+// implemented in hfx_api.cpp
+hfx_status hfx_fail(hfx_ctx* c, hfx_status s, const std::string& msg);
+hfx_status hfx_hip_check(hfx_ctx* c, hipError_t e, const char* what);
+hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
+                              hipStream_t st, hfx_fock_stats* stats);
+
+// implemented in misc_kernels.hip
+extern "C" {
+hipError_t hfx_prepare_density(const double* D, const double* cs, int n, double* Dp, unsigned long long* dmax_bits,
+                               hipStream_t st);
+hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
+hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
+hipError_t hfx_split(const PairInfo* bra, const double* ketq, int nket_total, const int* nket, int nbra,
+                     double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st);
+hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int n, double* F, int* bad,
+                        hipStream_t st);
+hipError_t hfx_one_electron(const void* sh, int nshell, const double* exps, const double* coefs, const double* atoms,
+                            int natom, const double* cs, const double* boys, int n, double* S, double* T, double* V,
+                            hipStream_t st);
+hipError_t hfx_antisym(const double* A, int n, double* out, hipStream_t st);
+int hfx_dot_partial(const double* a, const double* b, size_t n, int mode, double* out, hipStream_t st);
+int hfx_energy_partial(const double* D, const double* H, const double* F, size_t n, double* out, hipStream_t st);
+hipError_t hfx_lincomb(const double* const* M, const double* c, int m, size_t n, double* out, hipStream_t st);
+hipError_t hfx_scale_cols(const double* U, const double* w, const int* keep, int n, int nk, double* out,
+                          hipStream_t st);
+hipError_t hfx_weight_cols(const double* C, const double* occ, int n, int nk, double* out, hipStream_t st);
+// eri_dispatch.hip
+hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_bytes, hipStream_t stream,
+                            const ClassArgs* args);
+hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
+                              const double* cscale, double* Q, hipStream_t stream);
+}

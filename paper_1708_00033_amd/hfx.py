@@ -1,0 +1,250 @@
+"""ctypes binding of the HIP library ``libhfx.so`` (see include/hfx.h).
+
+Argument marshalling only: every step of a Fock build or an SCF runs in
+the library's HIP kernels.  There is no CPU fallback: importing this module
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1708_00033_amd.build` "
+                      "(the HIP library is required; there is no CPU fallback)")
+
+# torch's ROCm build carries its own HIP runtime with the same soname as the
+# system one; loading torch first makes libhfx.so bind to that runtime so
+# that torch tensors' device pointers and torch streams are valid in the
+# library (one HIP runtime per process).
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI does not need torch
+    torch = None
+
+_lib = C.CDLL(LIB_PATH)
+
+HFX_OK = 0
+HFX_ERR_INVALID_ARG = 1
+HFX_ERR_OOM = 2
+HFX_ERR_DEVICE = 3
+HFX_ERR_NOT_CONVERGED = 4
+HFX_ERR_NUMERICAL = 5
+HFX_ERR_STATE = 6
+STATUS_NAMES = {0: "HFX_OK", 1: "HFX_ERR_INVALID_ARG", 2: "HFX_ERR_OOM", 3: "HFX_ERR_DEVICE",
+                4: "HFX_ERR_NOT_CONVERGED", 5: "HFX_ERR_NUMERICAL", 6: "HFX_ERR_STATE"}
+HFX_PREC_FP64, HFX_PREC_MIXED = 0, 1
+HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL = 0, 1
+HFX_GUESS_SAD, HFX_GUESS_CORE = 0, 1
+
+CLASS_NAMES = [f"({b}|{k})" for bi, b in enumerate(["ss", "ps", "pp", "ds", "dp", "dd"])
+               for k in ["ss", "ps", "pp", "ds", "dp", "dd"][:bi + 1]]
+
+
+class hfx_shell(C.Structure):
+    _fields_ = [("atom", C.c_int), ("l", C.c_int), ("nprim", C.c_int),
+                ("exps", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double))]
+
+
+class hfx_options(C.Structure):
+    _fields_ = [("device", C.c_int), ("schwarz_tau", C.c_double), ("precision", C.c_int),
+                ("fp32_tau", C.c_double), ("digest", C.c_int), ("task_quartets", C.c_int),
+                ("log_level", C.c_int)]
+
+
+class hfx_scf_options(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("e_tol", C.c_double), ("d_rms_tol", C.c_double),
+                ("diis_max", C.c_int), ("guess", C.c_int), ("D0", C.POINTER(C.c_double)),
+                ("lindep", C.c_double)]
+
+
+class hfx_scf_result(C.Structure):
+    _fields_ = [("energy", C.c_double), ("e_nuc", C.c_double), ("iterations", C.c_int),
+                ("converged", C.c_int), ("guess_used", C.c_int), ("ndropped", C.c_int),
+                ("t_total_s", C.c_double), ("t_fock_s", C.c_double)]
+
+
+class hfx_fock_stats(C.Structure):
+    _fields_ = [("quartets_fp64", C.c_longlong), ("quartets_fp32", C.c_longlong),
+                ("integrals", C.c_longlong), ("prim_quartets", C.c_longlong), ("t_s", C.c_double)]
+
+
+_ctx_p = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_sigs = {
+    "hfx_default_options": ([C.POINTER(hfx_options)], C.c_int),
+    "hfx_default_scf_options": ([C.POINTER(hfx_scf_options)], C.c_int),
+    "hfx_create": ([C.POINTER(hfx_options), C.POINTER(_ctx_p)], C.c_int),
+    "hfx_load": ([_ctx_p, C.c_int, C.POINTER(C.c_int), _dp, C.c_int, C.POINTER(hfx_shell), C.c_int], C.c_int),
+    "hfx_dims": ([_ctx_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "hfx_core": ([_ctx_p, _dp, _dp, _dp], C.c_int),
+    "hfx_schwarz": ([_ctx_p, _dp], C.c_int),
+    "hfx_build_fock": ([_ctx_p, _dp, _dp, C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_build_fock_dev": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_build_2e_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                          C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
+    "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
+    "hfx_class_counts": ([_ctx_p, C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_kernel_timing": ([_ctx_p, C.c_int], C.c_int),
+    "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_last_error": ([_ctx_p], C.c_char_p),
+    "hfx_destroy": ([_ctx_p], None),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f
+
+EXPORTED = sorted(_sigs)
+
+
+class HfxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def default_options(**kw) -> hfx_options:
+    o = hfx_options()
+    hfx_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_scf_options(**kw) -> hfx_scf_options:
+    o = hfx_scf_options()
+    hfx_default_scf_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One hfx_ctx (owns its device memory)."""
+
+    def __init__(self, **opts):
+        self.opt = default_options(**opts)
+        p = _ctx_p()
+        st = hfx_create(C.byref(self.opt), C.byref(p))
+        if st != HFX_OK:
+            raise HfxError(st, "hfx_create failed")
+        self.ptr = p
+        self.nbf = self.nocc = self.nshell = 0
+
+    def _check(self, st: int):
+        if st != HFX_OK:
+            raise HfxError(st, hfx_last_error(self.ptr).decode())
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            hfx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, mol, charge: int = 0):
+        f = mol.flat()
+        shells = (hfx_shell * f["nshell"])()
+        self._keep = []
+        for s, sh in enumerate(mol.shells):
+            ex = np.ascontiguousarray(sh.exps, dtype=np.float64)
+            co = np.ascontiguousarray(sh.coefs, dtype=np.float64)
+            self._keep += [ex, co]
+            shells[s].atom, shells[s].l, shells[s].nprim = int(sh.atom), int(sh.l), len(ex)
+            shells[s].exps, shells[s].coefs = _d(ex), _d(co)
+        Z = np.ascontiguousarray(f["Z"], dtype=np.int32)
+        xyz = np.ascontiguousarray(f["xyz"], dtype=np.float64)
+        self._check(hfx_load(self.ptr, f["natom"], Z.ctypes.data_as(C.POINTER(C.c_int)), _d(xyz), f["nshell"],
+                             shells, charge))
+        nbf, nocc, nsh = C.c_int(), C.c_int(), C.c_int()
+        self._check(hfx_dims(self.ptr, C.byref(nbf), C.byref(nocc), C.byref(nsh)))
+        self.nbf, self.nocc, self.nshell = nbf.value, nocc.value, nsh.value
+        return self
+
+    def configure(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opt, k, v)
+        self._check(hfx_configure(self.ptr, C.byref(self.opt)))
+
+    def core(self):
+        n = self.nbf
+        S, H, e = np.zeros((n, n)), np.zeros((n, n)), C.c_double()
+        self._check(hfx_core(self.ptr, _d(S), _d(H), C.byref(e)))
+        return S, H, e.value
+
+    def schwarz(self):
+        Q = np.zeros((self.nshell, self.nshell))
+        self._check(hfx_schwarz(self.ptr, _d(Q)))
+        return Q
+
+    def build_fock(self, D: np.ndarray):
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        F = np.zeros_like(D)
+        st = hfx_fock_stats()
+        self._check(hfx_build_fock(self.ptr, _d(D), _d(F), C.byref(st)))
+        return F, st
+
+    def build_fock_dev(self, dD_ptr: int, dF_ptr: int, stream: int = 0, stats: bool = False):
+        st = hfx_fock_stats() if stats else None
+        self._check(hfx_build_fock_dev(self.ptr, C.c_void_p(dD_ptr), C.c_void_p(dF_ptr), C.c_void_p(stream),
+                                       C.byref(st) if stats else None))
+        return st
+
+    def build_2e_dev(self, dD_ptr: int, cj: float, ck: float, dG_ptr: int, stream: int = 0, stats: bool = False):
+        st = hfx_fock_stats() if stats else None
+        self._check(hfx_build_2e_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, C.c_void_p(dG_ptr), C.c_void_p(stream),
+                                     C.byref(st) if stats else None))
+        return st
+
+    def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, **kw):
+        o = default_scf_options(**kw)
+        keep = None
+        if D0 is not None:
+            keep = np.ascontiguousarray(D0, dtype=np.float64)
+            o.D0 = _d(keep)
+        n = self.nbf
+        res = hfx_scf_result()
+        D = np.zeros((n, n))
+        Cm = np.zeros((n, n)) if want_c else None
+        eps = np.zeros(n)
+        st = hfx_scf(self.ptr, C.byref(o), C.byref(res), _d(D), _d(Cm) if want_c else None, _d(eps))
+        if st not in (HFX_OK, HFX_ERR_NOT_CONVERGED):
+            self._check(st)
+        nmo = n - res.ndropped
+        out = dict(energy=res.energy, e_nuc=res.e_nuc, iterations=res.iterations, converged=bool(res.converged),
+                   guess_used=res.guess_used, ndropped=res.ndropped, t_total_s=res.t_total_s,
+                   t_fock_s=res.t_fock_s, D=D, eps=eps[:nmo], status=st)
+        if want_c:
+            out["C"] = Cm.reshape(-1)[: n * nmo].reshape(n, nmo)
+        return out
+
+    def class_counts(self) -> np.ndarray:
+        a = np.zeros(21 * 4, dtype=np.int64)
+        self._check(hfx_class_counts(self.ptr, a.ctypes.data_as(C.POINTER(C.c_longlong))))
+        return a.reshape(21, 4)
+
+    def kernel_timing(self, enable: bool = True):
+        self._check(hfx_kernel_timing(self.ptr, int(enable)))
+
+    def kernel_times(self):
+        ms = np.zeros(21)
+        n = np.zeros(21, dtype=np.int64)
+        self._check(hfx_kernel_times(self.ptr, _d(ms), n.ctypes.data_as(C.POINTER(C.c_longlong))))
+        return ms, n
