@@ -1,0 +1,230 @@
+"""Benchmark: screened ERI quartets/s and Fock-build time on one MI355X.
+
+Workload: 64 waters on a jittered 4^3 lattice (seed 1), s/p/d synthetic
+basis, 640 shells, 1216 basis functions, Schwarz threshold 1e-10 (a seeded
+stand-in for the paper's graphene bilayers in 6-31G(d), section 5.2).
+A step is one direct Fock build F = H + 2J - K from the converged FP64 SCF
+density (density preparation, all 21 quartet-class kernels, assembly), with
+the density and all data resident in HBM.  The FP64 build is the headline;
+the mixed-precision build (FP32 for quartets with Q_ab Q_cd max|D| < 1e-7) is
+timed the same way and reported with its error against the FP64 build.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+SETUP_FLOPS = 20            # per primitive quartet: p+q, 1/(p+q), rho, P-Q, T, prefactor, W-P, W-Q
+BOYS_FLOPS_TAYLOR = 3 * 7 + 4  # 8-term Taylor at the nearest grid point
+KERNEL_SOURCES = ["paper_1708_00033_amd/csrc/eri_impl.h", "paper_1708_00033_amd/csrc/hfx_internal.h",
+                  "paper_1708_00033_amd/csrc/gen_eri.py"]
+
+
+def class_flop_model():
+    """Algorithmic flops of each class: per primitive quartet (setup, Boys
+    with downward recursion, vertical recurrence) and per quartet
+    (horizontal recurrences, contraction sums, 6 updates x 2 flops per
+    integral for the digestion of eq. 2)."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_1708_00033_amd", "csrc"))
+    import gen_eri
+    out = []
+    for (B, K) in gen_eri.CLASSES:
+        la, lb = gen_eri.PAIR_CLASSES[B]
+        lc, ld = gen_eri.PAIR_CLASSES[K]
+        g = gen_eri.ClassGen(la, lb, lc, ld)
+        g.emit("x")
+        L = la + lb + lc + ld
+        nint = gen_eri.ncart(la) * gen_eri.ncart(lb) * gen_eri.ncart(lc) * gen_eri.ncart(ld)
+        es, fs = g.targets()
+        per_prim = SETUP_FLOPS + BOYS_FLOPS_TAYLOR + 3 * L + L + g.flops + len(es) * len(fs)
+        per_quartet = g.hrr_flops + 12 * nint
+        out.append((per_prim, per_quartet, nint))
+    return out
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(mol, D, target_s=15.0):
+    """The CPU oracle's 8-fold Fock build on a bounded sample of the same
+    workload: every stride-th bra shell pair (all its kets), sized for about
+    target_s seconds; quartets/s of the sample."""
+    import oracle
+    B = oracle.Basis(mol)
+    B.schwarz()
+    nthreads = oracle.num_threads()
+    # grow the sample (smaller stride) until it takes about target_s seconds
+    stride = 20011
+    while True:
+        t0 = time.time()
+        _, _, st2 = B.jk(D, 1e-10, stride=stride, phase=0)
+        dt2 = time.time() - t0
+        if dt2 >= 0.6 * target_s or stride == 1:
+            break
+        stride = max(1, int(stride * max(dt2, 0.05) / target_s))
+    stride2 = stride
+    return dict(value=st2[0] / dt2, unit="quartets/s", cores=nthreads, kind="oracle",
+                sample=f"bra shell pairs with index % {stride2} == 0 (all their kets): {st2[0]} screened quartets, "
+                       f"{st2[1]} integrals in {dt2:.1f} s, FP64 McMurchie-Davidson, OpenMP over bra pairs",
+                seconds=dt2)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--digest", type=int, default=0)
+    ap.add_argument("--task", type=int, default=8192)
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling run: synthetic projector density, FP64 builds only, no SCF and no CPU leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 512 MiB device copy (HBM-counter calibration for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1708_00033_amd import hfx
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    mol = W.cluster64_config()
+    ctx = hfx.Context(device=0, digest=args.digest, task_quartets=args.task).load(mol)
+    counts = ctx.class_counts()
+    log(f"loaded {mol.name}: nbf={ctx.nbf} shells={ctx.nshell} quartets={counts[:, 0].sum():.4e}")
+    if args.profile:
+        dev = torch.device("cuda:0")
+        D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 3), device=dev)
+        F = torch.empty_like(D)
+        sptr = torch.cuda.current_stream(dev).cuda_stream
+        for _ in range(args.warmup + args.steps):
+            ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sptr)
+        torch.cuda.synchronize()
+        if args.copy_calibration:
+            src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        log(f"profile run done: {args.warmup + args.steps} FP64 builds")
+        return
+    t0 = time.time()
+    r = ctx.scf(e_tol=1e-8, d_rms_tol=1e-7)
+    log(f"FP64 SCF: E={r['energy']:.10f} iterations={r['iterations']} converged={r['converged']} "
+        f"({time.time() - t0:.1f} s)")
+    Dh = r["D"]
+    dev = torch.device("cuda:0")
+    D = torch.tensor(Dh, device=dev)
+    F64 = torch.empty_like(D)
+    Fmx = torch.empty_like(D)
+    stream = torch.cuda.current_stream(dev)
+    sptr = stream.cuda_stream
+
+    def timed(nsteps, out, prec):
+        ctx.configure(precision=prec)
+        for _ in range(args.warmup):
+            ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr)
+        torch.cuda.synchronize()
+        ctx.kernel_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(nsteps):
+            ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        ms, n = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        st = ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr, stats=True)
+        return dt, ms, n, st
+
+    dt64, ms64, n64, st64 = timed(args.steps, F64, hfx.HFX_PREC_FP64)
+    dtmx, msmx, nmx, stmx = timed(args.steps, Fmx, hfx.HFX_PREC_MIXED)
+    quartets = int(counts[:, 0].sum())
+    value = quartets * args.steps / dt64
+    value_mx = quartets * args.steps / dtmx
+    Fd = (Fmx - F64).abs().max().item()
+    dE = float(torch.sum(D * (Fmx - F64)).item())   # E = tr(D (H + F)) at fixed D
+
+    # roofline of the dominant class kernel (FP64 build)
+    model = class_flop_model()
+    dom = int(np.argmax(ms64))
+    per_prim, per_q, nint = model[dom]
+    flops_launch = counts[dom, 2] * per_prim + counts[dom, 0] * per_q
+    avg_ms = ms64[dom] / max(n64[dom], 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if os.path.exists(prof):
+        with open(prof) as fh:
+            pj = json.load(fh)
+        if pj.get("source_hash") == source_hash() and pj.get("kernel") == hfx.CLASS_NAMES[dom]:
+            traffic = pj.get("hbm_bytes_per_launch")
+    res = {
+        "metric": "screened ERI quartets/s + Fock-build time, FP64 vs mixed @1e-6 Eh, 1 GPU",
+        "value": value,
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt64 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded water cluster, synthetic even-tempered basis)",
+        "config": {"workload": "64-water jittered lattice cluster, seed 1, 640 shells, 1216 Cartesian basis "
+                               "functions, Schwarz tau 1e-10, converged FP64 SCF density",
+                   "nbf": ctx.nbf, "shells": ctx.nshell, "quartets_per_build": quartets,
+                   "integrals_per_build": int(counts[:, 1].sum()),
+                   "primitive_quartets_per_build": int(counts[:, 2].sum()),
+                   "digest": "lds-staged" if args.digest == 0 else "global-atomic", "task_quartets": args.task},
+        "mixed": {"value": value_mx, "unit": "quartets/s", "ms_per_step": dtmx / args.steps * 1e3,
+                  "speedup_vs_fp64": dt64 / dtmx, "fp32_tau": 1e-7, "quartets_fp32": int(stmx.quartets_fp32),
+                  "quartets_fp64": int(stmx.quartets_fp64), "max_abs_dF_vs_fp64": Fd,
+                  "dE_vs_fp64_at_fixed_D": dE},
+        "roofline": {"bound": "alu", "kernel": hfx.CLASS_NAMES[dom], "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch)},
+        "build_flops_model_tflops": total_flops / (dt64 / args.steps) / 1e12,
+        "class_ms_fp64": {hfx.CLASS_NAMES[k]: round(ms64[k] / max(n64[k], 1), 3) for k in np.argsort(-ms64)[:8]},
+        "scf": {"energy": r["energy"], "iterations": r["iterations"]},
+    }
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = src.numel() * 8
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        cb = cpu_baseline(mol, Dh)
+        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

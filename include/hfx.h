@@ -73,7 +73,7 @@ typedef struct {
     int precision;         /* HFX_PREC_FP64 or HFX_PREC_MIXED */
     double fp32_tau;       /* MIXED: FP32 iff Q_ab Q_cd max|D| < fp32_tau (default 1e-7) */
     int digest;            /* HFX_DIGEST_LDS (bra rows staged in LDS) or HFX_DIGEST_GLOBAL */
-    int task_quartets;     /* quartets per workgroup task (default 2048; multiple of 256) */
+    int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
 } hfx_options;
 

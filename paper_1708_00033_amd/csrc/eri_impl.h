@@ -39,7 +39,7 @@ __device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, in
 
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
-                                       const PairInfo& ket, const double* dab, double* jab, double* FI,
+                                       const PairInfo& ket, int spos, const double* dab, double* jab, double* FI,
                                        double* FJ) {
     const int N = a.nbf;
     const double* __restrict__ D = a.D;
@@ -61,7 +61,9 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
             jab[mn] += g * v;
         }
     }
-    // J, ket block: global atomics
+    // J, ket block.  MODE 0: into the ket list's own accumulator, indexed by
+    // ket position so that a wave's atomics fall in a few 64-byte lines
+    // (scattered into W once per build); MODE 1: straight into W.
 #pragma unroll
     for (int l = 0; l < NC; ++l)
 #pragma unroll
@@ -69,7 +71,10 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
             double v = 0.0;
 #pragma unroll
             for (int mn = 0; mn < NA * NB; ++mn) v += I[mn * NC * ND + l * ND + s] * dab[mn];
-            atomicAdd(W + (size_t)(fc + l) * N + fd + s, cj2 * v);
+            if constexpr (MODE == 0)
+                atomicAdd(a.wket + (size_t)(l * ND + s) * a.nket_list + spos, cj2 * v);
+            else
+                atomicAdd(W + (size_t)(fc + l) * N + fd + s, cj2 * v);
         }
     // K: W_ac -= ck g sum_{nu sigma} I D_bd
     {
@@ -260,27 +265,28 @@ __global__ __launch_bounds__(HFX_WG) void k_class(const ClassArgs a) {
             jab[m * NB + n] = 0.0;
         }
     const double sbra = bra.a != bra.b ? 2.0 : 1.0;
+    const int kps = a.nket_list, kfs = a.nket_list * a.knprim;
     unsigned n64 = 0, n32 = 0;
     for (int s = s0 + (int)threadIdx.x; s < send; s += HFX_WG) {
         const PairInfo ket = a.ket[s];
         double I[NI];
         if (!MIXED || s < split) {
-            E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.prim + ket.prim_off, ket.nprim, bra.AB,
+            E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
                                     ket.AB, a.boys64, I);
             ++n64;
         } else {
             float If[NI];
-            E::template run<float>(a.prim + bra.prim_off, bra.nprim, a.prim + ket.prim_off, ket.nprim, bra.AB,
+            E::template run<float>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
                                    ket.AB, a.boys32, If);
 #pragma unroll
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
         }
-        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((a.same_class && s == r) ? 1.0 : 2.0);
+        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((ket.a == bra.a && ket.b == bra.b) ? 1.0 : 2.0);
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
             digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ);
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ);
     }
     // bra J block: wave reduction, one add per wave
     const int lane = threadIdx.x & 63;
@@ -326,7 +332,9 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
     if (i >= npairs) return;
     const PairInfo pr = pairs[i];
     double I[NA * NB * NA * NB];
-    E::template run<double>(prim + pr.prim_off, pr.nprim, prim + pr.prim_off, pr.nprim, pr.AB, pr.AB, boys, I);
+    // ket read from the array-of-structures layout: field stride 1, primitive stride 10 doubles
+    E::template run<double>(prim + pr.prim_off, pr.nprim, (const double*)(prim + pr.prim_off), 1,
+                            (int)(sizeof(PrimPair) / sizeof(double)), pr.nprim, pr.AB, pr.AB, boys, I);
     double mx = 0.0;
 #pragma unroll
     for (int m = 0; m < NA; ++m)
@@ -342,18 +350,17 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
 
 // Kernel variants of one class: digestion mode x precision policy.  Classes
 // with integral blocks of HFX_ROLLED_DIGEST_MIN or more (d-d bra with a d-d or
-// d-p ket) exist only as the FP64 global-atomic kernel: their register
+// d-p ket) exist only in FP64 (both digestion modes): their register
 // allocation is the build-time bottleneck and they carry a negligible share
-// of the quartets, so MIXED and LDS requests run that kernel (FP64 is the
-// more accurate choice).
+// of the quartets, so MIXED requests run the FP64 kernel (the more accurate
+// choice).
 template <class E>
 struct ClassKernels {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
     static const void* get(int variant) {
         if constexpr (kOnlyFp64Global) {
-            (void)variant;
-            return (const void*)k_class<E, 1, 0>;
+            return variant >= 2 ? (const void*)k_class<E, 1, 0> : (const void*)k_class<E, 0, 0>;
         } else {
             static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 0, 1>,
                                        (const void*)k_class<E, 1, 0>, (const void*)k_class<E, 1, 1>};
@@ -368,11 +375,11 @@ struct ClassKernels {
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_;                                   \
         template <typename R>                                                                          \
-        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const PrimPair* kp,    \
-                                                   int nkp, const double* ab, const double* cd,        \
-                                                   const R* tab, R* out) {                             \
-            fname<R>(bp, nbp, kp, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]), R(cd[2]),    \
-                     tab, out);                                                                        \
+        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
+                                                   int kfs, int kps, int nkp, const double* ab,        \
+                                                   const double* cd, const R* tab, R* out) {           \
+            fname<R>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),   \
+                     R(cd[2]), tab, out);                                                              \
         }                                                                                              \
     };                                                                                                 \
     extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \

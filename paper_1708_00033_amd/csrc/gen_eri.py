@@ -132,25 +132,32 @@ class ClassGen:
         lines = []
         L = self.L
         lines.append(f"template <typename R>\n__device__ __forceinline__ void {fname}(")
-        lines.append("    const PrimPair* __restrict__ bp, int nbp, const PrimPair* __restrict__ kp, int nkp,")
-        lines.append("    const R AB0, const R AB1, const R AB2, const R CD0, const R CD1, const R CD2,")
+        lines.append("    const PrimPair* __restrict__ bp, int nbp, const double* __restrict__ kq0, int kfs, int kps,")
+        lines.append("    int nkp, const R AB0, const R AB1, const R AB2, const R CD0, const R CD1, const R CD2,")
         lines.append("    const R* __restrict__ boys_tab, R* __restrict__ out) {")
         for a in acc_name.values():
             lines.append(f"  R {a} = R(0);")
-        lines.append("  for (int ib = 0; ib < nbp; ++ib) {")
-        lines.append("    const PrimPair& B = bp[ib];")
-        lines.append("    const R p = R(B.p), i2p = R(B.inv2p), Kb = R(B.K);")
-        lines.append("    const R P0 = R(B.P[0]), P1 = R(B.P[1]), P2 = R(B.P[2]);")
-        lines.append("    const R PA0 = R(B.PA[0]), PA1 = R(B.PA[1]), PA2 = R(B.PA[2]);")
-        lines.append("    for (int ik = 0; ik < nkp; ++ik) {")
-        lines.append("      const PrimPair& Kq = kp[ik];")
-        lines.append("      const R q = R(Kq.p), i2q = R(Kq.inv2p);")
-        lines.append("      const R QC0 = R(Kq.PA[0]), QC1 = R(Kq.PA[1]), QC2 = R(Kq.PA[2]);")
-        lines.append("      const R PQ0 = P0 - R(Kq.P[0]), PQ1 = P1 - R(Kq.P[1]), PQ2 = P2 - R(Kq.P[2]);")
-        lines.append("      const R ipq = R(1) / (p + q);")
+        lines.append("  // ket primitives (per lane, structure of arrays: field stride kfs, primitive stride kps)")
+        lines.append("  for (int ik = 0; ik < nkp; ++ik) {")
+        lines.append("    const double* kq = kq0 + ik * kps;")
+        lines.append("    const R q = R(kq[0]), i2q = R(kq[kfs]), Kk = R(kq[8 * kfs]);")
+        lines.append("    const R Q0 = R(kq[2 * kfs]), Q1 = R(kq[3 * kfs]), Q2 = R(kq[4 * kfs]);")
+        lines.append("    const R QC0 = R(kq[5 * kfs]), QC1 = R(kq[6 * kfs]), QC2 = R(kq[7 * kfs]);")
+        lines.append("    // bra primitives (uniform across the workgroup)")
+        # unrolling the bra loop gives independent Boys/recurrence chains to
+        # interleave; only worth its code size (and compile time) for low L
+        lines.append("#pragma unroll 3" if L <= 2 else "#pragma unroll 1")
+        lines.append("    for (int ib = 0; ib < nbp; ++ib) {")
+        lines.append("      // uniform address in the constant address space: scalar loads")
+        lines.append("      const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + ib);")
+        lines.append("      const R p = R(B[0]), i2p = R(B[1]), Kb = R(B[8]);")
+        lines.append("      const R PA0 = R(B[5]), PA1 = R(B[6]), PA2 = R(B[7]);")
+        lines.append("      const R PQ0 = R(B[2]) - Q0, PQ1 = R(B[3]) - Q1, PQ2 = R(B[4]) - Q2;")
+        lines.append("      const R rs = hfx_rsqrt(p + q);   // 1/sqrt(p+q)")
+        lines.append("      const R ipq = rs * rs;")
         lines.append("      const R rho = p * q * ipq;")
         lines.append("      const R T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);")
-        lines.append("      const R pref = Kb * R(Kq.K) * hfx_sqrt(ipq);")
+        lines.append("      const R pref = Kb * Kk * rs;")
         lines.append(f"      R F[{L + 1}];")
         lines.append(f"      boys_eval<R, {L}>(T, F, boys_tab);")
         body = list(self.vrr_code)

@@ -61,7 +61,7 @@ extern "C" hfx_status hfx_default_options(hfx_options* o) {
     o->precision = HFX_PREC_FP64;
     o->fp32_tau = 1e-7;
     o->digest = HFX_DIGEST_LDS;
-    o->task_quartets = 2048;
+    o->task_quartets = 8192;
     o->log_level = 0;
     return HFX_OK;
 }
@@ -98,15 +98,22 @@ static void release_system(hfx_ctx* c) {
     dfree(c->d_prim);
     for (int k = 0; k < 6; ++k) {
         dfree(c->d_pairs[k]);
-        dfree(c->d_pairq[k]);
         c->npair[k] = 0;
     }
-    for (auto& p : c->plan) {
+    for (auto& L : c->ketlists) {
+        dfree(L.d_pairs);
+        dfree(L.d_q);
+        dfree(L.d_soa);
+        dfree(L.d_wket);
+    }
+    c->ketlists.clear();
+    for (auto& p : c->plans) {
         dfree(p.d_nket);
         dfree(p.d_split);
         dfree(p.d_tasks);
-        p = ClassPlan();
     }
+    c->plans.clear();
+    for (auto& t : c->totals) t = ClassTotals();
     dfree(c->d_cscale);
     dfree(c->d_S);
     dfree(c->d_H);
@@ -130,7 +137,7 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         return HFX_ERR_DEVICE;
     }
     if (hipSetDevice(c->opt.device) != hipSuccess) { delete c; return HFX_ERR_DEVICE; }
-    std::vector<double> tab((size_t)BOYS_NT * BOYS_NM);
+    std::vector<double> tab((size_t)BOYS_NL * BOYS_NT * BOYS_ROW);
     hfx_boys_table(tab.data());
     std::vector<float> tab32(tab.begin(), tab.end());
     if (dalloc(&c->d_boys64, tab.size()) != hipSuccess || dalloc(&c->d_boys32, tab.size()) != hipSuccess ||
@@ -181,8 +188,8 @@ extern "C" hfx_status hfx_configure(hfx_ctx* c, const hfx_options* o) {
     c->opt = *o;
     if (!replan || !c->loaded) {
         // digestion mode may change without a new plan
-        for (auto& p : c->plan)
-            p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024 && !p.fp64_global_only) ? 0 : 1;
+        for (auto& p : c->plans)
+            p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024) ? 0 : 1;
         return HFX_OK;
     }
     return hfx_fail(c, HFX_ERR_STATE, "task_quartets changed: call hfx_load again");
@@ -196,34 +203,44 @@ static double dfact_odd(int n) {   // (2n-1)!!
     return r;
 }
 
-// Plan one class: per-bra screened ket counts, workgroup tasks, counts.
-static hfx_status plan_class(hfx_ctx* c, int B, int K, const std::vector<std::vector<PairInfo>>& lists) {
-    ClassPlan& P = c->plan[class_id(B, K)];
-    P = ClassPlan();
+// Plan one launch (class (B, K) against ket list li): per-bra screened ket
+// counts, workgroup tasks, counts.  Bras are the whole Q-sorted list of pair
+// class B; for B == K an unordered pair {bra, ket} is taken once, with the
+// ket not after the bra in that order (Q descending, then pair index).
+static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo>& bras,
+                           const std::vector<double>& bra_pos, const std::vector<PairInfo>& kets,
+                           const std::vector<double>& ket_pos) {
+    const KetList& KL = c->ketlists[li];
+    const int K = KL.K;
+    SubPlan P;
+    P.cid = class_id(B, K);
     P.B = B;
     P.K = K;
-    const auto& bras = lists[B];
-    const auto& kets = lists[K];
+    P.list = li;
     const double tau = c->opt.schwarz_tau;
     const int TQ = c->opt.task_quartets;
     std::vector<int> nket(bras.size(), 0);
-    std::vector<long long> kprim_prefix(kets.size() + 1, 0);
-    for (size_t s = 0; s < kets.size(); ++s) kprim_prefix[s + 1] = kprim_prefix[s] + kets[s].nprim;
     int nbra = 0;
     for (size_t r = 0; r < bras.size(); ++r) {
         const double qr = bras[r].Q;
-        // kets with Q_s * Q_r >= tau form a prefix of the Q-descending list
-        size_t lo = 0, hi = kets.size();
+        size_t lo = 0, hi = kets.size();   // kets with Q_s Q_r >= tau: a prefix
         while (lo < hi) {
             size_t mid = (lo + hi) / 2;
             if (kets[mid].Q * qr >= tau) lo = mid + 1; else hi = mid;
         }
         size_t n = lo;
-        if (B == K) n = std::min(n, r + 1);
+        if (B == K) {   // kets at or before the bra in the class order: a prefix too
+            size_t l2 = 0, h2 = kets.size();
+            while (l2 < h2) {
+                size_t mid = (l2 + h2) / 2;
+                if (ket_pos[mid] <= bra_pos[r]) l2 = mid + 1; else h2 = mid;
+            }
+            n = std::min(n, l2);
+        }
         nket[r] = (int)n;
         if (n > 0) nbra = (int)r + 1;
         P.quartets += (long long)n;
-        P.prim += (long long)bras[r].nprim * kprim_prefix[n];
+        P.prim += (long long)bras[r].nprim * (long long)KL.kp * (long long)n;
     }
     const int nint = ncart(kPairL[B][0]) * ncart(kPairL[B][1]) * ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
     P.integrals = P.quartets * nint;
@@ -232,16 +249,22 @@ static hfx_status plan_class(hfx_ctx* c, int B, int K, const std::vector<std::ve
         for (int s0 = 0; s0 < nket[r]; s0 += TQ) tasks.push_back(make_int2(r, s0));
     if (tasks.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many tasks for one launch");
     P.nbra = nbra;
-    P.nket_list = (int)kets.size();
     P.ntask = (int)tasks.size();
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->nbf * sizeof(double);
-    P.fp64_global_only = nint >= 600;   // see ClassKernels in eri_impl.h
-    P.mode = (c->opt.digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024 && !P.fp64_global_only) ? 0 : 1;
+    P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
+    P.mode = (c->opt.digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024) ? 0 : 1;
+    if (P.ntask == 0) return HFX_OK;
     HIPCK(dalloc(&P.d_nket, nbra));
     HIPCK(dalloc(&P.d_split, nbra));
     HIPCK(dalloc(&P.d_tasks, tasks.size()));
-    if (nbra) HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
-    if (!tasks.empty()) HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice));
+    ClassTotals& T = c->totals[P.cid];
+    T.quartets += P.quartets;
+    T.integrals += P.integrals;
+    T.prim += P.prim;
+    T.ntask += P.ntask;
+    c->plans.push_back(P);
     return HFX_OK;
 }
 
@@ -418,8 +441,9 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
             c->Qshell[(size_t)L[i].b * nshell + L[i].a] = q[i];
         }
     }
-    // ---- significant pairs, sorted by Q descending ----
+    // ---- significant pairs, sorted by Q descending (ties: pair order) ----
     const double tau = c->opt.schwarz_tau;
+    std::vector<std::vector<double>> pos(6);
     for (int B = 0; B < 6; ++B) {
         auto& L = all[B];
         std::vector<PairInfo> keep;
@@ -429,20 +453,68 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
         std::stable_sort(keep.begin(), keep.end(), [](const PairInfo& x, const PairInfo& y) { return x.Q > y.Q; });
         L.swap(keep);
         c->npair[B] = (int)L.size();
-        std::vector<double> q(L.size());
-        for (size_t i = 0; i < L.size(); ++i) q[i] = L[i].Q;
+        pos[B].resize(L.size());
+        for (size_t i = 0; i < L.size(); ++i) pos[B][i] = (double)i;
         HIPCK(dalloc(&c->d_pairs[B], L.size()));
-        HIPCK(dalloc(&c->d_pairq[B], L.size()));
-        if (!L.empty()) {
-            HIPCK(hipMemcpy(c->d_pairs[B], L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
-            HIPCK(hipMemcpy(c->d_pairq[B], q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (!L.empty()) HIPCK(hipMemcpy(c->d_pairs[B], L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
+    }
+    // ---- ket lists: one per pair class and primitive count ----
+    std::vector<std::vector<PairInfo>> klist;
+    std::vector<std::vector<double>> kpos;
+    for (int K = 0; K < 6; ++K) {
+        std::vector<int> nps;
+        for (auto& p : all[K])
+            if (std::find(nps.begin(), nps.end(), p.nprim) == nps.end()) nps.push_back(p.nprim);
+        std::sort(nps.begin(), nps.end());
+        for (int kp : nps) {
+            KetList KL;
+            KL.K = K;
+            KL.kp = kp;
+            std::vector<PairInfo> sub;
+            std::vector<double> sp;
+            for (size_t i = 0; i < all[K].size(); ++i)
+                if (all[K][i].nprim == kp) {
+                    sub.push_back(all[K][i]);
+                    sp.push_back(pos[K][i]);
+                }
+            KL.n = (int)sub.size();
+            const size_t n = sub.size();
+            std::vector<double> q(n), soa((size_t)9 * kp * n);
+            for (size_t s = 0; s < n; ++s) {
+                q[s] = sub[s].Q;
+                for (int k = 0; k < kp; ++k) {
+                    const PrimPair& pp = prim[sub[s].prim_off + k];
+                    const double f[9] = {pp.p, pp.inv2p, pp.P[0], pp.P[1], pp.P[2], pp.PA[0], pp.PA[1], pp.PA[2], pp.K};
+                    for (int fi = 0; fi < 9; ++fi) soa[((size_t)fi * kp + k) * n + s] = f[fi];
+                }
+            }
+            HIPCK(dalloc(&KL.d_pairs, n));
+            HIPCK(dalloc(&KL.d_q, n));
+            HIPCK(dalloc(&KL.d_soa, soa.size()));
+            KL.ncd = ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
+            HIPCK(dalloc(&KL.d_wket, (size_t)KL.ncd * n));
+            HIPCK(hipMemcpy(KL.d_pairs, sub.data(), n * sizeof(PairInfo), hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(KL.d_q, q.data(), n * sizeof(double), hipMemcpyHostToDevice));
+            HIPCK(hipMemcpy(KL.d_soa, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+            c->ketlists.push_back(KL);
+            klist.push_back(std::move(sub));
+            kpos.push_back(std::move(sp));
         }
     }
     for (int B = 0; B < 6; ++B)
-        for (int K = 0; K <= B; ++K) {
-            hfx_status s = plan_class(c, B, K, all);
+        for (size_t li = 0; li < c->ketlists.size(); ++li) {
+            if (c->ketlists[li].K > B) continue;
+            hfx_status s = plan_sub(c, B, (int)li, all[B], pos[B], klist[li], kpos[li]);
             if (s != HFX_OK) return s;
         }
+    // launch order: largest classes first (sub-launches of a class stay together)
+    {
+        static const int order[21] = {0, 1, 2, 6, 7, 3, 8, 9, 4, 10, 11, 13, 12, 5, 15, 16, 14, 18, 17, 19, 20};
+        int rank[21];
+        for (int i = 0; i < 21; ++i) rank[order[i]] = i;
+        std::stable_sort(c->plans.begin(), c->plans.end(),
+                         [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
+    }
 
     // ---- one-electron integrals ----
     std::vector<double> atoms(4 * (size_t)natom);
@@ -520,10 +592,10 @@ extern "C" hfx_status hfx_class_counts(const hfx_ctx* c, long long* counts) {
     if (!c || !counts) return HFX_ERR_INVALID_ARG;
     if (!c->loaded) return HFX_ERR_STATE;
     for (int k = 0; k < 21; ++k) {
-        counts[4 * k] = c->plan[k].quartets;
-        counts[4 * k + 1] = c->plan[k].integrals;
-        counts[4 * k + 2] = c->plan[k].prim;
-        counts[4 * k + 3] = c->plan[k].ntask;
+        counts[4 * k] = c->totals[k].quartets;
+        counts[4 * k + 1] = c->totals[k].integrals;
+        counts[4 * k + 2] = c->totals[k].prim;
+        counts[4 * k + 3] = c->totals[k].ntask;
     }
     return HFX_OK;
 }
@@ -582,19 +654,24 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
     HIPCK(hfx_fill_u64(c->d_counters, 43, st));   // 42 quartet counters + the non-finite flag
     HIPCK(hfx_prepare_density(dD, c->d_cscale, n, c->d_Dp, c->d_dmax, st));
     HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
-    // largest classes first
-    static const int order[21] = {0, 1, 2, 6, 7, 3, 8, 9, 4, 10, 11, 13, 12, 5, 15, 16, 14, 18, 17, 19, 20};
-    for (int oi = 0; oi < 21; ++oi) {
-        const int cid = order[oi];
-        ClassPlan& P = c->plan[cid];
-        if (P.ntask == 0) continue;
-        if (mixed && !P.fp64_global_only)
-            HIPCK(hfx_split(c->d_pairs[P.B], c->d_pairq[P.K], P.nket_list, P.d_nket, P.nbra, c->opt.fp32_tau,
-                            c->d_dmax, P.d_split, st));
+    for (auto& KL : c->ketlists) HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
+    for (size_t pi = 0; pi < c->plans.size(); ++pi) {
+        SubPlan& P = c->plans[pi];
+        const KetList& KL = c->ketlists[P.list];
+        const int cid = P.cid;
+        const bool first = pi == 0 || c->plans[pi - 1].cid != cid;
+        const bool last = pi + 1 == c->plans.size() || c->plans[pi + 1].cid != cid;
+        const bool mx = mixed && !P.fp64_only;
+        if (mx)
+            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, KL.n, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
+                            st));
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
-        a.ket = c->d_pairs[P.K];
+        a.ket = KL.d_pairs;
         a.prim = c->d_prim;
+        a.kprim = KL.d_soa;
+        a.nket_list = KL.n;
+        a.knprim = KL.kp;
         a.nket = P.d_nket;
         a.split = P.d_split;
         a.tasks = P.d_tasks;
@@ -602,20 +679,22 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.boys32 = c->d_boys32;
         a.D = c->d_Dp;
         a.W = c->d_W;
+        a.wket = KL.d_wket;
         a.counters = c->d_counters + 2 * cid;
         a.nbf = n;
-        a.same_class = P.B == P.K;
         a.task_quartets = c->opt.task_quartets;
         a.cj = cj;
         a.ck = ck;
-        if (c->timing) HIPCK(hipEventRecord(c->ev_start[cid], st));
-        HIPCK(hfx_launch_class(cid, P.mode, (mixed && !P.fp64_global_only) ? 1 : 0, P.ntask,
-                               P.mode == 0 ? P.lds_bytes : 0, st, &a));
-        if (c->timing) {
+        if (c->timing && first) HIPCK(hipEventRecord(c->ev_start[cid], st));
+        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, P.ntask, P.mode == 0 ? P.lds_bytes : 0, st, &a));
+        if (c->timing && last) {
             HIPCK(hipEventRecord(c->ev_stop[cid], st));
             c->ev_pending[cid] = true;
         }
     }
+    for (auto& KL : c->ketlists)
+        HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, n, c->d_W,
+                              st));
     HIPCK(hfx_assemble(dH, c->d_W, c->d_cscale, n, dOut, c->d_bad, st));
     c->last_stream = st;
     if (stats) {
@@ -628,8 +707,8 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         for (int k = 0; k < 21; ++k) {
             stats->quartets_fp64 += (long long)cnt[2 * k];
             stats->quartets_fp32 += (long long)cnt[2 * k + 1];
-            stats->integrals += c->plan[k].integrals;
-            stats->prim_quartets += c->plan[k].prim;
+            stats->integrals += c->totals[k].integrals;
+            stats->prim_quartets += c->totals[k].prim;
         }
         stats->t_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (bad) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite value in the Fock matrix");

@@ -15,10 +15,21 @@ struct ShellHost {
     int l, nprim, prim_off, bf;
 };
 
-struct ClassPlan {
-    int B = 0, K = 0;
+// Significant pairs of one pair class that share one primitive count, sorted
+// by Schwarz bound (descending); ket primitives as a structure of arrays.
+struct KetList {
+    int K = 0, kp = 0, n = 0;
+    PairInfo* d_pairs = nullptr;
+    double* d_q = nullptr;
+    double* d_soa = nullptr;
+    double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
+    int ncd = 1;
+};
+
+// One launch: class (B, K) against one ket list.
+struct SubPlan {
+    int cid = 0, B = 0, K = 0, list = 0;
     int nbra = 0;             // bras with at least one ket
-    int nket_list = 0;        // size of the ket list (pairs of class K)
     int ntask = 0;
     int* d_nket = nullptr;
     int* d_split = nullptr;
@@ -26,7 +37,11 @@ struct ClassPlan {
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;
     int mode = 0;             // digestion actually used (LDS may fall back to global)
-    bool fp64_global_only = false;   // class built only as the FP64 global-atomic kernel
+    bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
+};
+
+struct ClassTotals {
+    long long quartets = 0, integrals = 0, prim = 0, ntask = 0;
 };
 
 struct hfx_ctx {
@@ -46,11 +61,12 @@ struct hfx_ctx {
     std::vector<int> shell_atom;
     // device data
     PrimPair* d_prim = nullptr;
-    PairInfo* d_pairs[6] = {nullptr};   // significant pairs per pair class, Q descending
-    double* d_pairq[6] = {nullptr};
+    PairInfo* d_pairs[6] = {nullptr};   // significant pairs per pair class, Q descending (bras)
     int npair[6] = {0};
+    std::vector<KetList> ketlists;      // per pair class and primitive count (kets)
+    std::vector<SubPlan> plans;         // launches, grouped by class id
+    ClassTotals totals[21];
     std::vector<double> Qshell;         // nshell x nshell Schwarz bounds (host)
-    ClassPlan plan[21];
     double* d_boys64 = nullptr;
     float* d_boys32 = nullptr;
     double* d_cscale = nullptr;
@@ -87,6 +103,8 @@ hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t hfx_split(const PairInfo* bra, const double* ketq, int nket_total, const int* nket, int nbra,
                      double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st);
+hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, int nbf, double* W,
+                           hipStream_t st);
 hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int n, double* F, int* bad,
                         hipStream_t st);
 hipError_t hfx_one_electron(const void* sh, int nshell, const double* exps, const double* coefs, const double* atoms,

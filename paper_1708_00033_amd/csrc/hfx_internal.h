@@ -30,11 +30,17 @@ struct PairInfo {
     double pad;
 };
 
-// Arguments of one class kernel launch.
+// Arguments of one class kernel launch.  The kets of a launch all have the
+// same number of primitive pairs (knprim), so the primitive loop trip count
+// is uniform across a wave.  Ket primitive data are a structure of arrays:
+// field f (the PrimPair member order p, inv2p, P[3], PA[3], K) of primitive k
+// of ket s at kprim[(f * knprim + k) * nket_list + s].
 struct ClassArgs {
     const PairInfo* __restrict__ bra;   // bra pairs of the class, Q descending
-    const PairInfo* __restrict__ ket;   // ket pairs of the class, Q descending
-    const PrimPair* __restrict__ prim;  // all primitive pairs
+    const PairInfo* __restrict__ ket;   // ket pairs (one primitive count), Q descending
+    const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
+    const double* __restrict__ kprim;   // ket primitives, structure of arrays
+    int nket_list, knprim;
     const int* __restrict__ nket;       // per bra: number of kets (screened prefix)
     const int* __restrict__ split;      // per bra: kets below this index use FP64 (nullptr: all)
     const int2* __restrict__ tasks;     // (bra index, first ket) per workgroup
@@ -42,30 +48,72 @@ struct ClassArgs {
     const float* __restrict__ boys32;
     const double* __restrict__ D;       // component-scaled density D'
     double* __restrict__ W;             // accumulator, F_2e = s (W + W^T) s / 8
+    double* __restrict__ wket;          // LDS mode: ket-block J sums, [component][ket position]
     unsigned long long* __restrict__ counters;  // [0] FP64 quartets, [1] FP32 quartets
     int nbf;
-    int same_class;
     int task_quartets;
     double cj, ck;                      // W_ab += cj*2 g D_cd ; W_ac -= ck g D_bd
 };
 
-// ---- Boys function table -------------------------------------------------------
-// F_m(T_k) on T_k = k * BOYS_DT, k = 0..BOYS_NT-1, m = 0..BOYS_NM-1.
-// F_m(T) = sum_j F_{m+j}(T_k) (T_k - T)^j / j!  (dF_m/dT = -F_{m+1}).
+// Constant address space: loads through such a pointer at a wave-uniform
+// address become scalar (SMEM) loads.
+#define HFX_CONST_AS __attribute__((address_space(4)))
+
+// ---- Boys function tables ---------------------------------------------------
+// For every order L (0..BOYS_NL-1) one table of 64-byte rows:
+//   tab[(L * BOYS_NT + k) * 8 + j] = F_{L+j}(T_k) / j!,  T_k = k * BOYS_DT,
+// so that F_L(T) = sum_j tab[..j] (T_k - T)^j about the nearest grid point
+// (dF_m/dT = -F_{m+1}); one aligned row is one cache line.
 #define BOYS_DT 0.1
 #define BOYS_INV_DT 10.0
 #define BOYS_TMAX 40.0
 #define BOYS_NT 402
-#define BOYS_NM 17
+#define BOYS_NL 9
+#define BOYS_ROW 8
 #define BOYS_ORDER64 8   // Taylor terms, FP64 (|T - T_k| <= 0.05: remainder < 1e-15 F)
 #define BOYS_ORDER32 5   // Taylor terms, FP32 (remainder < 3e-9 F)
 
-void hfx_boys_table(double* tab);   // host, BOYS_NT * BOYS_NM entries
+void hfx_boys_table(double* tab);   // host, BOYS_NL * BOYS_NT * BOYS_ROW entries
 
 __device__ __forceinline__ double hfx_sqrt(double x) { return sqrt(x); }
+// 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps
+// y <- y (3/2 - x/2 y^2) (two steps for FP64, one for FP32).
+__device__ __forceinline__ double hfx_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    return y;
+}
+__device__ __forceinline__ float hfx_rsqrt(float x) {
+    float y = __builtin_amdgcn_rsqf(x);
+    return y * (1.5f - 0.5f * x * y * y);
+}
 __device__ __forceinline__ float hfx_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double hfx_exp(double x) { return exp(x); }
 __device__ __forceinline__ float hfx_exp(float x) { return __expf(x); }
+
+// Taylor value of F_L at T from the order-L table (row k, offset d = T_k - T).
+template <int NO>
+__device__ __forceinline__ double boys_taylor(const double* __restrict__ row, double d) {
+    const double2* r2 = reinterpret_cast<const double2*>(row);
+    const double2 c01 = r2[0], c23 = r2[1], c45 = r2[2], c67 = r2[3];
+    const double c[8] = {c01.x, c01.y, c23.x, c23.y, c45.x, c45.y, c67.x, c67.y};
+    double f = c[NO - 1];
+#pragma unroll
+    for (int j = NO - 2; j >= 0; --j) f = c[j] + f * d;
+    return f;
+}
+template <int NO>
+__device__ __forceinline__ float boys_taylor(const float* __restrict__ row, float d) {
+    const float4* r4 = reinterpret_cast<const float4*>(row);
+    const float4 c03 = r4[0], c47 = r4[1];
+    const float c[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
+    float f = c[NO - 1];
+#pragma unroll
+    for (int j = NO - 2; j >= 0; --j) f = c[j] + f * d;
+    return f;
+}
 
 template <typename R> struct BoysOrder;
 template <> struct BoysOrder<double> { static constexpr int value = BOYS_ORDER64; };
@@ -73,8 +121,8 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 
 // F[0..L] at T.  Below BOYS_TMAX: Taylor expansion of F_L about the nearest
 // grid point, then the downward recursion F_m = (2T F_{m+1} + e^{-T})/(2m+1)
-// (for L <= 1 every order is taken from the table, no exponential needed).
-// Above: F_0 = sqrt(pi/T)/2 and the upward recursion
+// (for L = 1 both orders come from their tables, no exponential needed).
+// Above: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to FP64 there) and the upward recursion
 // F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m.
 template <typename R, int L>
 __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) {
@@ -82,31 +130,21 @@ __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) 
     if (T < R(BOYS_TMAX)) {
         const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
         const R d = R(k) * R(BOYS_DT) - T;
-        const R* row = tab + k * BOYS_NM;
-        if constexpr (L <= 1) {
-#pragma unroll
-            for (int m = 0; m <= L; ++m) {
-                R f = row[m + NO - 1];
-#pragma unroll
-                for (int j = NO - 1; j >= 1; --j) f = row[m + j - 1] + f * d * R(1.0 / j);
-                F[m] = f;
-            }
-        } else {
-            R f = row[L + NO - 1];
-#pragma unroll
-            for (int j = NO - 1; j >= 1; --j) f = row[L + j - 1] + f * d * R(1.0 / j);
-            F[L] = f;
+        F[L] = boys_taylor<NO>(tab + ((size_t)L * BOYS_NT + k) * BOYS_ROW, d);
+        if constexpr (L == 1) {
+            F[0] = boys_taylor<NO>(tab + (size_t)k * BOYS_ROW, d);
+        } else if constexpr (L > 1) {
             const R e = hfx_exp(-T);
             const R t2 = R(2) * T;
 #pragma unroll
             for (int m = L - 1; m >= 0; --m) F[m] = (t2 * F[m + 1] + e) * R(1.0 / (2 * m + 1));
         }
     } else {
-        const R it = R(1) / T;
-        F[0] = R(0.886226925452758013649083741671) * hfx_sqrt(it);   // sqrt(pi)/2
+        const R rt = hfx_rsqrt(T);
+        F[0] = R(0.886226925452758013649083741671) * rt;   // sqrt(pi)/2 / sqrt(T)
         if constexpr (L > 0) {
             const R e = hfx_exp(-T);
-            const R h = R(0.5) * it;
+            const R h = R(0.5) * rt * rt;
 #pragma unroll
             for (int m = 0; m < L; ++m) F[m + 1] = (R(2 * m + 1) * F[m] - e) * h;
         }

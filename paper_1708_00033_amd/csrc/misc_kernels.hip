@@ -72,6 +72,20 @@ __global__ void k_assemble(const double* __restrict__ H, const double* __restric
     }
 }
 
+// W_cd += wket[comp][s] for every ket pair s of one list: each pair owns its
+// W block, so plain read-modify-write (no atomics) after the class kernels.
+__global__ void k_scatter_ket(const PairInfo* __restrict__ kets, int n, int nc, int nd,
+                              const double* __restrict__ wket, int nbf, double* __restrict__ W) {
+    const int i = blockIdx.x * MISC_WG + threadIdx.x;
+    if (i >= n * nc * nd) return;
+    const int s = i % n, comp = i / n;
+    const double v = wket[i];
+    if (v == 0.0) return;
+    const PairInfo p = kets[s];
+    const size_t idx = (size_t)(p.bfa + comp / nd) * nbf + p.bfb + comp % nd;
+    W[idx] += v;
+}
+
 // ---- one-electron integrals (Obara-Saika) ------------------------------------
 // One thread per shell pair (a >= b).  Overlap from the 1-D recursion
 //   S_{i+1,j} = X_PA S_ij + (i S_{i-1,j} + j S_{i,j-1})/(2p), same for j with X_PB;
@@ -336,6 +350,14 @@ hipError_t hfx_split(const PairInfo* bra, const double* ketq, int nket_total, co
     if (nbra <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_split, dim3((nbra + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, nket_total, nket,
                        nbra, fp32_tau, dmax_bits, split);
+    return hipGetLastError();
+}
+hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, int nbf, double* W,
+                           hipStream_t st) {
+    const int tot = n * nc * nd;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_ket, dim3((tot + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, kets, n, nc, nd, wket,
+                       nbf, W);
     return hipGetLastError();
 }
 hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int n, double* F, int* bad,
