@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--digest", type=int, default=0)
     ap.add_argument("--task", type=int, default=8192)
+    ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
+    ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
+    ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: synthetic projector density, FP64 builds only, no SCF and no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -121,6 +124,9 @@ def main():
         D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 3), device=dev)
         F = torch.empty_like(D)
         sptr = torch.cuda.current_stream(dev).cuda_stream
+        if args.tuning:
+            from paper_1708_00033_amd import autotune
+            autotune.apply(ctx, autotune.load(args.tuning))
         for _ in range(args.warmup + args.steps):
             ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sptr)
         torch.cuda.synchronize()
@@ -143,6 +149,16 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sptr = stream.cuda_stream
 
+    tuning = None
+    if not args.no_autotune:
+        from paper_1708_00033_amd import autotune
+        t0 = time.time()
+        tuning = autotune.autotune(ctx, D.data_ptr(), F64.data_ptr(), sptr)
+        if args.save_tuning:
+            autotune.save(tuning, args.save_tuning)
+        log(f"autotuned per-class scheduling in {time.time() - t0:.1f} s: "
+            f"{autotune.summary(tuning, ['(ss|ss)', '(ps|ss)', '(ds|ss)', '(ps|ps)'])}")
+
     def timed(nsteps, out, prec):
         ctx.configure(precision=prec)
         for _ in range(args.warmup):
@@ -156,32 +172,35 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         ms, n = ctx.kernel_times()
+        plans = ctx.plans()
         ctx.kernel_timing(False)
         st = ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr, stats=True)
-        return dt, ms, n, st
+        return dt, ms, n, plans, st
 
-    dt64, ms64, n64, st64 = timed(args.steps, F64, hfx.HFX_PREC_FP64)
-    dtmx, msmx, nmx, stmx = timed(args.steps, Fmx, hfx.HFX_PREC_MIXED)
+    dt64, ms64, n64, plans64, st64 = timed(args.steps, F64, hfx.HFX_PREC_FP64)
+    dtmx, msmx, nmx, plansmx, stmx = timed(args.steps, Fmx, hfx.HFX_PREC_MIXED)
     quartets = int(counts[:, 0].sum())
     value = quartets * args.steps / dt64
     value_mx = quartets * args.steps / dtmx
     Fd = (Fmx - F64).abs().max().item()
     dE = float(torch.sum(D * (Fmx - F64)).item())   # E = tr(D (H + F)) at fixed D
 
-    # roofline of the dominant class kernel (FP64 build)
+    # roofline of the dominant kernel launch of the FP64 build: one class
+    # against one ket list (one kernel symbol at one grid size)
     model = class_flop_model()
-    dom = int(np.argmax(ms64))
-    per_prim, per_q, nint = model[dom]
-    flops_launch = counts[dom, 2] * per_prim + counts[dom, 0] * per_q
-    avg_ms = ms64[dom] / max(n64[dom], 1)
+    dom = max(plans64, key=lambda p: p["ms"])
+    per_prim, per_q, nint = model[dom["cls"]]
+    flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    kname = f"k_class<Eval{dom['cls']}, {dom['mode']}, 0> grid {dom['tasks'] * 256}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
     prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if os.path.exists(prof):
         with open(prof) as fh:
             pj = json.load(fh)
-        if pj.get("source_hash") == source_hash() and pj.get("kernel") == hfx.CLASS_NAMES[dom]:
+        if pj.get("source_hash") == source_hash() and pj.get("kernel") == kname:
             traffic = pj.get("hbm_bytes_per_launch")
     res = {
         "metric": "screened ERI quartets/s + Fock-build time, FP64 vs mixed @1e-6 Eh, 1 GPU",
@@ -206,12 +225,16 @@ def main():
                   "speedup_vs_fp64": dt64 / dtmx, "fp32_tau": 1e-7, "quartets_fp32": int(stmx.quartets_fp32),
                   "quartets_fp64": int(stmx.quartets_fp64), "max_abs_dF_vs_fp64": Fd,
                   "dE_vs_fp64_at_fixed_D": dE},
-        "roofline": {"bound": "alu", "kernel": hfx.CLASS_NAMES[dom], "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kname, "class": hfx.CLASS_NAMES[dom["cls"]],
+                     "ket_nprim": dom["ket_nprim"], "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic, "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch)},
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch),
+                     "quartets_per_launch": dom["quartets"], "primitive_quartets_per_launch": dom["prim"]},
         "build_flops_model_tflops": total_flops / (dt64 / args.steps) / 1e12,
         "class_ms_fp64": {hfx.CLASS_NAMES[k]: round(ms64[k] / max(n64[k], 1), 3) for k in np.argsort(-ms64)[:8]},
+        "class_ms_mixed": {hfx.CLASS_NAMES[k]: round(msmx[k] / max(nmx[k], 1), 3) for k in np.argsort(-msmx)[:8]},
         "scf": {"energy": r["energy"], "iterations": r["iterations"]},
+        "autotune": None if tuning is None else {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()},
     }
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)

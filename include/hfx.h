@@ -136,6 +136,14 @@ hfx_status hfx_build_fock_dev(hfx_ctx *ctx, const double *dD, double *dF, void *
 hfx_status hfx_build_2e_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, double *dG,
                             void *stream, hfx_fock_stats *stats);
 
+/* One GPU's share of a multi-GPU build: dG = cj J - ck K restricted to the
+ * bra shell pairs r with r % nshards == shard (r = position in each class's
+ * Schwarz-ordered bra list).  Summing the nshards results gives the full
+ * two-electron matrix (the partial Fock matrices that the paper's
+ * ddi_gsumf reduces in algorithms 1-3). */
+hfx_status hfx_build_2e_shard_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, int shard,
+                                  int nshards, double *dG, void *stream);
+
 /* Closed-shell SCF to convergence (section 3, eq. 1): guess, Fock build,
  * Pulay DIIS, eigensolve of X^T F X, aufbau density.  D_out, C_out
  * (nbf x nmo, nmo = nbf - dropped), eps_out (nmo) are optional host arrays.
@@ -147,16 +155,31 @@ hfx_status hfx_scf(hfx_ctx *ctx, const hfx_scf_options *opt, hfx_scf_result *res
  * and device must stay as created). */
 hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
 
+/* Per-class scheduling knobs (class index 0..20, or -1 for all): quartets
+ * per workgroup task (0: the context's task_quartets) and XCD striping of
+ * long ket prefixes (1 on, 0 off, -1 default on).  Re-plans a loaded
+ * system; results are unchanged, only the work decomposition moves.  Set by
+ * the autotuner (paper_1708_00033_amd/autotune.py). */
+hfx_status hfx_set_class_tuning(hfx_ctx *ctx, int cls, int task_quartets, int xcd_stripe);
+
 /* Per-class plan counts: counts[21*4] = {unique quartets, integrals,
  * primitive quartets, workgroup tasks} for each canonical quartet class in
  * the order (ss|ss), (ps|ss), (ps|ps), (pp|ss), ..., (dd|dd). */
 hfx_status hfx_class_counts(const hfx_ctx *ctx, long long *counts);
 
-/* Kernel timing: when enabled, every class kernel is bracketed by HIP events
- * on its stream; hfx_kernel_times returns the summed milliseconds and launch
- * counts per class since the last reset (synchronises the last stream). */
+/* Kernel timing: when enabled, every class kernel launch is bracketed by HIP
+ * events on its stream; hfx_kernel_times returns per class the summed
+ * milliseconds of its launches and the number of timed builds since the last
+ * reset (synchronises on the recorded events). */
 hfx_status hfx_kernel_timing(hfx_ctx *ctx, int enable);
 hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
+
+/* Launches of a build: one per (quartet class, ket primitive count).  info[8]
+ * = {class index, ket primitives per pair, workgroup tasks (grid = 256 x
+ * tasks), unique quartets, primitive quartets, integrals, timed launches,
+ * digestion mode}; *ms = summed event time of the timed launches. */
+hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
+hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 
 const char *hfx_last_error(const hfx_ctx *ctx);
 void hfx_destroy(hfx_ctx *ctx);

@@ -23,8 +23,10 @@ extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, 
         if (e != hipSuccess) return e;
     }
     void* kargs[] = {(void*)args};
-    return hipLaunchKernel(fn, dim3(ntask), dim3(HFX_WG), kargs, lds_bytes, stream);
+    return hipLaunchKernel(fn, dim3(ntask), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
 }
+
+extern "C" int hfx_class_wgs(int cid) { return kEriClassInfo[cid].wgs; }
 
 extern "C" hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim,
                                          const double* boys, const double* cscale, double* Q,

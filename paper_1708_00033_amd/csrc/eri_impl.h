@@ -5,7 +5,8 @@
 // kets that survive screening Q_r Q_s >= tau are a prefix of the ket list
 // (for bra and ket of the same class, additionally s <= r keeps each
 // unordered quartet once).  A workgroup task is one bra pair and up to
-// task_quartets consecutive kets of its prefix; lanes take one quartet each.
+// consecutive kets of its prefix (at most task_quartets); lanes take one
+// quartet each.
 //
 // Digestion (section 4.1, eq. 2) accumulates W with
 //   W_ab += 2 cj g D_cd,  W_cd += 2 cj g D_ab,
@@ -239,21 +240,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One class, one digestion mode, one precision policy (MIXED = 1: kets at or
 // beyond split[r] are evaluated in FP32 and widened before digestion).
 template <class E, int MODE, int MIXED>
-__global__ __launch_bounds__(HFX_WG) void k_class(const ClassArgs a) {
+__global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     extern __shared__ double lds[];
     const int N = a.nbf;
-    const int2 task = a.tasks[blockIdx.x];
+    const int4 task = a.tasks[blockIdx.x];
     const int r = task.x, s0 = task.y;
+    if (r < 0) return;                                        // padding task (XCD striping)
+    if (a.nshards > 1 && r % a.nshards != a.shard) return;   // whole workgroup: uniform exit
     const PairInfo bra = a.bra[r];
     const int nk = a.nket[r];
-    const int send = min(s0 + a.task_quartets, nk);
+    const int send = min(task.z, nk);
     const int split = MIXED ? a.split[r] : nk;
     double* FI = lds;
     double* FJ = lds + NA * N;
     if constexpr (MODE == 0) {
-        for (int i = threadIdx.x; i < (NA + NB) * N; i += HFX_WG) lds[i] = 0.0;
+        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) lds[i] = 0.0;
         __syncthreads();
     }
     double dab[NAB], jab[NAB];
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(HFX_WG) void k_class(const ClassArgs a) {
     const double sbra = bra.a != bra.b ? 2.0 : 1.0;
     const int kps = a.nket_list, kfs = a.nket_list * a.knprim;
     unsigned n64 = 0, n32 = 0;
-    for (int s = s0 + (int)threadIdx.x; s < send; s += HFX_WG) {
+    for (int s = s0 + (int)threadIdx.x; s < send; s += E::WGS) {
         const PairInfo ket = a.ket[s];
         double I[NI];
         if (!MIXED || s < split) {
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(HFX_WG) void k_class(const ClassArgs a) {
     }
     if constexpr (MODE == 0) {
         __syncthreads();
-        for (int i = threadIdx.x; i < (NA + NB) * N; i += HFX_WG) {
+        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) {
             const double v = lds[i];
             if (v != 0.0) {
                 const int row = i < NA * N ? bra.bfa + i / N : bra.bfb + (i - NA * N) / N;
@@ -371,9 +374,9 @@ struct ClassKernels {
 
 // Per-class translation unit: evaluator wrapper, the four kernel variants
 // (digestion mode x precision policy), the Schwarz kernel and C lookups.
-#define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_)                                                      \
+#define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_)                                               \
     struct Eval##cid {                                                                                 \
-        static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_;                                   \
+        static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         template <typename R>                                                                          \
         __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
                                                    int kfs, int kps, int nkp, const double* ab,        \

@@ -38,6 +38,10 @@ import sys
 PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 PAIR_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd"]
 CLASSES = [(B, K) for B in range(6) for K in range(B + 1)]
+# Workgroup size per class: 512 lanes where the kernel needs <= 256 VGPRs, so
+# that classes whose LDS rows limit the workgroups per CU still reach 32
+# waves per CU; 256 for the register-heavy classes.
+WG512 = {0, 1, 2, 3, 4, 6, 7, 9, 10}
 
 
 def cart(l):
@@ -254,15 +258,15 @@ def main(out_dir):
             fh.write("\n".join(hdr))
         tu = [f"// Generated by gen_eri.py: kernels of class {cid} ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}).",
               f'#include "eri_class_{cid:02d}.h"', '#include "../eri_impl.h"', "",
-              f"HFX_CLASS_TU({cid}, {fname}, {la}, {lb}, {lc}, {ld})", ""]
+              f"HFX_CLASS_TU({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {512 if cid in WG512 else 256})", ""]
         with open(os.path.join(out_dir, f"eri_class_{cid:02d}.hip"), "w") as fh:
             fh.write("\n".join(tu))
         table.append((cid, B, K, la, lb, lc, ld, g.flops, g.hrr_flops, fname))
     parts = ["// Generated by gen_eri.py: class table.", "#pragma once", "",
-             "struct EriClassInfo { int B, K, la, lb, lc, ld, vrr_flops_per_prim, hrr_flops; };",
+             "struct EriClassInfo { int B, K, la, lb, lc, ld, vrr_flops_per_prim, hrr_flops, wgs; };",
              "static const EriClassInfo kEriClassInfo[21] = {"]
     for (cid, B, K, la, lb, lc, ld, fl, hfl, fname) in table:
-        parts.append(f"  {{{B}, {K}, {la}, {lb}, {lc}, {ld}, {fl}, {hfl}}},  // {fname}")
+        parts.append(f"  {{{B}, {K}, {la}, {lb}, {lc}, {ld}, {fl}, {hfl}, {512 if cid in WG512 else 256}}},  // {fname}")
     parts.append("};")
     parts.append("")
     parts.append("#define HFX_FOR_EACH_CID(X) " + " ".join(f"X({cid})" for cid in range(21)))

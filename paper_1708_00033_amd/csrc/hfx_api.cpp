@@ -52,6 +52,8 @@ static int class_id(int B, int K) { return B * (B + 1) / 2 + K; }           // B
 
 static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
 
+static hfx_status replan(hfx_ctx* c);
+
 // ---- options -----------------------------------------------------------------------
 
 extern "C" hfx_status hfx_default_options(hfx_options* o) {
@@ -107,10 +109,16 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_wket);
     }
     c->ketlists.clear();
+    c->host_bra.clear();
+    c->host_pos.clear();
+    c->host_ket.clear();
+    c->host_kpos.clear();
     for (auto& p : c->plans) {
         dfree(p.d_nket);
         dfree(p.d_split);
         dfree(p.d_tasks);
+        if (p.ev0) (void)hipEventDestroy(p.ev0);
+        if (p.ev1) (void)hipEventDestroy(p.ev1);
     }
     c->plans.clear();
     for (auto& t : c->totals) t = ClassTotals();
@@ -168,10 +176,6 @@ extern "C" void hfx_destroy(hfx_ctx* c) {
     dfree(c->d_dmax);
     dfree(c->d_counters);
     c->d_bad = nullptr;
-    for (int k = 0; k < 21; ++k) {
-        if (c->ev_start[k]) (void)hipEventDestroy(c->ev_start[k]);
-        if (c->ev_stop[k]) (void)hipEventDestroy(c->ev_stop[k]);
-    }
     if (c->blas) rocblas_destroy_handle(c->blas);
     delete c;
 }
@@ -184,15 +188,15 @@ extern "C" hfx_status hfx_configure(hfx_ctx* c, const hfx_options* o) {
     if (s != HFX_OK) return s;
     if (o->device != c->opt.device || o->schwarz_tau != c->opt.schwarz_tau)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "device and schwarz_tau cannot change after hfx_create");
-    const bool replan = o->task_quartets != c->opt.task_quartets;
+    const bool new_plan = o->task_quartets != c->opt.task_quartets;
     c->opt = *o;
-    if (!replan || !c->loaded) {
-        // digestion mode may change without a new plan
-        for (auto& p : c->plans)
-            p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024) ? 0 : 1;
-        return HFX_OK;
+    if (new_plan && c->loaded) {
+        HIPCK(hipSetDevice(c->opt.device));
+        return replan(c);
     }
-    return hfx_fail(c, HFX_ERR_STATE, "task_quartets changed: call hfx_load again");
+    // digestion mode may change without a new plan
+    for (auto& p : c->plans) p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024) ? 0 : 1;
+    return HFX_OK;
 }
 
 // ---- loading ----------------------------------------------------------------------------
@@ -218,7 +222,8 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.K = K;
     P.list = li;
     const double tau = c->opt.schwarz_tau;
-    const int TQ = c->opt.task_quartets;
+    const int TQ = c->tune_tq[P.cid] > 0 ? c->tune_tq[P.cid] : c->opt.task_quartets;
+    const bool stripe = c->tune_stripe[P.cid] >= 0 ? c->tune_stripe[P.cid] != 0 : true;
     std::vector<int> nket(bras.size(), 0);
     int nbra = 0;
     for (size_t r = 0; r < bras.size(); ++r) {
@@ -244,9 +249,40 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     }
     const int nint = ncart(kPairL[B][0]) * ncart(kPairL[B][1]) * ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
     P.integrals = P.quartets * nint;
-    std::vector<int2> tasks;
-    for (int r = 0; r < nbra; ++r)
-        for (int s0 = 0; s0 < nket[r]; s0 += TQ) tasks.push_back(make_int2(r, s0));
+    // Tasks, striped over the 8 XCDs (workgroup i runs on XCD i mod 8, each
+    // with its own L2): a long ket prefix is cut into chunks and chunk j of
+    // every bra goes to the XCD queue j mod 8, so an XCD streams only its
+    // share of each ket list; short prefixes fill the least loaded queue.
+    // Queues are interleaved (task 8k + j = queue j's k-th entry) and padded
+    // with empty tasks (r = -1).
+    const int NX = 8, WGS = hfx_class_wgs(class_id(B, K));
+    std::vector<std::vector<int4>> queue(NX);
+    std::vector<long long> load(NX, 0);
+    for (int r = 0; r < nbra; ++r) {
+        const int n = nket[r];
+        if (stripe && n >= 2 * NX * WGS) {
+            int nch = (n + TQ - 1) / TQ;
+            nch = ((nch + NX - 1) / NX) * NX;
+            int len = (n + nch - 1) / nch;
+            len = ((len + WGS - 1) / WGS) * WGS;
+            for (int j = 0, s0 = 0; s0 < n; ++j, s0 += len) {
+                queue[j % NX].push_back(make_int4(r, s0, std::min(n, s0 + len), 0));
+                load[j % NX] += std::min(len, n - s0);
+            }
+        } else {
+            for (int s0 = 0; s0 < n; s0 += TQ) {
+                const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                queue[q].push_back(make_int4(r, s0, std::min(n, s0 + TQ), 0));
+                load[q] += std::min(TQ, n - s0);
+            }
+        }
+    }
+    size_t qmax = 0;
+    for (auto& q : queue) qmax = std::max(qmax, q.size());
+    std::vector<int4> tasks;
+    tasks.reserve(qmax * NX);
+    for (size_t k = 0; k < qmax; ++k)
+        for (int j = 0; j < NX; ++j) tasks.push_back(k < queue[j].size() ? queue[j][k] : make_int4(-1, 0, 0, 0));
     if (tasks.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many tasks for one launch");
     P.nbra = nbra;
     P.ntask = (int)tasks.size();
@@ -258,7 +294,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     HIPCK(dalloc(&P.d_split, nbra));
     HIPCK(dalloc(&P.d_tasks, tasks.size()));
     HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
-    HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int4), hipMemcpyHostToDevice));
     ClassTotals& T = c->totals[P.cid];
     T.quartets += P.quartets;
     T.integrals += P.integrals;
@@ -266,6 +302,54 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     T.ntask += P.ntask;
     c->plans.push_back(P);
     return HFX_OK;
+}
+
+// (Re)build every launch plan from the stored Q-sorted lists with the
+// current per-class tuning.
+static hfx_status replan(hfx_ctx* c) {
+    for (auto& p : c->plans) {
+        dfree(p.d_nket);
+        dfree(p.d_split);
+        dfree(p.d_tasks);
+        if (p.ev0) (void)hipEventDestroy(p.ev0);
+        if (p.ev1) (void)hipEventDestroy(p.ev1);
+    }
+    c->plans.clear();
+    for (auto& t : c->totals) t = ClassTotals();
+    for (int B = 0; B < 6; ++B)
+        for (size_t li = 0; li < c->ketlists.size(); ++li) {
+            if (c->ketlists[li].K > B) continue;
+            hfx_status s = plan_sub(c, B, (int)li, c->host_bra[B], c->host_pos[B], c->host_ket[li], c->host_kpos[li]);
+            if (s != HFX_OK) return s;
+        }
+    // launch order: largest classes first (sub-launches of a class stay together)
+    static const int order[21] = {0, 1, 2, 6, 7, 3, 8, 9, 4, 10, 11, 13, 12, 5, 15, 16, 14, 18, 17, 19, 20};
+    int rank[21];
+    for (int i = 0; i < 21; ++i) rank[order[i]] = i;
+    std::stable_sort(c->plans.begin(), c->plans.end(),
+                     [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
+    if (c->timing)
+        for (auto& p : c->plans) {
+            HIPCK(hipEventCreate(&p.ev0));
+            HIPCK(hipEventCreate(&p.ev1));
+        }
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartets, int xcd_stripe) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (cid < -1 || cid >= 21) return hfx_fail(c, HFX_ERR_INVALID_ARG, "class index out of range");
+    if (task_quartets != 0 && (task_quartets < 256 || task_quartets % 256 != 0 || task_quartets > (1 << 24)))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be 0 or a multiple of 256 in [256, 2^24]");
+    if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
+    for (int k = 0; k < 21; ++k)
+        if (cid == -1 || cid == k) {
+            c->tune_tq[k] = task_quartets;
+            c->tune_stripe[k] = xcd_stripe;
+        }
+    if (!c->loaded) return HFX_OK;
+    HIPCK(hipSetDevice(c->opt.device));
+    return replan(c);
 }
 
 extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double* xyz, int nshell,
@@ -501,19 +585,13 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
             kpos.push_back(std::move(sp));
         }
     }
-    for (int B = 0; B < 6; ++B)
-        for (size_t li = 0; li < c->ketlists.size(); ++li) {
-            if (c->ketlists[li].K > B) continue;
-            hfx_status s = plan_sub(c, B, (int)li, all[B], pos[B], klist[li], kpos[li]);
-            if (s != HFX_OK) return s;
-        }
-    // launch order: largest classes first (sub-launches of a class stay together)
+    c->host_bra.assign(all.begin(), all.end());
+    c->host_pos = pos;
+    c->host_ket = std::move(klist);
+    c->host_kpos = std::move(kpos);
     {
-        static const int order[21] = {0, 1, 2, 6, 7, 3, 8, 9, 4, 10, 11, 13, 12, 5, 15, 16, 14, 18, 17, 19, 20};
-        int rank[21];
-        for (int i = 0; i < 21; ++i) rank[order[i]] = i;
-        std::stable_sort(c->plans.begin(), c->plans.end(),
-                         [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
+        hfx_status s = replan(c);
+        if (s != HFX_OK) return s;
     }
 
     // ---- one-electron integrals ----
@@ -603,15 +681,15 @@ extern "C" hfx_status hfx_class_counts(const hfx_ctx* c, long long* counts) {
 // ---- kernel timing ---------------------------------------------------------------------
 
 static void collect_timing(hfx_ctx* c) {
-    for (int k = 0; k < 21; ++k)
-        if (c->ev_pending[k]) {
-            (void)hipEventSynchronize(c->ev_stop[k]);
+    for (auto& p : c->plans)
+        if (p.pending) {
+            (void)hipEventSynchronize(p.ev1);
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]) == hipSuccess) {
-                c->class_ms[k] += ms;
-                c->class_launches[k] += 1;
+            if (hipEventElapsedTime(&ms, p.ev0, p.ev1) == hipSuccess) {
+                p.ms += ms;
+                p.launches += 1;
             }
-            c->ev_pending[k] = false;
+            p.pending = false;
         }
 }
 
@@ -619,12 +697,12 @@ extern "C" hfx_status hfx_kernel_timing(hfx_ctx* c, int enable) {
     if (!c) return HFX_ERR_INVALID_ARG;
     collect_timing(c);
     c->timing = enable != 0;
-    for (int k = 0; k < 21; ++k) {
-        c->class_ms[k] = 0.0;
-        c->class_launches[k] = 0;
-        if (c->timing && !c->ev_start[k]) {
-            HIPCK(hipEventCreate(&c->ev_start[k]));
-            HIPCK(hipEventCreate(&c->ev_stop[k]));
+    for (auto& p : c->plans) {
+        p.ms = 0.0;
+        p.launches = 0;
+        if (c->timing && !p.ev0) {
+            HIPCK(hipEventCreate(&p.ev0));
+            HIPCK(hipEventCreate(&p.ev1));
         }
     }
     return HFX_OK;
@@ -633,17 +711,46 @@ extern "C" hfx_status hfx_kernel_timing(hfx_ctx* c, int enable) {
 extern "C" hfx_status hfx_kernel_times(hfx_ctx* c, double* ms, long long* launches) {
     if (!c) return HFX_ERR_INVALID_ARG;
     collect_timing(c);
-    for (int k = 0; k < 21; ++k) {
-        if (ms) ms[k] = c->class_ms[k];
-        if (launches) launches[k] = c->class_launches[k];
+    double m[21] = {0};
+    long long l[21] = {0};
+    for (auto& p : c->plans) {
+        m[p.cid] += p.ms;
+        l[p.cid] = std::max(l[p.cid], p.launches);
     }
+    for (int k = 0; k < 21; ++k) {
+        if (ms) ms[k] = m[k];
+        if (launches) launches[k] = l[k];
+    }
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_plan_count(const hfx_ctx* c, int* n) {
+    if (!c || !n) return HFX_ERR_INVALID_ARG;
+    *n = (int)c->plans.size();
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* ms) {
+    if (!c || !info || i < 0 || i >= (int)c->plans.size()) return HFX_ERR_INVALID_ARG;
+    collect_timing(c);
+    const SubPlan& p = c->plans[i];
+    const KetList& KL = c->ketlists[p.list];
+    info[0] = p.cid;
+    info[1] = KL.kp;
+    info[2] = p.ntask;
+    info[3] = p.quartets;
+    info[4] = p.prim;
+    info[5] = p.integrals;
+    info[6] = p.launches;
+    info[7] = p.mode;
+    if (ms) *ms = p.ms;
     return HFX_OK;
 }
 
 // ---- the Fock build -------------------------------------------------------------------
 
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
-                              hipStream_t st, hfx_fock_stats* stats) {
+                              hipStream_t st, hfx_fock_stats* stats, int shard, int nshards) {
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "build: nothing loaded");
     const int n = c->nbf;
     const size_t nn = (size_t)n * n;
@@ -659,8 +766,6 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
         const int cid = P.cid;
-        const bool first = pi == 0 || c->plans[pi - 1].cid != cid;
-        const bool last = pi + 1 == c->plans.size() || c->plans[pi + 1].cid != cid;
         const bool mx = mixed && !P.fp64_only;
         if (mx)
             HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, KL.n, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
@@ -685,11 +790,13 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.task_quartets = c->opt.task_quartets;
         a.cj = cj;
         a.ck = ck;
-        if (c->timing && first) HIPCK(hipEventRecord(c->ev_start[cid], st));
+        a.shard = shard;
+        a.nshards = nshards;
+        if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
         HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, P.ntask, P.mode == 0 ? P.lds_bytes : 0, st, &a));
-        if (c->timing && last) {
-            HIPCK(hipEventRecord(c->ev_stop[cid], st));
-            c->ev_pending[cid] = true;
+        if (c->timing && P.ev1) {
+            HIPCK(hipEventRecord(P.ev1, st));
+            P.pending = true;
         }
     }
     for (auto& KL : c->ketlists)
@@ -726,7 +833,7 @@ extern "C" hfx_status hfx_build_fock_dev(hfx_ctx* c, const double* dD, double* d
                                          hfx_fock_stats* stats) {
     if (!c || !dD || !dF) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     HIPCK(hipSetDevice(c->opt.device));
-    return hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, (hipStream_t)stream, stats);
+    return hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, (hipStream_t)stream, stats, 0, 1);
 }
 
 extern "C" hfx_status hfx_build_2e_dev(hfx_ctx* c, const double* dD, double cj, double ck, double* dG, void* stream,
@@ -734,7 +841,16 @@ extern "C" hfx_status hfx_build_2e_dev(hfx_ctx* c, const double* dD, double cj, 
     if (!c || !dD || !dG) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     if (!std::isfinite(cj) || !std::isfinite(ck)) return hfx_fail(c, HFX_ERR_INVALID_ARG, "non-finite cj/ck");
     HIPCK(hipSetDevice(c->opt.device));
-    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, stats);
+    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, stats, 0, 1);
+}
+
+extern "C" hfx_status hfx_build_2e_shard_dev(hfx_ctx* c, const double* dD, double cj, double ck, int shard,
+                                             int nshards, double* dG, void* stream) {
+    if (!c || !dD || !dG) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    if (nshards < 1 || shard < 0 || shard >= nshards) return hfx_fail(c, HFX_ERR_INVALID_ARG, "bad shard");
+    if (!std::isfinite(cj) || !std::isfinite(ck)) return hfx_fail(c, HFX_ERR_INVALID_ARG, "non-finite cj/ck");
+    HIPCK(hipSetDevice(c->opt.device));
+    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, nullptr, shard, nshards);
 }
 
 extern "C" hfx_status hfx_build_fock(hfx_ctx* c, const double* D, double* F, hfx_fock_stats* stats) {
@@ -747,7 +863,7 @@ extern "C" hfx_status hfx_build_fock(hfx_ctx* c, const double* D, double* F, hfx
     if (!c->d_tmpF) HIPCK(dalloc(&c->d_tmpF, nn));
     HIPCK(hipMemcpy(c->d_tmpD, D, nn * 8, hipMemcpyHostToDevice));
     hfx_fock_stats local;
-    hfx_status s = hfx_build_internal(c, c->d_tmpD, 2.0, 1.0, c->d_H, c->d_tmpF, 0, stats ? stats : &local);
+    hfx_status s = hfx_build_internal(c, c->d_tmpD, 2.0, 1.0, c->d_H, c->d_tmpF, 0, stats ? stats : &local, 0, 1);
     if (s != HFX_OK) return s;
     HIPCK(hipMemcpy(F, c->d_tmpF, nn * 8, hipMemcpyDeviceToHost));
     return HFX_OK;

@@ -33,10 +33,15 @@ struct SubPlan {
     int ntask = 0;
     int* d_nket = nullptr;
     int* d_split = nullptr;
-    int2* d_tasks = nullptr;
+    int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;
     int mode = 0;             // digestion actually used (LDS may fall back to global)
+    // timing (when enabled): events around this launch, summed milliseconds
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool pending = false;
+    double ms = 0.0;
+    long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
 };
 
@@ -66,6 +71,12 @@ struct hfx_ctx {
     std::vector<KetList> ketlists;      // per pair class and primitive count (kets)
     std::vector<SubPlan> plans;         // launches, grouped by class id
     ClassTotals totals[21];
+    // host copies of the Q-sorted lists (for re-planning) and per-class tuning
+    std::vector<std::vector<PairInfo>> host_bra, host_ket;
+    std::vector<std::vector<double>> host_pos, host_kpos;
+    int tune_tq[21] = {0};                       // 0: opt.task_quartets
+    int tune_stripe[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                           -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: default (striped)
     std::vector<double> Qshell;         // nshell x nshell Schwarz bounds (host)
     double* d_boys64 = nullptr;
     float* d_boys32 = nullptr;
@@ -82,10 +93,6 @@ struct hfx_ctx {
     rocblas_handle blas = nullptr;
     // timing
     bool timing = false;
-    hipEvent_t ev_start[21] = {nullptr}, ev_stop[21] = {nullptr};
-    bool ev_pending[21] = {false};
-    double class_ms[21] = {0};
-    long long class_launches[21] = {0};
     hipStream_t last_stream = nullptr;
 };
 
@@ -93,7 +100,7 @@ struct hfx_ctx {
 hfx_status hfx_fail(hfx_ctx* c, hfx_status s, const std::string& msg);
 hfx_status hfx_hip_check(hfx_ctx* c, hipError_t e, const char* what);
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
-                              hipStream_t st, hfx_fock_stats* stats);
+                              hipStream_t st, hfx_fock_stats* stats, int shard, int nshards);
 
 // implemented in misc_kernels.hip
 extern "C" {
@@ -120,6 +127,7 @@ hipError_t hfx_weight_cols(const double* C, const double* occ, int n, int nk, do
 // eri_dispatch.hip
 hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_bytes, hipStream_t stream,
                             const ClassArgs* args);
+int hfx_class_wgs(int cid);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               const double* cscale, double* Q, hipStream_t stream);
 }

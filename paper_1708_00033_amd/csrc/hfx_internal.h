@@ -43,7 +43,7 @@ struct ClassArgs {
     int nket_list, knprim;
     const int* __restrict__ nket;       // per bra: number of kets (screened prefix)
     const int* __restrict__ split;      // per bra: kets below this index use FP64 (nullptr: all)
-    const int2* __restrict__ tasks;     // (bra index, first ket) per workgroup
+    const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0) per workgroup; bra -1: empty
     const double* __restrict__ boys64;
     const float* __restrict__ boys32;
     const double* __restrict__ D;       // component-scaled density D'
@@ -52,6 +52,7 @@ struct ClassArgs {
     unsigned long long* __restrict__ counters;  // [0] FP64 quartets, [1] FP32 quartets
     int nbf;
     int task_quartets;
+    int shard, nshards;                 // only bras with r % nshards == shard (1 shard: all)
     double cj, ck;                      // W_ab += cj*2 g D_cd ; W_ac -= ck g D_bd
 };
 

@@ -248,7 +248,7 @@ static hfx_status scf_core(hfx_ctx* c, const hfx_scf_options& o, double occ_pair
     out.converged = false;
     for (int it = 1; it <= o.max_iter; ++it) {
         auto tf = std::chrono::steady_clock::now();
-        hfx_status s = hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, F.p, st, nullptr);
+        hfx_status s = hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, F.p, st, nullptr, 0, 1);
         if (s != HFX_OK) return s;
         HIPCK(hipStreamSynchronize(st));
         out.t_fock += std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();

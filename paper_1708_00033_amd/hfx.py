@@ -89,11 +89,16 @@ _sigs = {
     "hfx_build_fock_dev": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_build_2e_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                           C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_build_2e_shard_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p,
+                                C.c_void_p], C.c_int),
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
     "hfx_class_counts": ([_ctx_p, C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_set_class_tuning": ([_ctx_p, C.c_int, C.c_int, C.c_int], C.c_int),
     "hfx_kernel_timing": ([_ctx_p, C.c_int], C.c_int),
     "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_plan_count": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
+    "hfx_plan_info": ([_ctx_p, C.c_int, C.POINTER(C.c_longlong), _dp], C.c_int),
     "hfx_last_error": ([_ctx_p], C.c_char_p),
     "hfx_destroy": ([_ctx_p], None),
 }
@@ -213,6 +218,11 @@ class Context:
                                      C.byref(st) if stats else None))
         return st
 
+    def build_2e_shard_dev(self, dD_ptr: int, cj: float, ck: float, shard: int, nshards: int, dG_ptr: int,
+                           stream: int = 0):
+        self._check(hfx_build_2e_shard_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, shard, nshards, C.c_void_p(dG_ptr),
+                                           C.c_void_p(stream)))
+
     def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, **kw):
         o = default_scf_options(**kw)
         keep = None
@@ -235,6 +245,15 @@ class Context:
             out["C"] = Cm.reshape(-1)[: n * nmo].reshape(n, nmo)
         return out
 
+    def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1):
+        self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe))
+
+    def apply_tuning(self, table: dict):
+        """table: {class index or name: {"task_quartets": int, "xcd_stripe": int}}"""
+        for k, v in table.items():
+            cid = CLASS_NAMES.index(k) if isinstance(k, str) and not k.isdigit() else int(k)
+            self.set_class_tuning(cid, int(v.get("task_quartets", 0)), int(v.get("xcd_stripe", -1)))
+
     def class_counts(self) -> np.ndarray:
         a = np.zeros(21 * 4, dtype=np.int64)
         self._check(hfx_class_counts(self.ptr, a.ctypes.data_as(C.POINTER(C.c_longlong))))
@@ -242,6 +261,20 @@ class Context:
 
     def kernel_timing(self, enable: bool = True):
         self._check(hfx_kernel_timing(self.ptr, int(enable)))
+
+    def plans(self):
+        """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, ms)."""
+        n = C.c_int()
+        self._check(hfx_plan_count(self.ptr, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            info = (C.c_longlong * 8)()
+            ms = C.c_double()
+            self._check(hfx_plan_info(self.ptr, i, info, C.byref(ms)))
+            out.append(dict(cls=int(info[0]), ket_nprim=int(info[1]), tasks=int(info[2]), quartets=int(info[3]),
+                            prim=int(info[4]), integrals=int(info[5]), launches=int(info[6]), mode=int(info[7]),
+                            ms=ms.value))
+        return out
 
     def kernel_times(self):
         ms = np.zeros(21)
