@@ -113,10 +113,26 @@ hfx_status hfx_create(const hfx_options *opt, hfx_ctx **out);
 hfx_status hfx_load(hfx_ctx *ctx, int natom, const int *Z, const double *xyz_bohr, int nshell,
                     const hfx_shell *shells, int charge);
 
-/* Basis size, doubly occupied orbitals, shells. */
+/* Load a batch of nmol independent molecules (one context, one launch per
+ * quartet class for all of them).  Molecule m has natom[m] atoms and
+ * nshell[m] shells; Z, xyz_bohr and shells are the concatenations in molecule
+ * order, each shell's atom index counting within its molecule; charge may be
+ * NULL (all neutral).  Pairs and quartets never mix molecules.  All matrices
+ * of a batch (D, F, S, H) are ragged: molecule m's nbf_m x nbf_m block at
+ * element offset offset[m] (hfx_batch_layout).  hfx_load is the nmol = 1 case. */
+hfx_status hfx_load_batch(hfx_ctx *ctx, int nmol, const int *natom, const int *Z, const double *xyz_bohr,
+                          const int *nshell, const hfx_shell *shells, const int *charge);
+
+/* Ragged layout of a loaded batch: nbf[nmol], nocc[nmol], offset[nmol] (any
+ * may be NULL) and the total element count. */
+hfx_status hfx_batch_layout(const hfx_ctx *ctx, int *nmol, int *nbf, int *nocc, long long *offset,
+                            long long *total);
+
+/* Basis size, doubly occupied orbitals, shells (totals over a batch). */
 hfx_status hfx_dims(const hfx_ctx *ctx, int *nbf, int *nocc, int *nshell);
 
-/* Host copies of S and H (nbf x nbf) and E_nuc; any pointer may be NULL. */
+/* Host copies of S and H (ragged layout; nbf x nbf for one molecule) and the
+ * total E_nuc; any pointer may be NULL. */
 hfx_status hfx_core(hfx_ctx *ctx, double *S, double *H, double *e_nuc);
 
 /* Schwarz bounds as an nshell x nshell host matrix. */
@@ -135,6 +151,13 @@ hfx_status hfx_build_fock_dev(hfx_ctx *ctx, const double *dD, double *dF, void *
  * ck=1 gives F - H; cj=1, ck=0 gives J; cj=0, ck=-1 gives K. */
 hfx_status hfx_build_2e_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, double *dG,
                             void *stream, hfx_fock_stats *stats);
+
+/* Capture one Fock build dF = F(dD) on a non-null stream into a HIP graph
+ * (an eager build runs first), and replay it.  The graph keeps dD, dF and
+ * the context's buffers; re-capture after hfx_load, hfx_configure or
+ * hfx_set_class_tuning. */
+hfx_status hfx_graph_capture(hfx_ctx *ctx, const double *dD, double *dF, void *stream);
+hfx_status hfx_graph_launch(hfx_ctx *ctx, void *stream);
 
 /* One GPU's share of a multi-GPU build: dG = cj J - ck K restricted to the
  * bra shell pairs r with r % nshards == shard (r = position in each class's

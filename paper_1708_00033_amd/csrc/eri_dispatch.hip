@@ -29,10 +29,9 @@ extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, 
 extern "C" int hfx_class_wgs(int cid) { return kEriClassInfo[cid].wgs; }
 
 extern "C" hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim,
-                                         const double* boys, const double* cscale, double* Q,
-                                         hipStream_t stream) {
+                                         const double* boys, double* Q, hipStream_t stream) {
     if (npairs <= 0) return hipSuccess;
     const void* fn = kSchwarzLookup[cid]();
-    void* kargs[] = {(void*)&pairs, (void*)&npairs, (void*)&prim, (void*)&boys, (void*)&cscale, (void*)&Q};
+    void* kargs[] = {(void*)&pairs, (void*)&npairs, (void*)&prim, (void*)&boys, (void*)&Q};
     return hipLaunchKernel(fn, dim3((npairs + HFX_WG - 1) / HFX_WG), dim3(HFX_WG), kargs, 0, stream);
 }

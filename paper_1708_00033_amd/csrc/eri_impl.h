@@ -41,10 +41,7 @@ __device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, in
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                        const PairInfo& ket, int spos, const double* dab, double* jab, double* FI,
-                                       double* FJ) {
-    const int N = a.nbf;
-    const double* __restrict__ D = a.D;
-    double* __restrict__ W = a.W;
+                                       double* FJ, const double* __restrict__ D, double* __restrict__ W, int N) {
     const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
@@ -160,10 +157,8 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_rolled(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                               const PairInfo& ket, const double* dab, double* jab, double* FI,
-                                              double* FJ) {
-    const int N = a.nbf;
-    const double* __restrict__ D = a.D;
-    double* __restrict__ W = a.W;
+                                              double* FJ, const double* __restrict__ D, double* __restrict__ W,
+                                              int N) {
     const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
 #pragma unroll 1
@@ -231,6 +226,72 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
         }
 }
 
+// Digestion of one pass of a large class: the integrals (a_k b | c d) of the
+// k-th Cartesian component of shell a, all b, c, d (I laid out [b][c][d]).
+// Same updates as digest(), restricted to mu = k; rolled loops (the block
+// lives in scratch, 8 NB NC ND bytes per lane).
+template <int NA, int NB, int NC, int ND, int MODE>
+__device__ __forceinline__ void digest_pass(int k, const double* I, double g, const ClassArgs& a,
+                                            const PairInfo& bra, const PairInfo& ket, int spos, const double* dab,
+                                            double* jab, double* FI, double* FJ, const double* __restrict__ D,
+                                            double* __restrict__ W, int N) {
+    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+    const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
+    constexpr int NCD = NC * ND;
+#pragma unroll 1
+    for (int n = 0; n < NB; ++n) {   // J, bra block (mu = k)
+        double v = 0.0;
+#pragma unroll 1
+        for (int ls = 0; ls < NCD; ++ls) v += I[n * NCD + ls] * D[(size_t)(fc + ls / ND) * N + fd + ls % ND];
+        jab[k * NB + n] += g * v;
+    }
+#pragma unroll 1
+    for (int ls = 0; ls < NCD; ++ls) {   // J, ket block
+        double v = 0.0;
+#pragma unroll 1
+        for (int n = 0; n < NB; ++n) v += I[n * NCD + ls] * dab[k * NB + n];
+        if constexpr (MODE == 0)
+            atomicAdd(a.wket + (size_t)ls * a.nket_list + spos, cj2 * v);
+        else
+            atomicAdd(W + (size_t)(fc + ls / ND) * N + fd + ls % ND, cj2 * v);
+    }
+#pragma unroll 1
+    for (int l = 0; l < NC; ++l) {   // K: (k, c_l) -= sum_{n s} I D_bd
+        double v = 0.0;
+#pragma unroll 1
+        for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+            for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
+        row_add<MODE>(FI + k * N, W, fa + k, fc + l, N, ckg * v);
+    }
+#pragma unroll 1
+    for (int s = 0; s < ND; ++s) {   // K: (k, d_s) -= sum_{n l} I D_bc
+        double v = 0.0;
+#pragma unroll 1
+        for (int n = 0; n < NB; ++n)
+#pragma unroll 1
+            for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
+        row_add<MODE>(FI + k * N, W, fa + k, fd + s, N, ckg * v);
+    }
+#pragma unroll 1
+    for (int n = 0; n < NB; ++n) {
+#pragma unroll 1
+        for (int s = 0; s < ND; ++s) {   // K: (b_n, d_s) -= sum_l I D_ac
+            double v = 0.0;
+#pragma unroll 1
+            for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fc + l];
+            row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v);
+        }
+#pragma unroll 1
+        for (int l = 0; l < NC; ++l) {   // K: (b_n, c_l) -= sum_s I D_ad
+            double v = 0.0;
+#pragma unroll 1
+            for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fd + s];
+            row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v);
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -244,15 +305,17 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     extern __shared__ double lds[];
-    const int N = a.nbf;
     const int4 task = a.tasks[blockIdx.x];
     const int r = task.x, s0 = task.y;
     if (r < 0) return;                                        // padding task (XCD striping)
     if (a.nshards > 1 && r % a.nshards != a.shard) return;   // whole workgroup: uniform exit
     const PairInfo bra = a.bra[r];
-    const int nk = a.nket[r];
-    const int send = min(task.z, nk);
-    const int split = MIXED ? a.split[r] : nk;
+    // the bra's molecule: its blocks of D' and W, leading dimension ld
+    const int N = bra.ld;
+    const double* __restrict__ Dm = a.D + a.moff[bra.mol];
+    double* __restrict__ Wm = a.W + a.moff[bra.mol];
+    const int send = task.z;                                  // kets [s0, send) of the list
+    const int split = MIXED ? a.split[r] : send;
     double* FI = lds;
     double* FJ = lds + NA * N;
     if constexpr (MODE == 0) {
@@ -264,7 +327,7 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     for (int m = 0; m < NA; ++m)
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            dab[m * NB + n] = a.D[(size_t)(bra.bfa + m) * N + bra.bfb + n];
+            dab[m * NB + n] = Dm[(size_t)(bra.bfa + m) * N + bra.bfb + n];
             jab[m * NB + n] = 0.0;
         }
     const double sbra = bra.a != bra.b ? 2.0 : 1.0;
@@ -272,6 +335,19 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     unsigned n64 = 0, n32 = 0;
     for (int s = s0 + (int)threadIdx.x; s < send; s += E::WGS) {
         const PairInfo ket = a.ket[s];
+        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((ket.a == bra.a && ket.b == bra.b) ? 1.0 : 2.0);
+        if constexpr (E::PASSES) {
+            // one Cartesian component of shell a per pass: a small block per pass
+            double Ik[NB * NC * ND];
+#pragma unroll 1
+            for (int k = 0; k < NA; ++k) {
+                E::template run_pass<double>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim,
+                                             bra.AB, ket.AB, a.boys64, Ik);
+                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N);
+            }
+            ++n64;
+            continue;
+        }
         double I[NI];
         if (!MIXED || s < split) {
             E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
@@ -285,11 +361,10 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
         }
-        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((ket.a == bra.a && ket.b == bra.b) ? 1.0 : 2.0);
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ);
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ, Dm, Wm, N);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ);
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N);
     }
     // bra J block: wave reduction, one add per wave
     const int lane = threadIdx.x & 63;
@@ -298,7 +373,7 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
         const double v = wave_sum(jab[mn]);
         if (lane == 0) {
             const int m = mn / NB, n = mn % NB;
-            row_add<MODE>(FI + m * N, a.W, bra.bfa + m, bra.bfb + n, N, 2.0 * a.cj * v);
+            row_add<MODE>(FI + m * N, Wm, bra.bfa + m, bra.bfb + n, N, 2.0 * a.cj * v);
         }
     }
     // quartet counters (one atomic per wave)
@@ -317,7 +392,7 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
             if (v != 0.0) {
                 const int row = i < NA * N ? bra.bfa + i / N : bra.bfb + (i - NA * N) / N;
                 const int col = i < NA * N ? i % N : (i - NA * N) % N;
-                atomicAdd(a.W + (size_t)row * N + col, v);
+                atomicAdd(Wm + (size_t)row * N + col, v);
             }
         }
     }
@@ -325,11 +400,15 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
 
 // Schwarz bound of every pair of one pair class: Q = sqrt(max (mn|mn)) with
 // the component normalisation s_m s_n applied (always FP64).
+// 1/sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!) of Cartesian component c of shell l.
+__device__ __forceinline__ double comp_scale(int l, int c) {
+    return (l == 2 && (c == 0 || c == 3 || c == 5)) ? 0.57735026918962576451 : 1.0;
+}
+
 template <class E>
 __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__ pairs, int npairs,
                                                      const PrimPair* __restrict__ prim,
-                                                     const double* __restrict__ boys,
-                                                     const double* __restrict__ cscale, double* __restrict__ Q) {
+                                                     const double* __restrict__ boys, double* __restrict__ Q) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB);
     const int i = blockIdx.x * HFX_WG + threadIdx.x;
     if (i >= npairs) return;
@@ -343,7 +422,7 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
     for (int m = 0; m < NA; ++m)
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            const double s = cscale[pr.bfa + m] * cscale[pr.bfb + n];
+            const double s = comp_scale(E::LA, m) * comp_scale(E::LB, n);
             const double v = I[(m * NB + n) * NA * NB + m * NB + n] * s * s;
             mx = v > mx ? v : mx;
         }
@@ -377,12 +456,38 @@ struct ClassKernels {
 #define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_)                                               \
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
+        static constexpr bool PASSES = false;                                                          \
         template <typename R>                                                                          \
         __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
                                                    int kfs, int kps, int nkp, const double* ab,        \
                                                    const double* cd, const R* tab, R* out) {           \
             fname<R>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),   \
                      R(cd[2]), tab, out);                                                              \
+        }                                                                                              \
+    };                                                                                                 \
+    extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \
+    extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }
+
+// Per-class translation unit of a large class: the full evaluator (Schwarz
+// bounds) plus the per-component passes used by the class kernels.
+#define HFX_CLASS_TU_PASSES(cid, fname, la_, lb_, lc_, ld_, wgs_)                                        \
+    struct Eval##cid {                                                                                 \
+        static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
+        static constexpr bool PASSES = true;                                                           \
+        template <typename R>                                                                          \
+        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
+                                                   int kfs, int kps, int nkp, const double* ab,        \
+                                                   const double* cd, const R* tab, R* out) {           \
+            fname<R>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),   \
+                     R(cd[2]), tab, out);                                                              \
+        }                                                                                              \
+        template <typename R>                                                                          \
+        __device__ __forceinline__ static void run_pass(int k, const PrimPair* bp, int nbp,            \
+                                                        const double* kq0, int kfs, int kps, int nkp,  \
+                                                        const double* ab, const double* cd,            \
+                                                        const R* tab, R* out) {                        \
+            fname##_pass<R>(k, bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),   \
+                            R(cd[1]), R(cd[2]), tab, out);                                             \
         }                                                                                              \
     };                                                                                                 \
     extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \

@@ -126,13 +126,68 @@ class ClassGen:
         return es, fs
 
     # ---- horizontal recurrences (after contraction) ----
-    def emit(self, fname):
-        es, fs = self.targets()
+    def emit(self, fname, a_sel=None):
+        """Straight-line evaluator.  a_sel = k restricts the outputs to the
+        k-th Cartesian component of shell a (all b, c, d): a pass of a large
+        class, with only the recurrence nodes that this pass needs."""
         acc_name = {}
-        for e in es:
-            for f in fs:
-                acc_name[(e, f)] = f"c_{len(acc_name)}"
-                self.vrr(e, f, 0)
+        hnodes = {}
+        hcode = []
+        nh = [0]
+        hfl = [0]
+
+        def hb(a, b, f):
+            key = (a, b, f)
+            if key in hnodes:
+                return hnodes[key]
+            if sum(b) == 0:
+                if (a, f) not in acc_name:
+                    acc_name[(a, f)] = f"c_{len(acc_name)}"
+                hnodes[key] = acc_name[(a, f)]
+                return hnodes[key]
+            i = direction(b)
+            b1 = sub(b, i)
+            x1 = hb(add(a, i), b1, f)
+            x2 = hb(a, b1, f)
+            name = f"h{nh[0]}"
+            nh[0] += 1
+            hfl[0] += 2
+            hcode.append(f"  const R {name} = {x1} + AB{i} * {x2};")
+            hnodes[key] = name
+            return name
+
+        knodes = {}
+
+        def hk(a, b, c, d):
+            key = (a, b, c, d)
+            if key in knodes:
+                return knodes[key]
+            if sum(d) == 0:
+                knodes[key] = hb(a, b, c)
+                return knodes[key]
+            i = direction(d)
+            d1 = sub(d, i)
+            x1 = hk(a, b, add(c, i), d1)
+            x2 = hk(a, b, c, d1)
+            name = f"h{nh[0]}"
+            nh[0] += 1
+            hfl[0] += 2
+            hcode.append(f"  const R {name} = {x1} + CD{i} * {x2};")
+            knodes[key] = name
+            return name
+
+        outs = []
+        idx = 0
+        alist = cart(self.la) if a_sel is None else [cart(self.la)[a_sel]]
+        for a in alist:
+            for b in cart(self.lb):
+                for c in cart(self.lc):
+                    for d in cart(self.ld):
+                        outs.append(f"  out[{idx}] = {hk(a, b, c, d)};")
+                        idx += 1
+        # vertical recurrence for exactly the accumulators the transfers use
+        for (e, f) in acc_name:
+            self.vrr(e, f, 0)
         lines = []
         L = self.L
         lines.append(f"template <typename R>\n__device__ __forceinline__ void {fname}(")
@@ -181,64 +236,17 @@ class ClassGen:
             lines.append(f"      {a} += {self.vrr_nodes[(e, f, 0)]};")
         lines.append("    }")
         lines.append("  }")
-        # bra HRR on the contracted [e0|f0]
-        hnodes = {}
-        hcode = []
-        nh = [0]
-        hfl = [0]
-
-        def hb(a, b, f):
-            key = (a, b, f)
-            if key in hnodes:
-                return hnodes[key]
-            if sum(b) == 0:
-                hnodes[key] = acc_name[(a, f)]
-                return hnodes[key]
-            i = direction(b)
-            b1 = sub(b, i)
-            x1 = hb(add(a, i), b1, f)
-            x2 = hb(a, b1, f)
-            name = f"h{nh[0]}"
-            nh[0] += 1
-            hfl[0] += 2
-            hcode.append(f"  const R {name} = {x1} + AB{i} * {x2};")
-            hnodes[key] = name
-            return name
-
-        knodes = {}
-
-        def hk(a, b, c, d):
-            key = (a, b, c, d)
-            if key in knodes:
-                return knodes[key]
-            if sum(d) == 0:
-                knodes[key] = hb(a, b, c)
-                return knodes[key]
-            i = direction(d)
-            d1 = sub(d, i)
-            x1 = hk(a, b, add(c, i), d1)
-            x2 = hk(a, b, c, d1)
-            name = f"h{nh[0]}"
-            nh[0] += 1
-            hfl[0] += 2
-            hcode.append(f"  const R {name} = {x1} + CD{i} * {x2};")
-            knodes[key] = name
-            return name
-
-        outs = []
-        idx = 0
-        for a in cart(self.la):
-            for b in cart(self.lb):
-                for c in cart(self.lc):
-                    for d in cart(self.ld):
-                        outs.append(f"  out[{idx}] = {hk(a, b, c, d)};")
-                        idx += 1
         lines.append("  (void)AB0; (void)AB1; (void)AB2; (void)CD0; (void)CD1; (void)CD2;")
         lines.extend(hcode)
         lines.extend(outs)
         lines.append("}")
         self.hrr_flops = hfl[0]
         return "\n".join(lines)
+
+
+# Classes whose whole integral block is too large for registers are also
+# emitted as passes, one per Cartesian component of shell a.
+PASS_CLASSES = {19, 20}
 
 
 def main(out_dir):
@@ -251,14 +259,29 @@ def main(out_dir):
         g = ClassGen(la, lb, lc, ld)
         fname = f"eri_{PAIR_NAMES[B]}_{PAIR_NAMES[K]}"
         body = g.emit(fname)
+        extra = []
+        if cid in PASS_CLASSES:
+            for k in range(ncart(la)):
+                extra.append(ClassGen(la, lb, lc, ld).emit(f"{fname}_p{k}", a_sel=k))
+            sw = ["template <typename R>",
+                  f"__device__ __forceinline__ void {fname}_pass(int k, const PrimPair* __restrict__ bp, int nbp,",
+                  "    const double* __restrict__ kq0, int kfs, int kps, int nkp, const R AB0, const R AB1,",
+                  "    const R AB2, const R CD0, const R CD1, const R CD2, const R* __restrict__ boys_tab,",
+                  "    R* __restrict__ out) {", "  switch (k) {"]
+            for k in range(ncart(la)):
+                sw.append(f"    case {k}: {fname}_p{k}<R>(bp, nbp, kq0, kfs, kps, nkp, AB0, AB1, AB2, CD0, CD1, CD2, "
+                          "boys_tab, out); break;")
+            sw += ["    default: break;", "  }", "}"]
+            extra.append("\n".join(sw))
         hdr = ["// Generated by gen_eri.py: Obara-Saika / Head-Gordon-Pople evaluator.",
                f"// class {cid}: ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}), L = {g.L}", "#pragma once",
-               '#include "../hfx_internal.h"', "", body, ""]
+               '#include "../hfx_internal.h"', "", body, ""] + extra + [""]
         with open(os.path.join(out_dir, f"eri_class_{cid:02d}.h"), "w") as fh:
             fh.write("\n".join(hdr))
+        macro = "HFX_CLASS_TU_PASSES" if cid in PASS_CLASSES else "HFX_CLASS_TU"
         tu = [f"// Generated by gen_eri.py: kernels of class {cid} ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}).",
               f'#include "eri_class_{cid:02d}.h"', '#include "../eri_impl.h"', "",
-              f"HFX_CLASS_TU({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {512 if cid in WG512 else 256})", ""]
+              f"{macro}({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {512 if cid in WG512 else 256})", ""]
         with open(os.path.join(out_dir, f"eri_class_{cid:02d}.hip"), "w") as fh:
             fh.write("\n".join(tu))
         table.append((cid, B, K, la, lb, lc, ld, g.flops, g.hrr_flops, fname))

@@ -97,6 +97,10 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
 // ---- lifetime ------------------------------------------------------------------------
 
 static void release_system(hfx_ctx* c) {
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
     dfree(c->d_prim);
     for (int k = 0; k < 6; ++k) {
         dfree(c->d_pairs[k]);
@@ -115,6 +119,7 @@ static void release_system(hfx_ctx* c) {
     c->host_kpos.clear();
     for (auto& p : c->plans) {
         dfree(p.d_nket);
+        dfree(p.d_kseg);
         dfree(p.d_split);
         dfree(p.d_tasks);
         if (p.ev0) (void)hipEventDestroy(p.ev0);
@@ -123,6 +128,10 @@ static void release_system(hfx_ctx* c) {
     c->plans.clear();
     for (auto& t : c->totals) t = ClassTotals();
     dfree(c->d_cscale);
+    dfree(c->d_moff);
+    dfree(c->d_mdim);
+    dfree(c->d_mboff);
+    c->kseg.clear();
     dfree(c->d_S);
     dfree(c->d_H);
     dfree(c->d_W);
@@ -224,26 +233,30 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     const double tau = c->opt.schwarz_tau;
     const int TQ = c->tune_tq[P.cid] > 0 ? c->tune_tq[P.cid] : c->opt.task_quartets;
     const bool stripe = c->tune_stripe[P.cid] >= 0 ? c->tune_stripe[P.cid] != 0 : true;
+    // bra r (molecule m) meets the kets of its own molecule: [seg[m], seg[m+1])
+    const std::vector<int>& seg = c->kseg[li];
     std::vector<int> nket(bras.size(), 0);
-    int nbra = 0;
+    std::vector<int2> kseg(bras.size(), make_int2(0, 0));
+    const int nbra = (int)bras.size();
     for (size_t r = 0; r < bras.size(); ++r) {
         const double qr = bras[r].Q;
-        size_t lo = 0, hi = kets.size();   // kets with Q_s Q_r >= tau: a prefix
+        const int kb = seg[bras[r].mol], ke = seg[bras[r].mol + 1];
+        int lo = kb, hi = ke;   // kets with Q_s Q_r >= tau: a prefix of the segment
         while (lo < hi) {
-            size_t mid = (lo + hi) / 2;
+            const int mid = (lo + hi) / 2;
             if (kets[mid].Q * qr >= tau) lo = mid + 1; else hi = mid;
         }
-        size_t n = lo;
+        int n = lo - kb;
         if (B == K) {   // kets at or before the bra in the class order: a prefix too
-            size_t l2 = 0, h2 = kets.size();
+            int l2 = kb, h2 = ke;
             while (l2 < h2) {
-                size_t mid = (l2 + h2) / 2;
+                const int mid = (l2 + h2) / 2;
                 if (ket_pos[mid] <= bra_pos[r]) l2 = mid + 1; else h2 = mid;
             }
-            n = std::min(n, l2);
+            n = std::min(n, l2 - kb);
         }
-        nket[r] = (int)n;
-        if (n > 0) nbra = (int)r + 1;
+        nket[r] = n;
+        kseg[r] = make_int2(kb, ke);
         P.quartets += (long long)n;
         P.prim += (long long)bras[r].nprim * (long long)KL.kp * (long long)n;
     }
@@ -259,20 +272,20 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     std::vector<std::vector<int4>> queue(NX);
     std::vector<long long> load(NX, 0);
     for (int r = 0; r < nbra; ++r) {
-        const int n = nket[r];
+        const int n = nket[r], kb = kseg[r].x;
         if (stripe && n >= 2 * NX * WGS) {
             int nch = (n + TQ - 1) / TQ;
             nch = ((nch + NX - 1) / NX) * NX;
             int len = (n + nch - 1) / nch;
             len = ((len + WGS - 1) / WGS) * WGS;
             for (int j = 0, s0 = 0; s0 < n; ++j, s0 += len) {
-                queue[j % NX].push_back(make_int4(r, s0, std::min(n, s0 + len), 0));
+                queue[j % NX].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + len), 0));
                 load[j % NX] += std::min(len, n - s0);
             }
         } else {
             for (int s0 = 0; s0 < n; s0 += TQ) {
                 const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                queue[q].push_back(make_int4(r, s0, std::min(n, s0 + TQ), 0));
+                queue[q].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + TQ), 0));
                 load[q] += std::min(TQ, n - s0);
             }
         }
@@ -286,14 +299,16 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     if (tasks.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many tasks for one launch");
     P.nbra = nbra;
     P.ntask = (int)tasks.size();
-    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->nbf * sizeof(double);
+    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
     P.mode = (c->opt.digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024) ? 0 : 1;
     if (P.ntask == 0) return HFX_OK;
     HIPCK(dalloc(&P.d_nket, nbra));
+    HIPCK(dalloc(&P.d_kseg, nbra));
     HIPCK(dalloc(&P.d_split, nbra));
     HIPCK(dalloc(&P.d_tasks, tasks.size()));
     HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(P.d_kseg, kseg.data(), nbra * sizeof(int2), hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int4), hipMemcpyHostToDevice));
     ClassTotals& T = c->totals[P.cid];
     T.quartets += P.quartets;
@@ -309,6 +324,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
 static hfx_status replan(hfx_ctx* c) {
     for (auto& p : c->plans) {
         dfree(p.d_nket);
+        dfree(p.d_kseg);
         dfree(p.d_split);
         dfree(p.d_tasks);
         if (p.ev0) (void)hipEventDestroy(p.ev0);
@@ -352,35 +368,47 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     return replan(c);
 }
 
-extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double* xyz, int nshell,
-                               const hfx_shell* sh, int charge) {
+extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int* Z, const double* xyz,
+                                     const int* nshell_m, const hfx_shell* sh, const int* charge_m) {
     if (!c) return HFX_ERR_INVALID_ARG;
-    if (natom <= 0 || !Z || !xyz || nshell <= 0 || !sh)
+    if (nmol <= 0 || !natom_m || !Z || !xyz || !nshell_m || !sh)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: empty system or null pointer");
-    for (int a = 0; a < natom; ++a) {
-        if (Z[a] < 0 || Z[a] > 118) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nuclear charge out of range");
-        for (int x = 0; x < 3; ++x)
-            if (!std::isfinite(xyz[3 * a + x])) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: non-finite coordinate");
+    // ---- validation ----
+    long long natom = 0, nshell = 0;
+    for (int m = 0; m < nmol; ++m) {
+        if (natom_m[m] <= 0 || nshell_m[m] <= 0)
+            return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: every molecule needs atoms and shells");
+        long long nel = -(charge_m ? charge_m[m] : 0);
+        for (int a = 0; a < natom_m[m]; ++a) {
+            const long long ga = natom + a;
+            if (Z[ga] < 0 || Z[ga] > 118) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nuclear charge out of range");
+            for (int x = 0; x < 3; ++x)
+                if (!std::isfinite(xyz[3 * ga + x]))
+                    return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: non-finite coordinate");
+            nel += Z[ga];
+        }
+        if (nel < 0 || nel % 2)
+            return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: closed shell needs an even electron count");
+        for (int s = 0; s < nshell_m[m]; ++s) {
+            const hfx_shell& q = sh[nshell + s];
+            if (q.atom < 0 || q.atom >= natom_m[m]) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: shell atom index");
+            if (q.l < 0 || q.l > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: only s, p, d shells (l <= 2)");
+            if (q.nprim < 1 || q.nprim > 16 || !q.exps || !q.coefs)
+                return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nprim must be in [1, 16]");
+            for (int k = 0; k < q.nprim; ++k)
+                if (!(q.exps[k] > 0.0) || !std::isfinite(q.exps[k]) || !std::isfinite(q.coefs[k]))
+                    return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: exponents must be finite and > 0");
+        }
+        natom += natom_m[m];
+        nshell += nshell_m[m];
     }
-    for (int s = 0; s < nshell; ++s) {
-        if (sh[s].atom < 0 || sh[s].atom >= natom) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: shell atom index");
-        if (sh[s].l < 0 || sh[s].l > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: only s, p, d shells (l <= 2)");
-        if (sh[s].nprim < 1 || sh[s].nprim > 16 || !sh[s].exps || !sh[s].coefs)
-            return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nprim must be in [1, 16]");
-        for (int k = 0; k < sh[s].nprim; ++k)
-            if (!(sh[s].exps[k] > 0.0) || !std::isfinite(sh[s].exps[k]) || !std::isfinite(sh[s].coefs[k]))
-                return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: exponents must be finite and > 0");
-    }
-    long long nelec = -charge;
-    for (int a = 0; a < natom; ++a) nelec += Z[a];
-    if (nelec < 0 || nelec % 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: closed shell needs an even electron count");
+    if (nshell > 0x7fffffff / 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: too many shells");
     HIPCK(hipSetDevice(c->opt.device));
     release_system(c);
 
-    c->natom = natom;
-    c->nshell = nshell;
-    c->nelec = (int)nelec;
-    c->nocc = (int)(nelec / 2);
+    c->nmol = nmol;
+    c->natom = (int)natom;
+    c->nshell = (int)nshell;
     c->Z.assign(Z, Z + natom);
     c->axyz.assign(xyz, xyz + 3 * natom);
     c->shells.clear();
@@ -391,118 +419,169 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
     c->raw_coefs.clear();
     c->shell_atom.clear();
     c->shell_exps_l.clear();
-    int nbf = 0;
-    for (int s = 0; s < nshell; ++s) {
-        const int l = sh[s].l, np = sh[s].nprim;
-        ShellHost h;
-        h.x = xyz[3 * sh[s].atom];
-        h.y = xyz[3 * sh[s].atom + 1];
-        h.z = xyz[3 * sh[s].atom + 2];
-        h.l = l;
-        h.nprim = np;
-        h.prim_off = (int)c->exps.size();
-        h.bf = nbf;
-        // unit-normalised primitives: (2a/pi)^{3/4} (4a)^{l/2} for the x^l
-        // component; contraction renormalised to unit self-overlap.
-        std::vector<double> nc(np);
-        for (int k = 0; k < np; ++k)
-            nc[k] = sh[s].coefs[k] * std::pow(2.0 * sh[s].exps[k] / M_PI, 0.75) * std::pow(4.0 * sh[s].exps[k], 0.5 * l);
-        double self = 0.0;
-        for (int i = 0; i < np; ++i)
-            for (int j = 0; j < np; ++j) {
-                const double p = sh[s].exps[i] + sh[s].exps[j];
-                self += nc[i] * nc[j] * std::pow(M_PI / p, 1.5) / std::pow(2.0 * p, l);
+    c->mol.assign(nmol, MolInfo());
+    int nbf_tot = 0, nocc_tot = 0, nelec_tot = 0;
+    long long nelem = 0;
+    for (int m = 0, a0 = 0, s0 = 0; m < nmol; a0 += natom_m[m], s0 += nshell_m[m], ++m) {
+        MolInfo& M = c->mol[m];
+        M.natom = natom_m[m];
+        M.aoff = a0;
+        M.nshell = nshell_m[m];
+        M.soff = s0;
+        int nbf = 0;
+        for (int s = s0; s < s0 + nshell_m[m]; ++s) {
+            const int l = sh[s].l, np = sh[s].nprim;
+            const int ga = a0 + sh[s].atom;
+            ShellHost h;
+            h.x = xyz[3 * ga];
+            h.y = xyz[3 * ga + 1];
+            h.z = xyz[3 * ga + 2];
+            h.l = l;
+            h.nprim = np;
+            h.prim_off = (int)c->exps.size();
+            h.bf = nbf;   // local to the molecule
+            // unit-normalised primitives: (2a/pi)^{3/4} (4a)^{l/2} for the x^l
+            // component; contraction renormalised to unit self-overlap.
+            std::vector<double> nc(np);
+            for (int k = 0; k < np; ++k)
+                nc[k] = sh[s].coefs[k] * std::pow(2.0 * sh[s].exps[k] / M_PI, 0.75) * std::pow(4.0 * sh[s].exps[k], 0.5 * l);
+            double self = 0.0;
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j < np; ++j) {
+                    const double p = sh[s].exps[i] + sh[s].exps[j];
+                    self += nc[i] * nc[j] * std::pow(M_PI / p, 1.5) / std::pow(2.0 * p, l);
+                }
+            const double rn = 1.0 / std::sqrt(self);
+            for (int k = 0; k < np; ++k) {
+                c->exps.push_back(sh[s].exps[k]);
+                c->coefs.push_back(nc[k] * rn);
             }
-        const double rn = 1.0 / std::sqrt(self);
-        for (int k = 0; k < np; ++k) {
-            c->exps.push_back(sh[s].exps[k]);
-            c->coefs.push_back(nc[k] * rn);
+            for (int x = l; x >= 0; --x)
+                for (int y = l - x; y >= 0; --y) {
+                    const int z = l - x - y;
+                    c->cscale.push_back(1.0 / std::sqrt(dfact_odd(x) * dfact_odd(y) * dfact_odd(z)));
+                }
+            nbf += ncart(l);
+            c->shells.push_back(h);
+            c->raw_exps.emplace_back(sh[s].exps, sh[s].exps + np);
+            c->raw_coefs.emplace_back(sh[s].coefs, sh[s].coefs + np);
+            c->shell_atom.push_back(ga);
+            c->shell_exps_l.push_back(l);
         }
-        for (int x = l; x >= 0; --x)
-            for (int y = l - x; y >= 0; --y) {
-                const int z = l - x - y;
-                c->cscale.push_back(1.0 / std::sqrt(dfact_odd(x) * dfact_odd(y) * dfact_odd(z)));
+        int nel = -(charge_m ? charge_m[m] : 0);
+        double e = 0.0;
+        for (int a = a0; a < a0 + natom_m[m]; ++a) {
+            nel += Z[a];
+            for (int b = a0; b < a; ++b) {
+                const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
+                             dz = xyz[3 * a + 2] - xyz[3 * b + 2];
+                const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+                if (r == 0.0 && Z[a] * Z[b] != 0) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: coincident nuclei");
+                if (r > 0.0) e += (double)Z[a] * Z[b] / r;
             }
-        nbf += ncart(l);
-        c->shells.push_back(h);
-        c->raw_exps.emplace_back(sh[s].exps, sh[s].exps + np);
-        c->raw_coefs.emplace_back(sh[s].coefs, sh[s].coefs + np);
-        c->shell_atom.push_back(sh[s].atom);
-        c->shell_exps_l.push_back(l);
+        }
+        M.nbf = nbf;
+        M.boff = nbf_tot;
+        M.moff = nelem;
+        M.nelec = nel;
+        M.nocc = nel / 2;
+        M.enuc = e;
+        nbf_tot += nbf;
+        nocc_tot += M.nocc;
+        nelec_tot += nel;
+        nelem += (long long)nbf * nbf;
     }
-    c->nbf = nbf;
-    double e = 0.0;
-    for (int a = 0; a < natom; ++a)
-        for (int b = 0; b < a; ++b) {
-            const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
-                         dz = xyz[3 * a + 2] - xyz[3 * b + 2];
-            const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-            if (r == 0.0 && Z[a] * Z[b] != 0) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: coincident nuclei");
-            if (r > 0.0) e += (double)Z[a] * Z[b] / r;
+    c->nbf = nbf_tot;
+    c->nocc = nocc_tot;
+    c->nelec = nelec_tot;
+    c->nelem = (size_t)nelem;
+    c->enuc = 0.0;
+    c->max_ld = 0;
+    for (auto& M : c->mol) {
+        c->enuc += M.enuc;
+        c->max_ld = std::max(c->max_ld, M.nbf);
+    }
+    {
+        std::vector<long long> moff(nmol);
+        std::vector<int> mdim(nmol), mboff(nmol);
+        for (int m = 0; m < nmol; ++m) {
+            moff[m] = c->mol[m].moff;
+            mdim[m] = c->mol[m].nbf;
+            mboff[m] = c->mol[m].boff;
         }
-    c->enuc = e;
-    const size_t nn = (size_t)nbf * nbf;
-    HIPCK(dalloc(&c->d_cscale, nbf));
-    HIPCK(hipMemcpy(c->d_cscale, c->cscale.data(), nbf * sizeof(double), hipMemcpyHostToDevice));
+        HIPCK(dalloc(&c->d_moff, nmol));
+        HIPCK(dalloc(&c->d_mdim, nmol));
+        HIPCK(dalloc(&c->d_mboff, nmol));
+        HIPCK(hipMemcpy(c->d_moff, moff.data(), nmol * sizeof(long long), hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(c->d_mdim, mdim.data(), nmol * sizeof(int), hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(c->d_mboff, mboff.data(), nmol * sizeof(int), hipMemcpyHostToDevice));
+    }
+    HIPCK(dalloc(&c->d_cscale, nbf_tot));
+    HIPCK(hipMemcpy(c->d_cscale, c->cscale.data(), nbf_tot * sizeof(double), hipMemcpyHostToDevice));
 
-    // ---- all shell pairs in canonical orientation, primitive-pair data ----
+    // ---- shell pairs within each molecule, canonical orientation ----
     std::vector<PrimPair> prim;
     std::vector<std::vector<PairInfo>> all(6);
-    for (int a = 0; a < nshell; ++a)
-        for (int b = 0; b <= a; ++b) {
-            int A = a, Bs = b;
-            if (c->shells[b].l > c->shells[a].l) std::swap(A, Bs);
-            const ShellHost& SA = c->shells[A];
-            const ShellHost& SB = c->shells[Bs];
-            PairInfo pi;
-            pi.a = A;
-            pi.b = Bs;
-            pi.bfa = SA.bf;
-            pi.bfb = SB.bf;
-            pi.AB[0] = SA.x - SB.x;
-            pi.AB[1] = SA.y - SB.y;
-            pi.AB[2] = SA.z - SB.z;
-            pi.Q = 0.0;
-            pi.pad = 0.0;
-            const double ab2 = pi.AB[0] * pi.AB[0] + pi.AB[1] * pi.AB[1] + pi.AB[2] * pi.AB[2];
-            pi.prim_off = (int)prim.size();
-            int np = 0;
-            double kmax = 0.0;
-            for (int i = 0; i < SA.nprim; ++i)
-                for (int j = 0; j < SB.nprim; ++j) {
-                    const double al = c->exps[SA.prim_off + i], be = c->exps[SB.prim_off + j];
-                    const double p = al + be, mu = al * be / p;
-                    PrimPair pp;
-                    pp.p = p;
-                    pp.inv2p = 0.5 / p;
-                    pp.P[0] = (al * SA.x + be * SB.x) / p;
-                    pp.P[1] = (al * SA.y + be * SB.y) / p;
-                    pp.P[2] = (al * SA.z + be * SB.z) / p;
-                    pp.PA[0] = pp.P[0] - SA.x;
-                    pp.PA[1] = pp.P[1] - SA.y;
-                    pp.PA[2] = pp.P[2] - SA.z;
-                    const double ek = std::exp(-mu * ab2);
-                    // sqrt(2 pi^{5/2}) = sqrt(2) pi^{5/4}
-                    pp.K = c->coefs[SA.prim_off + i] * c->coefs[SB.prim_off + j] * ek * 1.4142135623730951 *
-                           std::pow(M_PI, 1.25) / p;
-                    pp.pad = 0.0;
-                    kmax = std::max(kmax, ek);
-                    prim.push_back(pp);
-                    ++np;
+    for (int m = 0; m < nmol; ++m) {
+        const MolInfo& M = c->mol[m];
+        for (int a = M.soff; a < M.soff + M.nshell; ++a)
+            for (int b = M.soff; b <= a; ++b) {
+                int A = a, Bs = b;
+                if (c->shells[b].l > c->shells[a].l) std::swap(A, Bs);
+                const ShellHost& SA = c->shells[A];
+                const ShellHost& SB = c->shells[Bs];
+                PairInfo pi;
+                pi.a = A;
+                pi.b = Bs;
+                pi.bfa = SA.bf;
+                pi.bfb = SB.bf;
+                pi.AB[0] = SA.x - SB.x;
+                pi.AB[1] = SA.y - SB.y;
+                pi.AB[2] = SA.z - SB.z;
+                pi.Q = 0.0;
+                pi.mol = m;
+                pi.ld = M.nbf;
+                const double ab2 = pi.AB[0] * pi.AB[0] + pi.AB[1] * pi.AB[1] + pi.AB[2] * pi.AB[2];
+                pi.prim_off = (int)prim.size();
+                int np = 0;
+                double kmax = 0.0;
+                for (int i = 0; i < SA.nprim; ++i)
+                    for (int j = 0; j < SB.nprim; ++j) {
+                        const double al = c->exps[SA.prim_off + i], be = c->exps[SB.prim_off + j];
+                        const double p = al + be, mu = al * be / p;
+                        PrimPair pp;
+                        pp.p = p;
+                        pp.inv2p = 0.5 / p;
+                        pp.P[0] = (al * SA.x + be * SB.x) / p;
+                        pp.P[1] = (al * SA.y + be * SB.y) / p;
+                        pp.P[2] = (al * SA.z + be * SB.z) / p;
+                        pp.PA[0] = pp.P[0] - SA.x;
+                        pp.PA[1] = pp.P[1] - SA.y;
+                        pp.PA[2] = pp.P[2] - SA.z;
+                        const double ek = std::exp(-mu * ab2);
+                        // sqrt(2 pi^{5/2}) = sqrt(2) pi^{5/4}
+                        pp.K = c->coefs[SA.prim_off + i] * c->coefs[SB.prim_off + j] * ek * 1.4142135623730951 *
+                               std::pow(M_PI, 1.25) / p;
+                        pp.pad = 0.0;
+                        kmax = std::max(kmax, ek);
+                        prim.push_back(pp);
+                        ++np;
+                    }
+                pi.nprim = np;
+                if (kmax < 1e-40) {   // Gaussian overlap exp(-mu R^2) < 1e-40 for every primitive pair
+                    prim.resize(pi.prim_off);
+                    continue;
                 }
-            pi.nprim = np;
-            if (kmax < 1e-40) {   // Gaussian overlap exp(-mu R^2) < 1e-40 for every primitive pair
-                prim.resize(pi.prim_off);
-                continue;
+                if (prim.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many primitive pairs");
+                all[pair_class(SA.l, SB.l)].push_back(pi);
             }
-            all[pair_class(SA.l, SB.l)].push_back(pi);
-        }
-    if (prim.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many primitive pairs");
+    }
     HIPCK(dalloc(&c->d_prim, prim.size()));
     HIPCK(hipMemcpy(c->d_prim, prim.data(), prim.size() * sizeof(PrimPair), hipMemcpyHostToDevice));
 
     // ---- Schwarz bounds on the GPU (FP64 class kernels on (ab|ab)) ----
-    c->Qshell.assign((size_t)nshell * nshell, 0.0);
+    const bool keep_qshell = nmol == 1;
+    c->Qshell.assign(keep_qshell ? (size_t)nshell * nshell : 0, 0.0);
     double qmax = 0.0;
     for (int B = 0; B < 6; ++B) {
         auto& L = all[B];
@@ -512,7 +591,7 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
         HIPCK(dalloc(&dp, L.size()));
         HIPCK(dalloc(&dq, L.size()));
         HIPCK(hipMemcpy(dp, L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
-        HIPCK(hfx_launch_schwarz(class_id(B, B), dp, (int)L.size(), c->d_prim, c->d_boys64, c->d_cscale, dq, 0));
+        HIPCK(hfx_launch_schwarz(class_id(B, B), dp, (int)L.size(), c->d_prim, c->d_boys64, dq, 0));
         std::vector<double> q(L.size());
         HIPCK(hipMemcpy(q.data(), dq, q.size() * sizeof(double), hipMemcpyDeviceToHost));
         dfree(dp);
@@ -521,11 +600,13 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
             if (!std::isfinite(q[i])) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite Schwarz bound");
             L[i].Q = q[i];
             qmax = std::max(qmax, q[i]);
-            c->Qshell[(size_t)L[i].a * nshell + L[i].b] = q[i];
-            c->Qshell[(size_t)L[i].b * nshell + L[i].a] = q[i];
+            if (keep_qshell) {
+                c->Qshell[(size_t)L[i].a * nshell + L[i].b] = q[i];
+                c->Qshell[(size_t)L[i].b * nshell + L[i].a] = q[i];
+            }
         }
     }
-    // ---- significant pairs, sorted by Q descending (ties: pair order) ----
+    // ---- significant pairs, sorted by molecule then Q descending (ties: pair order) ----
     const double tau = c->opt.schwarz_tau;
     std::vector<std::vector<double>> pos(6);
     for (int B = 0; B < 6; ++B) {
@@ -534,7 +615,9 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
         keep.reserve(L.size());
         for (auto& p : L)
             if (p.Q * qmax >= tau) keep.push_back(p);
-        std::stable_sort(keep.begin(), keep.end(), [](const PairInfo& x, const PairInfo& y) { return x.Q > y.Q; });
+        std::stable_sort(keep.begin(), keep.end(), [](const PairInfo& x, const PairInfo& y) {
+            return x.mol < y.mol || (x.mol == y.mol && x.Q > y.Q);
+        });
         L.swap(keep);
         c->npair[B] = (int)L.size();
         pos[B].resize(L.size());
@@ -542,9 +625,10 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
         HIPCK(dalloc(&c->d_pairs[B], L.size()));
         if (!L.empty()) HIPCK(hipMemcpy(c->d_pairs[B], L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
     }
-    // ---- ket lists: one per pair class and primitive count ----
+    // ---- ket lists: one per pair class and primitive count (molecule segments) ----
     std::vector<std::vector<PairInfo>> klist;
     std::vector<std::vector<double>> kpos;
+    c->kseg.clear();
     for (int K = 0; K < 6; ++K) {
         std::vector<int> nps;
         for (auto& p : all[K])
@@ -563,6 +647,9 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
                 }
             KL.n = (int)sub.size();
             const size_t n = sub.size();
+            std::vector<int> seg(nmol + 1, 0);   // molecule m's kets: [seg[m], seg[m+1])
+            for (size_t s = 0; s < n; ++s) seg[sub[s].mol + 1]++;
+            for (int m = 0; m < nmol; ++m) seg[m + 1] += seg[m];
             std::vector<double> q(n), soa((size_t)9 * kp * n);
             for (size_t s = 0; s < n; ++s) {
                 q[s] = sub[s].Q;
@@ -583,6 +670,7 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
             c->ketlists.push_back(KL);
             klist.push_back(std::move(sub));
             kpos.push_back(std::move(sp));
+            c->kseg.push_back(std::move(seg));
         }
     }
     c->host_bra.assign(all.begin(), all.end());
@@ -594,36 +682,41 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
         if (s != HFX_OK) return s;
     }
 
-    // ---- one-electron integrals ----
+    // ---- one-electron integrals, one launch per molecule (its own nuclei) ----
     std::vector<double> atoms(4 * (size_t)natom);
-    for (int a = 0; a < natom; ++a) {
+    for (long long a = 0; a < natom; ++a) {
         atoms[4 * a] = xyz[3 * a];
         atoms[4 * a + 1] = xyz[3 * a + 1];
         atoms[4 * a + 2] = xyz[3 * a + 2];
         atoms[4 * a + 3] = Z[a];
     }
+    const size_t ne = c->nelem;
     ShellHost* dsh = nullptr;
     double *dexp = nullptr, *dcoef = nullptr, *datoms = nullptr, *dT = nullptr, *dV = nullptr;
     HIPCK(dalloc(&dsh, nshell));
     HIPCK(dalloc(&dexp, c->exps.size()));
     HIPCK(dalloc(&dcoef, c->coefs.size()));
     HIPCK(dalloc(&datoms, atoms.size()));
-    HIPCK(dalloc(&c->d_S, nn));
-    HIPCK(dalloc(&dT, nn));
-    HIPCK(dalloc(&dV, nn));
+    HIPCK(dalloc(&c->d_S, ne));
+    HIPCK(dalloc(&dT, ne));
+    HIPCK(dalloc(&dV, ne));
     HIPCK(hipMemcpy(dsh, c->shells.data(), nshell * sizeof(ShellHost), hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(dexp, c->exps.data(), c->exps.size() * 8, hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(dcoef, c->coefs.data(), c->coefs.size() * 8, hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(datoms, atoms.data(), atoms.size() * 8, hipMemcpyHostToDevice));
-    HIPCK(hfx_one_electron(dsh, nshell, dexp, dcoef, datoms, natom, c->d_cscale, c->d_boys64, nbf, c->d_S, dT, dV, 0));
-    // H = T + V (reuse the assemble-free path: simple host-free add via fill + axpy with rocBLAS)
-    HIPCK(dalloc(&c->d_H, nn));
-    HIPCK(hipMemcpy(c->d_H, dT, nn * 8, hipMemcpyDeviceToDevice));
+    for (int m = 0; m < nmol; ++m) {
+        const MolInfo& M = c->mol[m];
+        HIPCK(hfx_one_electron(dsh + M.soff, M.nshell, dexp, dcoef, datoms + 4 * (size_t)M.aoff, M.natom,
+                               c->d_cscale + M.boff, c->d_boys64, M.nbf, c->d_S + M.moff, dT + M.moff, dV + M.moff,
+                               0));
+    }
+    HIPCK(dalloc(&c->d_H, ne));
+    HIPCK(hipMemcpy(c->d_H, dT, ne * 8, hipMemcpyDeviceToDevice));
     {
         const double one = 1.0;
         rocblas_set_pointer_mode(c->blas, rocblas_pointer_mode_host);
         rocblas_set_stream(c->blas, 0);
-        if (rocblas_daxpy(c->blas, (rocblas_int)nn, &one, dV, 1, c->d_H, 1) != rocblas_status_success)
+        if (rocblas_daxpy(c->blas, (rocblas_int)ne, &one, dV, 1, c->d_H, 1) != rocblas_status_success)
             return hfx_fail(c, HFX_ERR_DEVICE, "rocblas_daxpy failed");
     }
     HIPCK(hipDeviceSynchronize());
@@ -633,9 +726,28 @@ extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double
     dfree(datoms);
     dfree(dT);
     dfree(dV);
-    HIPCK(dalloc(&c->d_W, nn));
-    HIPCK(dalloc(&c->d_Dp, nn));
+    HIPCK(dalloc(&c->d_W, ne));
+    HIPCK(dalloc(&c->d_Dp, ne));
     c->loaded = true;
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_load(hfx_ctx* c, int natom, const int* Z, const double* xyz, int nshell,
+                               const hfx_shell* sh, int charge) {
+    return hfx_load_batch(c, 1, &natom, Z, xyz, &nshell, sh, &charge);
+}
+
+extern "C" hfx_status hfx_batch_layout(const hfx_ctx* c, int* nmol, int* nbf, int* nocc, long long* offset,
+                                       long long* total) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return HFX_ERR_STATE;
+    if (nmol) *nmol = c->nmol;
+    for (int m = 0; m < c->nmol; ++m) {
+        if (nbf) nbf[m] = c->mol[m].nbf;
+        if (nocc) nocc[m] = c->mol[m].nocc;
+        if (offset) offset[m] = c->mol[m].moff;
+    }
+    if (total) *total = (long long)c->nelem;
     return HFX_OK;
 }
 
@@ -652,7 +764,7 @@ extern "C" hfx_status hfx_core(hfx_ctx* c, double* S, double* H, double* enuc) {
     if (!c) return HFX_ERR_INVALID_ARG;
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_core: nothing loaded");
     HIPCK(hipSetDevice(c->opt.device));
-    const size_t nn = (size_t)c->nbf * c->nbf;
+    const size_t nn = c->nelem;
     if (S) HIPCK(hipMemcpy(S, c->d_S, nn * 8, hipMemcpyDeviceToHost));
     if (H) HIPCK(hipMemcpy(H, c->d_H, nn * 8, hipMemcpyDeviceToHost));
     if (enuc) *enuc = c->enuc;
@@ -662,6 +774,7 @@ extern "C" hfx_status hfx_core(hfx_ctx* c, double* S, double* H, double* enuc) {
 extern "C" hfx_status hfx_schwarz(hfx_ctx* c, double* Q) {
     if (!c || !Q) return HFX_ERR_INVALID_ARG;
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_schwarz: nothing loaded");
+    if (c->nmol != 1) return hfx_fail(c, HFX_ERR_STATE, "hfx_schwarz: single-molecule contexts only");
     std::memcpy(Q, c->Qshell.data(), c->Qshell.size() * sizeof(double));
     return HFX_OK;
 }
@@ -752,14 +865,14 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
                               hipStream_t st, hfx_fock_stats* stats, int shard, int nshards) {
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "build: nothing loaded");
-    const int n = c->nbf;
-    const size_t nn = (size_t)n * n;
+    const size_t nn = c->nelem;
     const bool mixed = c->opt.precision == HFX_PREC_MIXED;
     auto t0 = std::chrono::steady_clock::now();
     if (c->timing) collect_timing(c);
     HIPCK(hfx_fill_u64(c->d_dmax, 1, st));
     HIPCK(hfx_fill_u64(c->d_counters, 43, st));   // 42 quartet counters + the non-finite flag
-    HIPCK(hfx_prepare_density(dD, c->d_cscale, n, c->d_Dp, c->d_dmax, st));
+    HIPCK(hfx_prepare_density(dD, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, c->d_Dp,
+                              c->d_dmax, st));
     HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
     for (auto& KL : c->ketlists) HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
@@ -768,7 +881,7 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         const int cid = P.cid;
         const bool mx = mixed && !P.fp64_only;
         if (mx)
-            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, KL.n, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
+            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_kseg, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
                             st));
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
@@ -777,8 +890,8 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.kprim = KL.d_soa;
         a.nket_list = KL.n;
         a.knprim = KL.kp;
-        a.nket = P.d_nket;
         a.split = P.d_split;
+        a.moff = c->d_moff;
         a.tasks = P.d_tasks;
         a.boys64 = c->d_boys64;
         a.boys32 = c->d_boys32;
@@ -786,8 +899,6 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.W = c->d_W;
         a.wket = KL.d_wket;
         a.counters = c->d_counters + 2 * cid;
-        a.nbf = n;
-        a.task_quartets = c->opt.task_quartets;
         a.cj = cj;
         a.ck = ck;
         a.shard = shard;
@@ -800,9 +911,10 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         }
     }
     for (auto& KL : c->ketlists)
-        HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, n, c->d_W,
+        HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, c->d_moff, c->d_W,
                               st));
-    HIPCK(hfx_assemble(dH, c->d_W, c->d_cscale, n, dOut, c->d_bad, st));
+    HIPCK(hfx_assemble(dH, c->d_W, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, dOut, c->d_bad,
+                       st));
     c->last_stream = st;
     if (stats) {
         HIPCK(hipStreamSynchronize(st));
@@ -853,10 +965,58 @@ extern "C" hfx_status hfx_build_2e_shard_dev(hfx_ctx* c, const double* dD, doubl
     return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, nullptr, shard, nshards);
 }
 
+// ---- HIP graph of one build -------------------------------------------------------
+// One eager build first (kernel attributes, first-touch), then the same
+// launch sequence is captured on the caller's stream and instantiated.  Every
+// node is a kernel (fills are kernels too: no memset nodes).
+
+extern "C" hfx_status hfx_graph_capture(hfx_ctx* c, const double* dD, double* dF, void* stream) {
+    if (!c || !dD || !dF || !stream)
+        return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "graph capture needs device pointers and a non-null stream")
+                 : HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_graph_capture: nothing loaded");
+    HIPCK(hipSetDevice(c->opt.device));
+    hipStream_t st = (hipStream_t)stream;
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    hfx_status s = hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, st, nullptr, 0, 1);
+    if (s != HFX_OK) {
+        c->timing = timing;
+        return s;
+    }
+    HIPCK(hipStreamSynchronize(st));
+    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    s = hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, st, nullptr, 0, 1);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    c->timing = timing;
+    if (s != HFX_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    HIPCK(e);
+    const hipError_t ei = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCK(ei);
+    return HFX_OK;
+}
+
+extern "C" hfx_status hfx_graph_launch(hfx_ctx* c, void* stream) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (!c->graph_exec) return hfx_fail(c, HFX_ERR_STATE, "hfx_graph_launch: no captured graph");
+    HIPCK(hipSetDevice(c->opt.device));
+    HIPCK(hipGraphLaunch(c->graph_exec, (hipStream_t)stream));
+    return HFX_OK;
+}
+
 extern "C" hfx_status hfx_build_fock(hfx_ctx* c, const double* D, double* F, hfx_fock_stats* stats) {
     if (!c || !D || !F) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_build_fock: nothing loaded");
-    const size_t nn = (size_t)c->nbf * c->nbf;
+    const size_t nn = c->nelem;
     if (!finite_host(D, nn)) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite density");
     HIPCK(hipSetDevice(c->opt.device));
     if (!c->d_tmpD) HIPCK(dalloc(&c->d_tmpD, nn));

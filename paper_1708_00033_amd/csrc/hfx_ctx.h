@@ -32,6 +32,7 @@ struct SubPlan {
     int nbra = 0;             // bras with at least one ket
     int ntask = 0;
     int* d_nket = nullptr;
+    int2* d_kseg = nullptr;   // per bra: its molecule's segment of the ket list
     int* d_split = nullptr;
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
@@ -49,13 +50,29 @@ struct ClassTotals {
     long long quartets = 0, integrals = 0, prim = 0, ntask = 0;
 };
 
+// One molecule of a batch (a single system is a batch of one).  Its
+// matrices are the ragged block at element offset moff, nbf x nbf row-major.
+struct MolInfo {
+    int natom = 0, aoff = 0, nshell = 0, soff = 0;
+    int nbf = 0, boff = 0, nelec = 0, nocc = 0;
+    long long moff = 0;
+    double enuc = 0.0;
+};
+
 struct hfx_ctx {
     hfx_options opt{};
     std::string err;
     bool loaded = false;
     // system
-    int natom = 0, nshell = 0, nbf = 0, nelec = 0, nocc = 0;
+    int natom = 0, nshell = 0, nbf = 0, nelec = 0, nocc = 0;   // totals over the batch
     double enuc = 0.0;
+    int nmol = 0, max_ld = 0;
+    size_t nelem = 0;                   // sum of nbf_m^2 (ragged matrix storage)
+    std::vector<MolInfo> mol;
+    long long* d_moff = nullptr;
+    int* d_mdim = nullptr;
+    int* d_mboff = nullptr;
+    std::vector<std::vector<int>> kseg;   // per ket list: molecule segment starts (nmol + 1)
     std::vector<int> Z;
     std::vector<double> axyz;
     std::vector<ShellHost> shells;
@@ -91,6 +108,7 @@ struct hfx_ctx {
     unsigned long long* d_counters = nullptr;  // 2 per class
     int* d_bad = nullptr;
     rocblas_handle blas = nullptr;
+    hipGraphExec_t graph_exec = nullptr;   // captured build (hfx_graph_capture)
     // timing
     bool timing = false;
     hipStream_t last_stream = nullptr;
@@ -104,16 +122,16 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
 
 // implemented in misc_kernels.hip
 extern "C" {
-hipError_t hfx_prepare_density(const double* D, const double* cs, int n, double* Dp, unsigned long long* dmax_bits,
-                               hipStream_t st);
+hipError_t hfx_prepare_density(const double* D, const double* cs, int nmol, const long long* moff, const int* mdim,
+                               const int* mboff, int max_ld, double* Dp, unsigned long long* dmax_bits, hipStream_t st);
 hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
-hipError_t hfx_split(const PairInfo* bra, const double* ketq, int nket_total, const int* nket, int nbra,
+hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int2* kseg, const int* nket, int nbra,
                      double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st);
-hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, int nbf, double* W,
-                           hipStream_t st);
-hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int n, double* F, int* bad,
-                        hipStream_t st);
+hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,
+                           double* W, hipStream_t st);
+hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int nmol, const long long* moff,
+                        const int* mdim, const int* mboff, int max_ld, double* F, int* bad, hipStream_t st);
 hipError_t hfx_one_electron(const void* sh, int nshell, const double* exps, const double* coefs, const double* atoms,
                             int natom, const double* cs, const double* boys, int n, double* S, double* T, double* V,
                             hipStream_t st);
@@ -129,5 +147,5 @@ hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_
                             const ClassArgs* args);
 int hfx_class_wgs(int cid);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
-                              const double* cscale, double* Q, hipStream_t stream);
+                              double* Q, hipStream_t stream);
 }

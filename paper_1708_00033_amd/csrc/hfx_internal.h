@@ -22,12 +22,13 @@ struct PrimPair {
 // One shell pair in canonical orientation: shells a (higher l) and b, their
 // first basis functions, its primitive pairs, its Schwarz bound and A - B.
 struct PairInfo {
-    int a, b;
-    int bfa, bfb;
+    int a, b;          // shells (global index)
+    int bfa, bfb;      // first basis functions, local to the molecule
     int prim_off, nprim;
     double Q;
     double AB[3];
-    double pad;
+    int mol;           // molecule of a batch
+    int ld;            // its basis size (leading dimension of its blocks)
 };
 
 // Arguments of one class kernel launch.  The kets of a launch all have the
@@ -41,17 +42,15 @@ struct ClassArgs {
     const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
     int nket_list, knprim;
-    const int* __restrict__ nket;       // per bra: number of kets (screened prefix)
-    const int* __restrict__ split;      // per bra: kets below this index use FP64 (nullptr: all)
+    const int* __restrict__ split;      // per bra: kets below this list position use FP64
     const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0) per workgroup; bra -1: empty
+    const long long* __restrict__ moff; // per molecule: element offset of its blocks in D', W
     const double* __restrict__ boys64;
     const float* __restrict__ boys32;
     const double* __restrict__ D;       // component-scaled density D'
     double* __restrict__ W;             // accumulator, F_2e = s (W + W^T) s / 8
     double* __restrict__ wket;          // LDS mode: ket-block J sums, [component][ket position]
     unsigned long long* __restrict__ counters;  // [0] FP64 quartets, [1] FP32 quartets
-    int nbf;
-    int task_quartets;
     int shard, nshards;                 // only bras with r % nshards == shard (1 shard: all)
     double cj, ck;                      // W_ab += cj*2 g D_cd ; W_ac -= ck g D_bd
 };

@@ -9,15 +9,25 @@
 
 // ---- per build --------------------------------------------------------------
 
+// Matrices are stored per molecule (ragged): molecule m's nbf_m x nbf_m
+// block starts at element moff[m]; its basis functions are global indices
+// mboff[m] .. mboff[m] + nbf_m - 1 (component factors cs[]).  Elementwise
+// kernels run on a (gx, nmol) grid, row y = molecule.
+
 // D' = s_m s_n D (component normalisation moved onto the density),
 // dmax = max |D| (bit pattern of a non-negative double is order preserving).
-__global__ void k_prepare_density(const double* __restrict__ D, const double* __restrict__ cs, int n,
-                                  double* __restrict__ Dp, unsigned long long* __restrict__ dmax_bits) {
-    const size_t nn = (size_t)n * n;
+__global__ void k_prepare_density(const double* __restrict__ D, const double* __restrict__ cs,
+                                  const long long* __restrict__ moff, const int* __restrict__ mdim,
+                                  const int* __restrict__ mboff, double* __restrict__ Dp,
+                                  unsigned long long* __restrict__ dmax_bits) {
+    const int mol = blockIdx.y;
+    const int n = mdim[mol];
+    const size_t nn = (size_t)n * n, base = (size_t)moff[mol];
+    const double* __restrict__ c = cs + mboff[mol];
     double mx = 0.0;
     for (size_t i = (size_t)blockIdx.x * MISC_WG + threadIdx.x; i < nn; i += (size_t)gridDim.x * MISC_WG) {
-        const double d = D[i];
-        Dp[i] = cs[i / n] * cs[i % n] * d;
+        const double d = D[base + i];
+        Dp[base + i] = c[i / n] * c[i % n] * d;
         const double ad = fabs(d);
         mx = (ad > mx || ad != ad) ? ad : mx;   // NaN propagates
     }
@@ -41,33 +51,39 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
-// FP64/FP32 split per bra r: kets s < split[r] satisfy Q_r Q_s max|D| >= fp32_tau.
-__global__ void k_split(const PairInfo* __restrict__ bra, const double* __restrict__ ketq, int nket_total,
-                        const int* __restrict__ nket, int nbra, double fp32_tau,
+// FP64/FP32 split per bra r: within its molecule's ket segment [kb, ke) the
+// kets s with Q_r Q_s max|D| >= fp32_tau come first (Q descending);
+// split[r] = kb + min(their count, nket[r]) is a list position.
+__global__ void k_split(const PairInfo* __restrict__ bra, const double* __restrict__ ketq,
+                        const int2* __restrict__ kseg, const int* __restrict__ nket, int nbra, double fp32_tau,
                         const unsigned long long* __restrict__ dmax_bits, int* __restrict__ split) {
     const int r = blockIdx.x * MISC_WG + threadIdx.x;
     if (r >= nbra) return;
     const double dmax = __longlong_as_double((long long)*dmax_bits);
     const double qr = bra[r].Q * dmax;
-    // number of kets with ketq[s] * qr >= fp32_tau (ketq descending)
-    int lo = 0, hi = nket_total;
+    const int kb = kseg[r].x, ke = kseg[r].y;
+    int lo = kb, hi = ke;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (ketq[mid] * qr >= fp32_tau) lo = mid + 1; else hi = mid;
     }
-    split[r] = min(lo, nket[r]);
+    split[r] = kb + min(lo - kb, nket[r]);
 }
 
-// F = H + s_m s_n (W + W^T) / 8 (H may be null: two-electron part only);
-// raises *bad if a non-finite value appears.
+// F = H + s_m s_n (W + W^T) / 8 per molecule block (H may be null: two-electron
+// part only); raises *bad if a non-finite value appears.
 __global__ void k_assemble(const double* __restrict__ H, const double* __restrict__ W, const double* __restrict__ cs,
-                           int n, double* __restrict__ F, int* __restrict__ bad) {
-    const size_t nn = (size_t)n * n;
+                           const long long* __restrict__ moff, const int* __restrict__ mdim,
+                           const int* __restrict__ mboff, double* __restrict__ F, int* __restrict__ bad) {
+    const int mol = blockIdx.y;
+    const int n = mdim[mol];
+    const size_t nn = (size_t)n * n, base = (size_t)moff[mol];
+    const double* __restrict__ c = cs + mboff[mol];
     for (size_t i = (size_t)blockIdx.x * MISC_WG + threadIdx.x; i < nn; i += (size_t)gridDim.x * MISC_WG) {
-        const size_t r = i / n, c = i % n;
-        const double g = 0.125 * cs[r] * cs[c] * (W[i] + W[c * n + r]);
-        const double f = (H ? H[i] : 0.0) + g;
-        F[i] = f;
+        const size_t r = i / n, col = i % n;
+        const double g = 0.125 * c[r] * c[col] * (W[base + i] + W[base + col * n + r]);
+        const double f = (H ? H[base + i] : 0.0) + g;
+        F[base + i] = f;
         if (!isfinite(f) && bad) *bad = 1;
     }
 }
@@ -75,14 +91,15 @@ __global__ void k_assemble(const double* __restrict__ H, const double* __restric
 // W_cd += wket[comp][s] for every ket pair s of one list: each pair owns its
 // W block, so plain read-modify-write (no atomics) after the class kernels.
 __global__ void k_scatter_ket(const PairInfo* __restrict__ kets, int n, int nc, int nd,
-                              const double* __restrict__ wket, int nbf, double* __restrict__ W) {
+                              const double* __restrict__ wket, const long long* __restrict__ moff,
+                              double* __restrict__ W) {
     const int i = blockIdx.x * MISC_WG + threadIdx.x;
     if (i >= n * nc * nd) return;
     const int s = i % n, comp = i / n;
     const double v = wket[i];
     if (v == 0.0) return;
     const PairInfo p = kets[s];
-    const size_t idx = (size_t)(p.bfa + comp / nd) * nbf + p.bfb + comp % nd;
+    const size_t idx = (size_t)moff[p.mol] + (size_t)(p.bfa + comp / nd) * p.ld + p.bfb + comp % nd;
     W[idx] += v;
 }
 
@@ -332,37 +349,46 @@ static int grid_for(size_t n) {
 }
 
 extern "C" {
-hipError_t hfx_prepare_density(const double* D, const double* cs, int n, double* Dp, unsigned long long* dmax_bits,
+static dim3 ragged_grid(int max_ld, int nmol) {
+    size_t g = ((size_t)max_ld * max_ld + MISC_WG - 1) / MISC_WG;
+    if (g > 4096) g = 4096;
+    return dim3((unsigned)(g ? g : 1), (unsigned)nmol);
+}
+hipError_t hfx_prepare_density(const double* D, const double* cs, int nmol, const long long* moff, const int* mdim,
+                               const int* mboff, int max_ld, double* Dp, unsigned long long* dmax_bits,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_prepare_density, dim3(grid_for((size_t)n * n)), dim3(MISC_WG), 0, st, D, cs, n, Dp, dmax_bits);
+    hipLaunchKernelGGL(k_prepare_density, ragged_grid(max_ld, nmol), dim3(MISC_WG), 0, st, D, cs, moff, mdim, mboff, Dp,
+                       dmax_bits);
     return hipGetLastError();
 }
 hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(MISC_WG), 0, st, p, n, v);
     return hipGetLastError();
 }
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3((n + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, p, n);
     return hipGetLastError();
 }
-hipError_t hfx_split(const PairInfo* bra, const double* ketq, int nket_total, const int* nket, int nbra,
+hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int2* kseg, const int* nket, int nbra,
                      double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st) {
     if (nbra <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_split, dim3((nbra + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, nket_total, nket,
+    hipLaunchKernelGGL(k_split, dim3((nbra + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, kseg, nket,
                        nbra, fp32_tau, dmax_bits, split);
     return hipGetLastError();
 }
-hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, int nbf, double* W,
-                           hipStream_t st) {
+hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,
+                           double* W, hipStream_t st) {
     const int tot = n * nc * nd;
     if (tot <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_ket, dim3((tot + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, kets, n, nc, nd, wket,
-                       nbf, W);
+                       moff, W);
     return hipGetLastError();
 }
-hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int n, double* F, int* bad,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_assemble, dim3(grid_for((size_t)n * n)), dim3(MISC_WG), 0, st, H, W, cs, n, F, bad);
+hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int nmol, const long long* moff,
+                        const int* mdim, const int* mboff, int max_ld, double* F, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble, ragged_grid(max_ld, nmol), dim3(MISC_WG), 0, st, H, W, cs, moff, mdim, mboff, F, bad);
     return hipGetLastError();
 }
 hipError_t hfx_one_electron(const void* sh, int nshell, const double* exps, const double* coefs, const double* atoms,

@@ -451,6 +451,7 @@ extern "C" hfx_status hfx_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_re
                               double* C_out, double* eps_out) {
     if (!c || !res) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_scf: nothing loaded");
+    if (c->nmol != 1) return hfx_fail(c, HFX_ERR_STATE, "hfx_scf: use hfx_batch_scf for a batch");
     hfx_scf_options o;
     if (opt) o = *opt; else hfx_default_scf_options(&o);
     if (o.max_iter < 1 || o.diis_max < 0 || o.diis_max > 32 || !(o.e_tol > 0) || !(o.d_rms_tol > 0) ||

@@ -82,6 +82,12 @@ _sigs = {
     "hfx_default_scf_options": ([C.POINTER(hfx_scf_options)], C.c_int),
     "hfx_create": ([C.POINTER(hfx_options), C.POINTER(_ctx_p)], C.c_int),
     "hfx_load": ([_ctx_p, C.c_int, C.POINTER(C.c_int), _dp, C.c_int, C.POINTER(hfx_shell), C.c_int], C.c_int),
+    "hfx_load_batch": ([_ctx_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, C.POINTER(C.c_int),
+                        C.POINTER(hfx_shell), C.POINTER(C.c_int)], C.c_int),
+    "hfx_batch_layout": ([_ctx_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                          C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_graph_capture": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hfx_graph_launch": ([_ctx_p, C.c_void_p], C.c_int),
     "hfx_dims": ([_ctx_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hfx_core": ([_ctx_p, _dp, _dp, _dp], C.c_int),
     "hfx_schwarz": ([_ctx_p, _dp], C.c_int),
@@ -178,10 +184,51 @@ class Context:
         xyz = np.ascontiguousarray(f["xyz"], dtype=np.float64)
         self._check(hfx_load(self.ptr, f["natom"], Z.ctypes.data_as(C.POINTER(C.c_int)), _d(xyz), f["nshell"],
                              shells, charge))
+        self.layout = None
         nbf, nocc, nsh = C.c_int(), C.c_int(), C.c_int()
         self._check(hfx_dims(self.ptr, C.byref(nbf), C.byref(nocc), C.byref(nsh)))
         self.nbf, self.nocc, self.nshell = nbf.value, nocc.value, nsh.value
         return self
+
+    def load_batch(self, mols):
+        """Load independent molecules as one batch; returns self.  Layout in
+        self.layout = (nbf[], nocc[], offset[], total)."""
+        nat = np.array([m.natom for m in mols], dtype=np.int32)
+        nsh = np.array([m.nshell for m in mols], dtype=np.int32)
+        Z = np.ascontiguousarray(np.concatenate([m.Z for m in mols]).astype(np.int32))
+        xyz = np.ascontiguousarray(np.concatenate([m.xyz for m in mols]), dtype=np.float64)
+        shells = (hfx_shell * int(nsh.sum()))()
+        self._keep = []
+        i = 0
+        for m in mols:
+            for sh in m.shells:
+                ex = np.ascontiguousarray(sh.exps, dtype=np.float64)
+                co = np.ascontiguousarray(sh.coefs, dtype=np.float64)
+                self._keep += [ex, co]
+                shells[i].atom, shells[i].l, shells[i].nprim = int(sh.atom), int(sh.l), len(ex)
+                shells[i].exps, shells[i].coefs = _d(ex), _d(co)
+                i += 1
+        ip = C.POINTER(C.c_int)
+        self._check(hfx_load_batch(self.ptr, len(mols), nat.ctypes.data_as(ip), Z.ctypes.data_as(ip), _d(xyz),
+                                   nsh.ctypes.data_as(ip), shells, None))
+        nm = C.c_int()
+        nbf = np.zeros(len(mols), dtype=np.int32)
+        nocc = np.zeros(len(mols), dtype=np.int32)
+        off = np.zeros(len(mols), dtype=np.int64)
+        tot = C.c_longlong()
+        self._check(hfx_batch_layout(self.ptr, C.byref(nm), nbf.ctypes.data_as(ip), nocc.ctypes.data_as(ip),
+                                     off.ctypes.data_as(C.POINTER(C.c_longlong)), C.byref(tot)))
+        self.layout = (nbf, nocc, off, tot.value)
+        n1, n2, n3 = C.c_int(), C.c_int(), C.c_int()
+        self._check(hfx_dims(self.ptr, C.byref(n1), C.byref(n2), C.byref(n3)))
+        self.nbf, self.nocc, self.nshell = n1.value, n2.value, n3.value
+        return self
+
+    def graph_capture(self, dD_ptr: int, dF_ptr: int, stream: int):
+        self._check(hfx_graph_capture(self.ptr, C.c_void_p(dD_ptr), C.c_void_p(dF_ptr), C.c_void_p(stream)))
+
+    def graph_launch(self, stream: int):
+        self._check(hfx_graph_launch(self.ptr, C.c_void_p(stream)))
 
     def configure(self, **kw):
         for k, v in kw.items():
@@ -189,8 +236,14 @@ class Context:
         self._check(hfx_configure(self.ptr, C.byref(self.opt)))
 
     def core(self):
-        n = self.nbf
-        S, H, e = np.zeros((n, n)), np.zeros((n, n)), C.c_double()
+        """S, H (n x n for one molecule; ragged 1-D for a batch) and E_nuc."""
+        if getattr(self, "layout", None) is not None:
+            tot = self.layout[3]
+            S, H = np.zeros(tot), np.zeros(tot)
+        else:
+            n = self.nbf
+            S, H = np.zeros((n, n)), np.zeros((n, n))
+        e = C.c_double()
         self._check(hfx_core(self.ptr, _d(S), _d(H), C.byref(e)))
         return S, H, e.value
 
@@ -200,6 +253,7 @@ class Context:
         return Q
 
     def build_fock(self, D: np.ndarray):
+        """F from a host D (n x n, or the ragged 1-D layout for a batch)."""
         D = np.ascontiguousarray(D, dtype=np.float64)
         F = np.zeros_like(D)
         st = hfx_fock_stats()
