@@ -86,6 +86,74 @@ def cpu_baseline(mol, D, target_s=15.0):
                 seconds=dt2)
 
 
+def batched_bench(args, log):
+    """256 independent clusters of 1-16 waters (sizes seeded), one batched
+    build per step (one launch per quartet class and ket list for all of them)
+    vs the same 256 molecules built one context at a time; FP64, mixed and a
+    HIP-graph replay of the FP64 batched build.  Densities: per molecule an
+    orthogonal projector onto nocc random directions (the screened quartet set,
+    hence the FP64 work, does not depend on D)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1708_00033_amd import hfx, autotune
+    mols = W.cluster_batch(256, 2)
+    t0 = time.time()
+    bctx = hfx.Context(device=0).load_batch(mols)
+    t_load = time.time() - t0
+    nbf, nocc, off, tot = bctx.layout
+    Dh = np.concatenate([W.random_orthonormal_density(int(n), int(o), 1000 + i).ravel()
+                         for i, (n, o) in enumerate(zip(nbf, nocc))])
+    dev = torch.device("cuda:0")
+    D = torch.tensor(Dh, device=dev)
+    F = torch.empty_like(D)
+    stream = torch.cuda.Stream(dev)
+    sp = stream.cuda_stream
+    counts = bctx.class_counts()
+    quartets = int(counts[:, 0].sum())
+    with torch.cuda.stream(stream):
+        tuning = autotune.autotune(bctx, D.data_ptr(), F.data_ptr(), sp, sync=stream.synchronize)
+
+        def time_builds(fn, n):
+            fn()
+            stream.synchronize()
+            t = time.perf_counter()
+            for _ in range(n):
+                fn()
+            stream.synchronize()
+            return (time.perf_counter() - t) / n
+
+        bctx.configure(precision=hfx.HFX_PREC_FP64)
+        t64 = time_builds(lambda: bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp), args.steps)
+        F64 = F.clone()
+        bctx.graph_capture(D.data_ptr(), F.data_ptr(), sp)
+        tg = time_builds(lambda: bctx.graph_launch(sp), args.steps)
+        graph_err = (F - F64).abs().max().item()
+        bctx.configure(precision=hfx.HFX_PREC_MIXED)
+        tmx = time_builds(lambda: bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp), args.steps)
+        mixed_err = (F - F64).abs().max().item()
+        bctx.configure(precision=hfx.HFX_PREC_FP64)
+        # the same molecules one context (and one set of launches) at a time
+        ctxs = [hfx.Context(device=0).load(m) for m in mols]
+        Ds = [D[int(o):int(o) + int(n) * int(n)] for o, n in zip(off, nbf)]
+        Fs = [F[int(o):int(o) + int(n) * int(n)] for o, n in zip(off, nbf)]
+
+        def one_by_one():
+            for c, d, f in zip(ctxs, Ds, Fs):
+                c.build_fock_dev(d.data_ptr(), f.data_ptr(), sp)
+        tseq = time_builds(one_by_one, max(1, args.steps // 2))
+        seq_err = (F - F64).abs().max().item()
+    return {"workload": "256 water clusters, sizes ~U{1..16} (seed 2), molecule i seed 2e6+i, s/p/d basis",
+            "molecules": len(mols), "basis_functions": int(nbf.sum()), "quartets_per_build": quartets,
+            "load_s": t_load,
+            "fp64_ms": t64 * 1e3, "fp64_quartets_per_s": quartets / t64,
+            "graph_replay_ms": tg * 1e3, "graph_max_abs_diff": graph_err,
+            "mixed_ms": tmx * 1e3, "mixed_quartets_per_s": quartets / tmx, "mixed_max_abs_dF": mixed_err,
+            "one_context_per_molecule_ms": tseq * 1e3, "one_context_per_molecule_max_abs_diff": seq_err,
+            "speedup_batched_vs_one_by_one": tseq / t64, "speedup_mixed_vs_fp64": t64 / tmx,
+            "autotune": {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +163,7 @@ def main():
     ap.add_argument("--digest", type=int, default=0)
     ap.add_argument("--task", type=int, default=8192)
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
     ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
     ap.add_argument("--profile", action="store_true",
@@ -236,6 +305,9 @@ def main():
         "scf": {"energy": r["energy"], "iterations": r["iterations"]},
         "autotune": None if tuning is None else {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()},
     }
+    if not args.no_batch:
+        log("batched builds: 256 clusters of 1-16 waters ...")
+        res["batched"] = batched_bench(args, log)
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
