@@ -123,15 +123,27 @@ def batched_bench(args, log):
             stream.synchronize()
             return (time.perf_counter() - t) / n
 
+        def class_ms():
+            bctx.kernel_timing(True)
+            bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp)
+            stream.synchronize()
+            ms, _ = bctx.kernel_times()
+            bctx.kernel_timing(False)
+            order = np.argsort(-ms)[:8]
+            return {hfx.CLASS_NAMES[k]: round(float(ms[k]), 3) for k in order}
+
         bctx.configure(precision=hfx.HFX_PREC_FP64)
         t64 = time_builds(lambda: bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp), args.steps)
         F64 = F.clone()
+        cms64 = class_ms()
         bctx.graph_capture(D.data_ptr(), F.data_ptr(), sp)
         tg = time_builds(lambda: bctx.graph_launch(sp), args.steps)
         graph_err = (F - F64).abs().max().item()
         bctx.configure(precision=hfx.HFX_PREC_MIXED)
         tmx = time_builds(lambda: bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp), args.steps)
         mixed_err = (F - F64).abs().max().item()
+        cmsmx = class_ms()
+        stm = bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp, stats=True)
         bctx.configure(precision=hfx.HFX_PREC_FP64)
         # the same molecules one context (and one set of launches) at a time
         ctxs = [hfx.Context(device=0).load(m) for m in mols]
@@ -151,6 +163,8 @@ def batched_bench(args, log):
             "mixed_ms": tmx * 1e3, "mixed_quartets_per_s": quartets / tmx, "mixed_max_abs_dF": mixed_err,
             "one_context_per_molecule_ms": tseq * 1e3, "one_context_per_molecule_max_abs_diff": seq_err,
             "speedup_batched_vs_one_by_one": tseq / t64, "speedup_mixed_vs_fp64": t64 / tmx,
+            "class_ms_fp64": cms64, "class_ms_mixed": cmsmx,
+            "mixed_quartets_fp32": int(stm.quartets_fp32), "mixed_quartets_fp64": int(stm.quartets_fp64),
             "autotune": {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()}}
 
 
@@ -193,9 +207,11 @@ def main():
         D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 3), device=dev)
         F = torch.empty_like(D)
         sptr = torch.cuda.current_stream(dev).cuda_stream
+        from paper_1708_00033_amd import autotune
         if args.tuning:
-            from paper_1708_00033_amd import autotune
             autotune.apply(ctx, autotune.load(args.tuning))
+        else:
+            ctx.set_class_tuning(-1, *autotune.PREFERRED)
         for _ in range(args.warmup + args.steps):
             ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sptr)
         torch.cuda.synchronize()
@@ -262,7 +278,7 @@ def main():
     flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    kname = f"k_class<Eval{dom['cls']}, {dom['mode']}, 0> grid {dom['tasks'] * 256}"
+    kname = f"k_class<Eval{dom['cls']}, {dom['mode']}, 0> grid {dom['tasks'] * dom['wgs']}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
     prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")

@@ -197,10 +197,11 @@ hfx_status hfx_class_counts(const hfx_ctx *ctx, long long *counts);
 hfx_status hfx_kernel_timing(hfx_ctx *ctx, int enable);
 hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 
-/* Launches of a build: one per (quartet class, ket primitive count).  info[8]
- * = {class index, ket primitives per pair, workgroup tasks (grid = 256 x
- * tasks), unique quartets, primitive quartets, integrals, timed launches,
- * digestion mode}; *ms = summed event time of the timed launches. */
+/* Launches of a build: one per (quartet class, ket primitive count).  info[9]
+ * = {class index, ket primitives per pair, workgroups (one task each),
+ * unique quartets, primitive quartets, integrals, timed launches, digestion
+ * mode, work-items per workgroup}; *ms = summed event time of the timed
+ * launches. */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 

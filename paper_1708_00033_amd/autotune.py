@@ -20,10 +20,17 @@ DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = (
     (2048, 0), (2048, 1), (8192, 0), (8192, 1), (32768, 0), (32768, 1))
 
 
+PREFERRED: Tuple[int, int] = (32768, 0)
+
+
 def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
              candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, reps: int = 2,
-             sync=None) -> Dict[str, dict]:
-    """Return {class name: {"task_quartets", "xcd_stripe", "ms", "candidates_ms"}}."""
+             sync=None, prefer: Tuple[int, int] = PREFERRED, margin: float = 0.03) -> Dict[str, dict]:
+    """Return {class name: {"task_quartets", "xcd_stripe", "ms", "candidates_ms"}}.
+
+    A class keeps the ``prefer`` setting (when it is a candidate) unless another
+    candidate is faster by more than ``margin`` (relative): timing noise then
+    does not flip the launch shape from one run to the next."""
     if sync is None:
         import torch
         sync = torch.cuda.synchronize
@@ -42,6 +49,10 @@ def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
     table = {}
     for k in range(21):
         best = int(np.argmin(times[:, k]))
+        if tuple(prefer) in [tuple(c) for c in candidates]:
+            pi = [tuple(c) for c in candidates].index(tuple(prefer))
+            if times[pi, k] <= times[best, k] * (1.0 + margin):
+                best = pi
         tq, st = candidates[best]
         table[hfx.CLASS_NAMES[k]] = {"task_quartets": int(tq), "xcd_stripe": int(st),
                                       "ms": float(times[best, k]),

@@ -856,6 +856,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[5] = p.integrals;
     info[6] = p.launches;
     info[7] = p.mode;
+    info[8] = hfx_class_wgs(p.cid);
     if (ms) *ms = p.ms;
     return HFX_OK;
 }

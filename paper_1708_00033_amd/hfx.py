@@ -317,17 +317,17 @@ class Context:
         self._check(hfx_kernel_timing(self.ptr, int(enable)))
 
     def plans(self):
-        """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, ms)."""
+        """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, wgs, ms)."""
         n = C.c_int()
         self._check(hfx_plan_count(self.ptr, C.byref(n)))
         out = []
         for i in range(n.value):
-            info = (C.c_longlong * 8)()
+            info = (C.c_longlong * 9)()
             ms = C.c_double()
             self._check(hfx_plan_info(self.ptr, i, info, C.byref(ms)))
             out.append(dict(cls=int(info[0]), ket_nprim=int(info[1]), tasks=int(info[2]), quartets=int(info[3]),
                             prim=int(info[4]), integrals=int(info[5]), launches=int(info[6]), mode=int(info[7]),
-                            ms=ms.value))
+                            wgs=int(info[8]), ms=ms.value))
         return out
 
     def kernel_times(self):
