@@ -65,13 +65,19 @@ typedef struct {
 
 enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 };
 enum { HFX_DIGEST_LDS = 0, HFX_DIGEST_GLOBAL = 1 };
-enum { HFX_GUESS_SAD = 0, HFX_GUESS_CORE = 1 };
+enum { HFX_GUESS_SAD = 0, HFX_GUESS_CORE = 1, HFX_GUESS_LEARNED = 2 };
+
+/* Learned initial-guess network (see the section "Learned initial guess"). */
+typedef struct hfx_guess hfx_guess;
 
 typedef struct {
     int device;            /* HIP device ordinal */
     double schwarz_tau;    /* quartet kept iff Q_ab Q_cd >= tau (default 1e-10) */
     int precision;         /* HFX_PREC_FP64 or HFX_PREC_MIXED */
-    double fp32_tau;       /* MIXED: FP32 iff Q_ab Q_cd max|D| < fp32_tau (default 1e-7) */
+    double fp32_tau;       /* MIXED: a quartet may be evaluated in FP32 only if
+                              Q_ab Q_cd max|D| < fp32_tau (default 1e-7); the
+                              choice is made per 64 consecutive kets of a bra
+                              (one wavefront), FP64 unless all of them qualify */
     int digest;            /* HFX_DIGEST_LDS (bra rows staged in LDS) or HFX_DIGEST_GLOBAL */
     int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
@@ -82,9 +88,11 @@ typedef struct {
     double e_tol;          /* |E_k - E_{k-1}| < e_tol (default 1e-8) */
     double d_rms_tol;      /* and rms(D_{k+1} - D_k) < d_rms_tol (default 1e-7) */
     int diis_max;          /* Pulay DIIS subspace (default 8; 0 disables) */
-    int guess;             /* HFX_GUESS_SAD or HFX_GUESS_CORE */
+    int guess;             /* HFX_GUESS_SAD, HFX_GUESS_CORE or HFX_GUESS_LEARNED */
     const double *D0;      /* optional host nbf x nbf restart density (NULL: use guess) */
     double lindep;         /* S eigenvalues below this are dropped (default 1e-7) */
+    hfx_guess *model;      /* HFX_GUESS_LEARNED: the network (SAD when its
+                              prediction is rejected, see hfx_guess_apply) */
 } hfx_scf_options;
 
 typedef struct {
@@ -204,6 +212,77 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
  * launches. */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
+
+/* Superposition-of-atomic-densities guess of the loaded molecule (the SCF
+ * default start): host nbf x nbf out. */
+hfx_status hfx_sad_density(hfx_ctx *ctx, double *D);
+
+/* ---- Learned initial guess --------------------------------------------------
+ * An extension of the SCF start (the paper's SCF of section 3 starts from a
+ * core-Hamiltonian path): a network predicts, for every atom pair within
+ * 6 A (A = B included), the converged-minus-SAD density block in a local
+ * frame of the pair; the blocks are rotated back and added to SAD.
+ * Molecules of O and H only, with 15 basis functions per O and 2 per H.
+ *
+ * Pairs: A <= B in (element O before H, atom index) order, sorted by type
+ * (0 O-O, 1 O-H, 2 H-H), then A, then B.  Frame of a pair: z from A to B (for
+ * A = B toward A's nearest atom), x toward the nearest atom C (distance in
+ * 1e-6 bohr bins, then index) whose direction from A is not within
+ * sin 0.1 of z, y = z x x; without such a C, x from the global axis least
+ * aligned with z.  Local block P = T_A(R^T)^T D_AB T_B(R^T) where T(R)
+ * rotates the atom's Cartesian s, p and unit-normalised d functions; packed
+ * FP32 blocks: every pair's na x nb row-major block in pair order (type 0
+ * rows are 225 floats, type 1 30, type 2 4).
+ * Features: 164 FP32 per pair = one-hot element of A (O, H), of B, 32 radial
+ * Gaussians exp(-eta (R_AB - mu_k)^2) fc(R_AB) (mu_k = 0.5 .. 6 A in 31
+ * steps, eta = 1 / (2 dmu^2), fc = (cos(pi R / 6 A) + 1) / 2), then the
+ * environments of A and of B (for O then H neighbours: the radial functions
+ * summed over the atoms of that element other than the atom itself). */
+
+/* Pair list, frames and features of the loaded single molecule (device,
+ * owned by ctx until the next load).  counts[3] (optional): pairs per type. */
+hfx_status hfx_guess_setup(hfx_ctx *ctx, int *counts);
+/* Host copies (each optional): X npair x 164, pairs npair x 2 atom indices,
+ * frames npair x 9 (rows x, y, z). */
+hfx_status hfx_guess_features(hfx_ctx *ctx, float *X, int *pairs, double *frames);
+/* Device pointer to the features (owned by ctx). */
+hfx_status hfx_guess_features_dev(hfx_ctx *ctx, const float **dX);
+/* dT = packed local blocks of dD - dDbase (dDbase may be NULL): training targets. */
+hfx_status hfx_guess_targets_dev(hfx_ctx *ctx, const double *dD, const double *dDbase, float *dT, void *stream);
+/* dD = dDbase + the packed blocks dT rotated back into the molecule (each
+ * pair's block at (A, B) and its transpose at (B, A); a self block is
+ * symmetrised first).  dDbase NULL: add to dD in place. */
+hfx_status hfx_guess_assemble_dev(hfx_ctx *ctx, const float *dT, const double *dDbase, double *dD, void *stream);
+
+/* Network: 164 -> 256 -> 256 -> 256 (SiLU) -> per pair type a linear head of
+ * 225 / 30 / 4 outputs, BF16 MFMA with FP32 accumulation.  Parameters (FP32,
+ * packed): W1[256x164] b1[256] W2[256x256] b2 W3[256x256] b3, heads
+ * H0[225x256] c0 H1[30x256] c1 H2[4x256] c2 (W: out x in, row-major), then
+ * the feature mean[164], feature scale[164] and target scales[3]: input
+ * (x - mean) / scale, block = output x target scale of the pair's type. */
+hfx_status hfx_guess_create(int device, hfx_guess **out);
+void hfx_guess_destroy(hfx_guess *g);
+long long hfx_guess_param_count(void);
+hfx_status hfx_guess_set_params(hfx_guess *g, const float *params);   /* host */
+hfx_status hfx_guess_get_params(hfx_guess *g, float *params);         /* host */
+/* Gradient of the last hfx_guess_grad_dev, packed like the parameters
+ * (zeros for the mean, scale and target-scale entries). */
+hfx_status hfx_guess_get_grads(hfx_guess *g, float *grads);
+/* dX: rows grouped by type (counts[t] rows of type t, 164 FP32 each);
+ * dT: packed blocks (forward: written; grad: the targets). */
+hfx_status hfx_guess_forward_dev(hfx_guess *g, const float *dX, const int *counts, float *dT, void *stream);
+/* Loss = mean over all block elements of (output - target / target scale)^2;
+ * computes the gradient (synchronises the stream when loss != NULL). */
+hfx_status hfx_guess_grad_dev(hfx_guess *g, const float *dX, const int *counts, const float *dT, void *stream,
+                              double *loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on the weights
+ * and biases with the last gradient. */
+hfx_status hfx_guess_adam(hfx_guess *g, double lr, void *stream);
+/* dD (device, in/out): a base density (SAD) on entry, base + prediction on
+ * return; *used = 0 and dD unchanged when the prediction is not finite or
+ * |tr(D S) - nocc| > 0.05 nocc.  Synchronises the stream. */
+hfx_status hfx_guess_apply(hfx_ctx *ctx, hfx_guess *g, double *dD, void *stream, int *used);
+const char *hfx_guess_last_error(const hfx_guess *g);
 
 const char *hfx_last_error(const hfx_ctx *ctx);
 void hfx_destroy(hfx_ctx *ctx);

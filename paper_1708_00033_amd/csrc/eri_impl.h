@@ -298,8 +298,9 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One class, one digestion mode, one precision policy (MIXED = 1: kets at or
-// beyond split[r] are evaluated in FP32 and widened before digestion).
+// One class, one digestion mode, one precision policy (MIXED = 1: waves whose
+// kets all lie at or beyond split[r] are evaluated in FP32 and widened before
+// digestion).
 template <class E, int MODE, int MIXED>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
@@ -349,7 +350,10 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
             continue;
         }
         double I[NI];
-        if (!MIXED || s < split) {
+        // precision per wavefront: FP32 only when every ket of the wave lies
+        // at or beyond the split (no divergent FP64/FP32 waves)
+        const int wave_first = __builtin_amdgcn_readfirstlane(s - (int)(threadIdx.x & 63));
+        if (!MIXED || wave_first < split) {
             E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
                                     ket.AB, a.boys64, I);
             ++n64;

@@ -77,6 +77,7 @@ extern "C" hfx_status hfx_default_scf_options(hfx_scf_options* o) {
     o->guess = HFX_GUESS_SAD;
     o->D0 = nullptr;
     o->lindep = 1e-7;
+    o->model = nullptr;
     return HFX_OK;
 }
 
@@ -97,6 +98,7 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
 // ---- lifetime ------------------------------------------------------------------------
 
 static void release_system(hfx_ctx* c) {
+    hfx_guess_release(c);
     if (c->graph_exec) {
         (void)hipGraphExecDestroy(c->graph_exec);
         c->graph_exec = nullptr;

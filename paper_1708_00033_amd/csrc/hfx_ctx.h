@@ -59,6 +59,8 @@ struct MolInfo {
     double enuc = 0.0;
 };
 
+struct GuessPairsDev;   // learned-guess pair data (guess.hip)
+
 struct hfx_ctx {
     hfx_options opt{};
     std::string err;
@@ -109,10 +111,14 @@ struct hfx_ctx {
     int* d_bad = nullptr;
     rocblas_handle blas = nullptr;
     hipGraphExec_t graph_exec = nullptr;   // captured build (hfx_graph_capture)
+    GuessPairsDev* guess = nullptr;        // hfx_guess_setup
     // timing
     bool timing = false;
     hipStream_t last_stream = nullptr;
 };
+
+// implemented in guess.hip
+void hfx_guess_release(hfx_ctx* c);
 
 // implemented in hfx_api.cpp
 hfx_status hfx_fail(hfx_ctx* c, hfx_status s, const std::string& msg);

@@ -447,6 +447,18 @@ static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
     return HFX_OK;
 }
 
+extern "C" hfx_status hfx_sad_density(hfx_ctx* c, double* D_out) {
+    if (!c || !D_out) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_sad_density: nothing loaded");
+    if (c->nmol != 1) return hfx_fail(c, HFX_ERR_STATE, "hfx_sad_density: single molecules only");
+    HIPCK(hipSetDevice(c->opt.device));
+    std::vector<double> Ds;
+    hfx_status s = sad_guess(c, Ds);
+    if (s != HFX_OK) return s;
+    std::memcpy(D_out, Ds.data(), Ds.size() * sizeof(double));
+    return HFX_OK;
+}
+
 extern "C" hfx_status hfx_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_result* res, double* D_out,
                               double* C_out, double* eps_out) {
     if (!c || !res) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
@@ -472,11 +484,19 @@ extern "C" hfx_status hfx_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_re
         guess_used = -1;
     } else if (o.guess == HFX_GUESS_CORE) {
         core = true;
-    } else if (o.guess == HFX_GUESS_SAD) {
+    } else if (o.guess == HFX_GUESS_SAD || o.guess == HFX_GUESS_LEARNED) {
+        if (o.guess == HFX_GUESS_LEARNED && !o.model)
+            return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_scf: learned guess without a model");
         std::vector<double> Ds;
         hfx_status s = sad_guess(c, Ds);
         if (s != HFX_OK) return s;
         HIPCK(hipMemcpy(D.p, Ds.data(), nn * 8, hipMemcpyHostToDevice));
+        if (o.guess == HFX_GUESS_LEARNED) {
+            int used = 0;
+            s = hfx_guess_apply(c, o.model, D.p, nullptr, &used);
+            if (s != HFX_OK) return s;
+            if (!used) guess_used = HFX_GUESS_SAD;   // prediction rejected: SAD fallback
+        }
     } else {
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_scf: unknown guess");
     }

@@ -41,7 +41,9 @@ STATUS_NAMES = {0: "HFX_OK", 1: "HFX_ERR_INVALID_ARG", 2: "HFX_ERR_OOM", 3: "HFX
                 4: "HFX_ERR_NOT_CONVERGED", 5: "HFX_ERR_NUMERICAL", 6: "HFX_ERR_STATE"}
 HFX_PREC_FP64, HFX_PREC_MIXED = 0, 1
 HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL = 0, 1
-HFX_GUESS_SAD, HFX_GUESS_CORE = 0, 1
+HFX_GUESS_SAD, HFX_GUESS_CORE, HFX_GUESS_LEARNED = 0, 1, 2
+GUESS_NFEAT = 164
+GUESS_HEAD_OUT = (225, 30, 4)
 
 CLASS_NAMES = [f"({b}|{k})" for bi, b in enumerate(["ss", "ps", "pp", "ds", "dp", "dd"])
                for k in ["ss", "ps", "pp", "ds", "dp", "dd"][:bi + 1]]
@@ -61,7 +63,7 @@ class hfx_options(C.Structure):
 class hfx_scf_options(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("e_tol", C.c_double), ("d_rms_tol", C.c_double),
                 ("diis_max", C.c_int), ("guess", C.c_int), ("D0", C.POINTER(C.c_double)),
-                ("lindep", C.c_double)]
+                ("lindep", C.c_double), ("model", C.c_void_p)]
 
 
 class hfx_scf_result(C.Structure):
@@ -105,6 +107,24 @@ _sigs = {
     "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_plan_count": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
     "hfx_plan_info": ([_ctx_p, C.c_int, C.POINTER(C.c_longlong), _dp], C.c_int),
+    "hfx_sad_density": ([_ctx_p, _dp], C.c_int),
+    "hfx_guess_setup": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
+    "hfx_guess_features": ([_ctx_p, C.POINTER(C.c_float), C.POINTER(C.c_int), _dp], C.c_int),
+    "hfx_guess_features_dev": ([_ctx_p, C.POINTER(C.c_void_p)], C.c_int),
+    "hfx_guess_targets_dev": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hfx_guess_assemble_dev": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hfx_guess_create": ([C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "hfx_guess_destroy": ([C.c_void_p], None),
+    "hfx_guess_param_count": ([], C.c_longlong),
+    "hfx_guess_set_params": ([C.c_void_p, C.POINTER(C.c_float)], C.c_int),
+    "hfx_guess_get_params": ([C.c_void_p, C.POINTER(C.c_float)], C.c_int),
+    "hfx_guess_get_grads": ([C.c_void_p, C.POINTER(C.c_float)], C.c_int),
+    "hfx_guess_forward_dev": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p], C.c_int),
+    "hfx_guess_grad_dev": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p,
+                            C.POINTER(C.c_double)], C.c_int),
+    "hfx_guess_adam": ([C.c_void_p, C.c_double, C.c_void_p], C.c_int),
+    "hfx_guess_apply": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)], C.c_int),
+    "hfx_guess_last_error": ([C.c_void_p], C.c_char_p),
     "hfx_last_error": ([_ctx_p], C.c_char_p),
     "hfx_destroy": ([_ctx_p], None),
 }
@@ -277,8 +297,12 @@ class Context:
         self._check(hfx_build_2e_shard_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, shard, nshards, C.c_void_p(dG_ptr),
                                            C.c_void_p(stream)))
 
-    def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, **kw):
+    def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, model: "GuessNet" = None, **kw):
         o = default_scf_options(**kw)
+        if model is not None:
+            o.model = model.ptr
+            if "guess" not in kw:
+                o.guess = HFX_GUESS_LEARNED
         keep = None
         if D0 is not None:
             keep = np.ascontiguousarray(D0, dtype=np.float64)
@@ -298,6 +322,51 @@ class Context:
         if want_c:
             out["C"] = Cm.reshape(-1)[: n * nmo].reshape(n, nmo)
         return out
+
+    # ---- learned initial guess ----
+    def sad_density(self) -> np.ndarray:
+        D = np.zeros((self.nbf, self.nbf))
+        self._check(hfx_sad_density(self.ptr, _d(D)))
+        return D
+
+    def guess_setup(self):
+        """Pair list, frames and features on the device; returns counts per
+        pair type (O-O, O-H, H-H)."""
+        c = (C.c_int * 3)()
+        self._check(hfx_guess_setup(self.ptr, c))
+        self.guess_counts = tuple(int(x) for x in c)
+        return self.guess_counts
+
+    def guess_features(self):
+        """Host copies: X (npair, 164) float32, pairs (npair, 2), frames (npair, 3, 3)."""
+        n = sum(self.guess_counts)
+        X = np.zeros((n, GUESS_NFEAT), dtype=np.float32)
+        P = np.zeros((n, 2), dtype=np.int32)
+        R = np.zeros((n, 3, 3))
+        self._check(hfx_guess_features(self.ptr, X.ctypes.data_as(C.POINTER(C.c_float)),
+                                       P.ctypes.data_as(C.POINTER(C.c_int)), _d(R)))
+        return X, P, R
+
+    def guess_features_dev(self) -> int:
+        p = C.c_void_p()
+        self._check(hfx_guess_features_dev(self.ptr, C.byref(p)))
+        return p.value
+
+    def guess_packed_size(self) -> int:
+        return sum(c * n for c, n in zip(self.guess_counts, GUESS_HEAD_OUT))
+
+    def guess_targets_dev(self, dD_ptr: int, dDbase_ptr: int, dT_ptr: int, stream: int = 0):
+        self._check(hfx_guess_targets_dev(self.ptr, C.c_void_p(dD_ptr), C.c_void_p(dDbase_ptr or None),
+                                          C.c_void_p(dT_ptr), C.c_void_p(stream)))
+
+    def guess_assemble_dev(self, dT_ptr: int, dDbase_ptr: int, dD_ptr: int, stream: int = 0):
+        self._check(hfx_guess_assemble_dev(self.ptr, C.c_void_p(dT_ptr), C.c_void_p(dDbase_ptr or None),
+                                           C.c_void_p(dD_ptr), C.c_void_p(stream)))
+
+    def guess_apply(self, model: "GuessNet", dD_ptr: int, stream: int = 0) -> bool:
+        used = C.c_int()
+        self._check(hfx_guess_apply(self.ptr, model.ptr, C.c_void_p(dD_ptr), C.c_void_p(stream), C.byref(used)))
+        return bool(used.value)
 
     def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1):
         self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe))
@@ -335,3 +404,93 @@ class Context:
         n = np.zeros(21, dtype=np.int64)
         self._check(hfx_kernel_times(self.ptr, _d(ms), n.ctypes.data_as(C.POINTER(C.c_longlong))))
         return ms, n
+
+
+class GuessNet:
+    """The learned-guess network (hfx_guess): parameters, BF16 MFMA forward
+    and gradient, Adam.  Parameters are a packed float32 vector of
+    ``param_count()`` entries (layout in include/hfx.h)."""
+
+    def __init__(self, device: int = 0, params: Optional[np.ndarray] = None):
+        self.ptr = C.c_void_p()
+        st = hfx_guess_create(device, C.byref(self.ptr))
+        if st != HFX_OK:
+            raise HfxError(st, "hfx_guess_create failed")
+        if params is not None:
+            self.set_params(params)
+
+    @staticmethod
+    def param_count() -> int:
+        return int(hfx_guess_param_count())
+
+    # packed layout of include/hfx.h: (name, rows, cols)
+    LAYOUT = (("W1", 256, GUESS_NFEAT), ("b1", 256, 1), ("W2", 256, 256), ("b2", 256, 1), ("W3", 256, 256),
+              ("b3", 256, 1), ("H0", 225, 256), ("c0", 225, 1), ("H1", 30, 256), ("c1", 30, 1), ("H2", 4, 256),
+              ("c2", 4, 1), ("fmean", GUESS_NFEAT, 1), ("fscale", GUESS_NFEAT, 1), ("tscale", 3, 1))
+
+    @classmethod
+    def init_params(cls, seed: int, fmean, fscale, tscale) -> np.ndarray:
+        """Seeded start: uniform(+-sqrt(6 / fan_in)) hidden weights, heads ten
+        times smaller, zero biases, and the given input / target scalers."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for name, r, c in cls.LAYOUT:
+            if name[0] in "WH":
+                lim = np.sqrt(6.0 / c) * (0.1 if name[0] == "H" else 1.0)
+                parts.append(rng.uniform(-lim, lim, size=r * c))
+            elif name == "fmean":
+                parts.append(np.asarray(fmean, float).ravel())
+            elif name == "fscale":
+                parts.append(np.asarray(fscale, float).ravel())
+            elif name == "tscale":
+                parts.append(np.asarray(tscale, float).ravel())
+            else:
+                parts.append(np.zeros(r * c))
+        out = np.concatenate(parts).astype(np.float32)
+        assert out.size == cls.param_count()
+        return out
+
+    def _check(self, st: int):
+        if st != HFX_OK:
+            raise HfxError(st, hfx_guess_last_error(self.ptr).decode())
+
+    def close(self):
+        if self.ptr:
+            hfx_guess_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.param_count():
+            raise ValueError(f"expected {self.param_count()} parameters, got {p.size}")
+        self._check(hfx_guess_set_params(self.ptr, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.param_count(), dtype=np.float32)
+        self._check(hfx_guess_get_params(self.ptr, p.ctypes.data_as(C.POINTER(C.c_float))))
+        return p
+
+    def get_grads(self) -> np.ndarray:
+        p = np.zeros(self.param_count(), dtype=np.float32)
+        self._check(hfx_guess_get_grads(self.ptr, p.ctypes.data_as(C.POINTER(C.c_float))))
+        return p
+
+    def forward_dev(self, dX_ptr: int, counts, dT_ptr: int, stream: int = 0):
+        c = (C.c_int * 3)(*[int(x) for x in counts])
+        self._check(hfx_guess_forward_dev(self.ptr, C.c_void_p(dX_ptr), c, C.c_void_p(dT_ptr), C.c_void_p(stream)))
+
+    def grad_dev(self, dX_ptr: int, counts, dT_ptr: int, stream: int = 0, want_loss: bool = True):
+        c = (C.c_int * 3)(*[int(x) for x in counts])
+        loss = C.c_double()
+        self._check(hfx_guess_grad_dev(self.ptr, C.c_void_p(dX_ptr), c, C.c_void_p(dT_ptr), C.c_void_p(stream),
+                                       C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def adam(self, lr: float, stream: int = 0):
+        self._check(hfx_guess_adam(self.ptr, float(lr), C.c_void_p(stream)))

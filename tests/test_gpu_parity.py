@@ -112,10 +112,23 @@ def test_mixed_precision_dimer(dimer):
     ctx = _hfx().Context(precision=1).load(m)
     F, st = ctx.build_fock(r64["D"])
     F64, _ = ctx64.build_fock(r64["D"])
-    assert st.quartets_fp32 > 0
+    assert st.quartets_fp32 + st.quartets_fp64 == 14706
     assert np.abs(F - F64).max() < 1e-5
     r = ctx.scf(e_tol=1e-10, d_rms_tol=1e-8)
     assert abs(r["energy"] - r64["energy"]) < 1e-6
+
+
+def test_mixed_precision_wavefronts_16_waters():
+    """FP32 is chosen per wavefront of kets; a 16-water cluster has long ket
+    runs beyond the split, so a large share goes FP32, within tolerance."""
+    m = W.water_cluster(16, 77)
+    D = W.random_orthonormal_density(m.nbf, m.nocc, 5)
+    F64, s64 = _hfx().Context().load(m).build_fock(D)
+    Fmx, smx = _hfx().Context(precision=1).load(m).build_fock(D)
+    assert smx.quartets_fp32 + smx.quartets_fp64 == s64.quartets_fp64
+    assert smx.quartets_fp32 > 0.2 * s64.quartets_fp64
+    assert np.abs(Fmx - F64).max() < 1e-6
+    assert abs(np.sum(D * (Fmx - F64))) < 1e-6
 
 
 def test_invalid_inputs():
