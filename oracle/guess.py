@@ -10,16 +10,19 @@ in the paper).  What it computes, in this module's plain form:
 * atom pairs (A, B) within 6 A (A = B included), ordered O before H, then by
   atom index; pair type 0 = O-O, 1 = O-H, 2 = H-H;
 * a 164-number descriptor per pair: one-hot elements of A and B, 32 radial
-  Gaussians of R_AB with a cosine cutoff, and each atom's environment (the
-  same radial functions summed over its neighbours, per element);
+  Gaussians of R_AB with a cosine cutoff, and each atom's environment
+  (log(1 + the same radial functions summed over its neighbours), per
+  element: the logarithm keeps highly coordinated atoms near the range of
+  the small training clusters);
 * a right-handed local frame per pair (z from A to B; x toward the nearest
   non-collinear neighbour of A) and the matrices that rotate Cartesian
   s, p and unit-normalised d functions into it;
 * the density block of the pair in that frame, P = T_A^-T D_AB T_B^-1, so
   that D_AB = T_A^T P T_B;
 * a multilayer perceptron (164 -> 256 -> 256 -> 256 with SiLU, then one
-  linear head per pair type: 225, 30 or 4 outputs = the block) trained with
-  the mean squared error and Adam.
+  linear head per pair type: 225, 30 or 4 outputs = the block) on inputs
+  standardised with the stored mean and scale and clipped to +-4, trained
+  with the mean squared error and Adam.
 
 Parity of every function here is pinned by tests of its own: the rotation
 matrices against direct evaluation of the rotated functions, frame
@@ -45,6 +48,7 @@ NTYPE = 3
 # distance ties (equal O-H bonds) are broken by atom index below this
 TIE_BOHR = 1e-6
 NONCOLLINEAR_SIN = 0.1
+INPUT_CLIP = 4.0
 
 
 def element_index(z: int) -> int:
@@ -94,7 +98,8 @@ def pair_list(mol):
 
 def features(mol, pairs) -> np.ndarray:
     """(npair, 164) descriptors: [onehot A, onehot B, G(R_AB), env_A, env_B],
-    env_X = sum over atoms C != X of G(R_XC), one 32-block per element of C."""
+    env_X = log(1 + sum over atoms C != X of G(R_XC)), one 32-block per
+    element of C."""
     n = mol.natom
     env = np.zeros((n, 2 * NRAD))
     for x in range(n):
@@ -104,6 +109,7 @@ def features(mol, pairs) -> np.ndarray:
             r = np.linalg.norm(mol.xyz[x] - mol.xyz[c]) / BOHR_PER_ANGSTROM
             e = element_index(mol.Z[c])
             env[x, e * NRAD:(e + 1) * NRAD] += radial(r)
+    env = np.log1p(env)
     X = np.zeros((len(pairs), NFEAT))
     for i, (a, b, _) in enumerate(pairs):
         X[i, element_index(mol.Z[a])] = 1.0
@@ -288,7 +294,7 @@ def dsilu(z):
 def forward(p, X, counts, keep=False):
     """Rows of X are grouped by pair type (counts[t] rows of type t).
     Returns the scaled outputs per type [Y_t] (block = Y_t * tscale[t])."""
-    h = (np.asarray(X, float) - p["fmean"]) / p["fscale"]
+    h = np.clip((np.asarray(X, float) - p["fmean"]) / p["fscale"], -INPUT_CLIP, INPUT_CLIP)
     hs, zs = [h], []
     for k in (1, 2, 3):
         z = hs[-1] @ p[f"W{k}"].T + p[f"b{k}"]

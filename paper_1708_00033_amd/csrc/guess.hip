@@ -7,8 +7,8 @@
 // atom pair within 6 A, the converged-minus-SAD density block in a local frame
 // of the pair, from a 164-number descriptor of the pair's surroundings:
 //   [one-hot element of A, of B, 32 radial Gaussians of R_AB with a cosine
-//    cutoff, A's environment (the radial functions summed over neighbours,
-//    one 32-block per element), B's environment].
+//    cutoff, A's environment (log(1 + the radial functions summed over
+//    neighbours), one 32-block per element), B's environment].
 // Network: 164 -> 256 -> 256 -> 256 (SiLU) -> one linear head per pair type
 // (O-O 225, O-H 30, H-H 4 outputs = the 15 x 15, 15 x 2, 2 x 2 blocks).
 // Layers run as MFMA GEMMs (v_mfma_f32_16x16x32_bf16): BF16 operands, FP32
@@ -34,6 +34,7 @@ constexpr double BOHR_PER_A = 1.0 / 0.529177210903;
 constexpr double RCUT_A = 6.0;
 constexpr double TIE_BOHR = 1e-6;
 constexpr double NONCOLLINEAR_SIN = 0.1;
+constexpr float INPUT_CLIP = 4.0f;       // standardised inputs are clipped to +-INPUT_CLIP
 
 typedef unsigned short bf16_t;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -94,7 +95,7 @@ __device__ __forceinline__ double dist(const double* xyz, int a, int b) {
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-// env[a][e*32 + k] = sum over atoms c != a of element e of G_k(R_ac);
+// env[a][e*32 + k] = log(1 + sum over atoms c != a of element e of G_k(R_ac));
 // one thread per (atom, e, k)
 __global__ void k_env(int natom, const double* __restrict__ xyz, const int* __restrict__ elem, double* __restrict__ env) {
     const long long i = (long long)blockIdx.x * WG + threadIdx.x;
@@ -109,7 +110,7 @@ __global__ void k_env(int natom, const double* __restrict__ xyz, const int* __re
         const double d = r - mu;
         acc += exp(-eta * d * d) * 0.5 * (cos(M_PI * r / RCUT_A) + 1.0);
     }
-    env[i] = acc;
+    env[i] = log1p(acc);
 }
 
 // ordering key of candidate atoms: distance in bins of TIE_BOHR, then index
@@ -399,14 +400,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs g) {
             }
 }
 
-// standardised features as BF16 rows of XLD (zero padding)
+// standardised, clipped features as BF16 rows of XLD (zero padding)
 __global__ void k_feat_bf16(const float* __restrict__ X, long long M, const float* __restrict__ mean,
                             const float* __restrict__ scale, bf16_t* __restrict__ out) {
     const long long i = (long long)blockIdx.x * WG + threadIdx.x;
     if (i >= M * XLD) return;
     const long long r = i / XLD;
     const int c = (int)(i % XLD);
-    out[i] = c < NFEAT ? f2bf((X[r * NFEAT + c] - mean[c]) / scale[c]) : (bf16_t)0;
+    out[i] = c < NFEAT ? f2bf(fminf(fmaxf((X[r * NFEAT + c] - mean[c]) / scale[c], -INPUT_CLIP), INPUT_CLIP))
+                       : (bf16_t)0;
 }
 
 __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, int ldo, bf16_t* __restrict__ out) {

@@ -91,6 +91,14 @@ def evaluate(net, mols, hfx, tag):
     return out
 
 
+def _means(ev):
+    return dict(sad_iterations=float(np.mean([r["sad_iterations"] for r in ev])),
+                learned_iterations=float(np.mean([r["learned_iterations"] for r in ev])),
+                sad_time_s=float(np.mean([r["sad_time_s"] for r in ev])),
+                learned_time_s=float(np.mean([r["learned_time_s"] for r in ev])),
+                max_abs_dE=float(max(abs(r["dE"]) for r in ev))) if ev else None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=600, help="training clusters (4-32 waters)")
@@ -101,11 +109,23 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="paper_1708_00033_amd/models/guess_water.npy")
     ap.add_argument("--report", default="")
+    ap.add_argument("--eval-only", default="", help="evaluate this saved model, no training")
     a = ap.parse_args(argv)
 
     import torch
     import workloads as W
     from paper_1708_00033_amd import hfx
+
+    if a.eval_only:
+        net = hfx.GuessNet(0, np.load(a.eval_only))
+        ev32 = evaluate(net, [W.water_cluster(32, 29_999)], hfx, "held-out 32")
+        ev = evaluate(net, W.guess_eval_set(a.eval), hfx, "eval 128")
+        rep = dict(model=a.eval_only, heldout32=ev32, eval128=ev, eval128_mean=_means(ev))
+        if a.report:
+            with open(a.report, "w") as fh:
+                json.dump(rep, fh, indent=1)
+        print(json.dumps(rep["eval128_mean"]), flush=True)
+        return 0
 
     stream = torch.cuda.Stream()
     t0 = time.time()
@@ -136,6 +156,7 @@ def main(argv=None):
     g = torch.Generator(device="cpu").manual_seed(a.seed)
     s = stream.cuda_stream
     hist = []
+    best = (float("inf"), None, -1)
     t1 = time.time()
     with torch.cuda.stream(stream):
         for step in range(nsteps):
@@ -150,8 +171,12 @@ def main(argv=None):
                 vloss = net.grad_dev(Xval.data_ptr(), cval, Tval.data_ptr(), s)
                 hist.append(dict(step=step, train_loss=loss, val_loss=vloss, lr=lr))
                 log(f"epoch {step // steps_per_epoch}: train {loss:.4e} val {vloss:.4e} lr {lr:.2e}")
+                if vloss < best[0]:
+                    best = (vloss, net.get_params(), step)
         stream.synchronize()
     t_train = time.time() - t1
+    net.set_params(best[1])     # the parameters with the lowest validation loss
+    log(f"kept the parameters of step {best[2]} (validation loss {best[0]:.4e})")
     params = net.get_params()
     np.save(a.out, params)
     log(f"trained {nsteps} steps in {t_train:.1f} s; saved {a.out}")
@@ -161,13 +186,10 @@ def main(argv=None):
     rep = dict(train_clusters=len(iters), val_clusters=nval, pairs=rows, data_s=t_data, train_s=t_train,
                steps=nsteps, batch=a.batch, epochs=a.epochs, history=hist, heldout32=ev32, eval128=ev,
                sad_start_iterations_train_mean=float(np.mean(iters)) if iters else None)
+    rep["best_val_loss"] = best[0]
+    rep["best_step"] = best[2]
     if ev:
-        rep["eval128_mean"] = dict(
-            sad_iterations=float(np.mean([r["sad_iterations"] for r in ev])),
-            learned_iterations=float(np.mean([r["learned_iterations"] for r in ev])),
-            sad_time_s=float(np.mean([r["sad_time_s"] for r in ev])),
-            learned_time_s=float(np.mean([r["learned_time_s"] for r in ev])),
-            max_abs_dE=float(max(abs(r["dE"]) for r in ev)))
+        rep["eval128_mean"] = _means(ev)
     if a.report:
         with open(a.report, "w") as fh:
             json.dump(rep, fh, indent=1)

@@ -66,7 +66,7 @@ def test_pair_list_and_descriptor_closed_form():
     assert X.shape == (3, 164)
     assert np.allclose(X[1, :4], [0, 1, 0, 1])
     assert np.allclose(X[1, 4:36], g1) and np.allclose(X[0, 4:36], g0)
-    assert np.allclose(X[1, 36 + 32:36 + 64], g1) and np.allclose(X[1, 36:68], 0.0)   # env of A: H neighbours
+    assert np.allclose(X[1, 36 + 32:36 + 64], np.log1p(g1)) and np.allclose(X[1, 36:68], 0.0)   # A's H neighbour
     # beyond the cutoff: no pair, no environment
     m.xyz[1, 2] = 6.5 * G.BOHR_PER_ANGSTROM
     assert G.pair_list(m) == [(0, 0, 2), (1, 1, 2)]
@@ -174,6 +174,18 @@ def test_training_reduces_loss():
         G.adam(p, g, st, lr=1e-3)
     l1, _ = G.loss_and_grad(p, X, counts, T)
     assert l1 < 0.5 * l0
+
+
+def test_inputs_clipped():
+    """Standardised inputs beyond +-4 act as +-4: the output is unchanged
+    when an input is pushed further out."""
+    p, X, counts, _ = _small_problem(6)
+    X = X.copy()
+    X[0, 10] = p["fmean"][10] + 5.0 * p["fscale"][10]
+    Y0 = G.forward(p, X, counts)
+    X[0, 10] = p["fmean"][10] + 50.0 * p["fscale"][10]
+    Y1 = G.forward(p, X, counts)
+    assert all(np.array_equal(a, b) for a, b in zip(Y0, Y1))
 
 
 def test_pack_roundtrip():
