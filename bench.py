@@ -165,7 +165,57 @@ def batched_bench(args, log):
             "speedup_batched_vs_one_by_one": tseq / t64, "speedup_mixed_vs_fp64": t64 / tmx,
             "class_ms_fp64": cms64, "class_ms_mixed": cmsmx,
             "mixed_quartets_fp32": int(stm.quartets_fp32), "mixed_quartets_fp64": int(stm.quartets_fp64),
-            "autotune": {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()}}
+            "autotune": autotune.summary(tuning)}
+
+
+def large_bench(args, log):
+    """512 waters (9728 basis functions), Schwarz tau 1e-11: FP64 and mixed
+    builds from a rank-2560 projector density, optionally full SCF in both
+    precisions (--large-scf)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1708_00033_amd import hfx
+    mol = W.cluster512_config()
+    t0 = time.time()
+    ctx = hfx.Context(device=0, schwarz_tau=1e-11).load(mol)
+    t_load = time.time() - t0
+    counts = ctx.class_counts()
+    quartets = int(counts[:, 0].sum())
+    log(f"512 waters loaded in {t_load:.1f} s: nbf={ctx.nbf} quartets={quartets:.4e}")
+    dev = torch.device("cuda:0")
+    D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 33), device=dev)
+    F64 = torch.empty_like(D)
+    Fmx = torch.empty_like(D)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    out = {"workload": "512-water jittered lattice cluster, seed 3, 5120 shells, 9728 basis functions, "
+                       "Schwarz tau 1e-11, projector density of rank 2560",
+           "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
+           "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load}
+    for prec, Fo, tag in ((hfx.HFX_PREC_FP64, F64, "fp64"), (hfx.HFX_PREC_MIXED, Fmx, "mixed")):
+        ctx.configure(precision=prec)
+        ctx.kernel_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = ctx.build_fock_dev(D.data_ptr(), Fo.data_ptr(), sp, stats=True)
+        dt = time.perf_counter() - t
+        ms, n = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        out[tag] = {"build_s": dt, "quartets_per_s": quartets / dt, "quartets_fp32": int(st.quartets_fp32),
+                    "class_ms": {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}}
+        log(f"512 waters {tag} build: {dt:.2f} s, {quartets / dt:.3e} quartets/s")
+    out["mixed"]["max_abs_dF_vs_fp64"] = (Fmx - F64).abs().max().item()
+    out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(torch.sum(D * (Fmx - F64)).item())
+    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["build_s"] / out["mixed"]["build_s"]
+    if args.large_scf:
+        for prec, tag in ((hfx.HFX_PREC_FP64, "scf_fp64"), (hfx.HFX_PREC_MIXED, "scf_mixed")):
+            ctx.configure(precision=prec)
+            r = ctx.scf()
+            out[tag] = {"energy": r["energy"], "iterations": r["iterations"], "converged": r["converged"],
+                        "t_total_s": r["t_total_s"], "t_fock_s": r["t_fock_s"]}
+            log(f"512 waters {tag}: E={r['energy']:.10f} it={r['iterations']} {r['t_total_s']:.1f} s")
+        out["scf_mixed"]["dE_vs_fp64"] = out["scf_mixed"]["energy"] - out["scf_fp64"]["energy"]
+    return out
 
 
 def main():
@@ -178,6 +228,9 @@ def main():
     ap.add_argument("--task", type=int, default=8192)
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
+    ap.add_argument("--large", action="store_true", help="also time FP64 and mixed builds of 512 waters")
+    ap.add_argument("--large-scf", action="store_true", help="with --large: full SCF in both precisions")
+    ap.add_argument("--only-large", action="store_true", help="run only the 512-water part")
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
     ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
     ap.add_argument("--profile", action="store_true",
@@ -198,6 +251,9 @@ def main():
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
+    if args.only_large:
+        print(json.dumps({"large": large_bench(args, log)}))
+        return
     mol = W.cluster64_config()
     ctx = hfx.Context(device=0, digest=args.digest, task_quartets=args.task).load(mol)
     counts = ctx.class_counts()
@@ -278,7 +334,8 @@ def main():
     flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    kname = f"k_class<Eval{dom['cls']}, {dom['mode']}, 0> grid {dom['tasks'] * dom['wgs']}"
+    kname = (f"{'k_class_persist' if dom['persistent'] else 'k_class'}<Eval{dom['cls']}, {dom['mode']}, 0> "
+             f"grid {dom['blocks'] * dom['wgs']}")
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
     prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -319,11 +376,13 @@ def main():
         "class_ms_fp64": {hfx.CLASS_NAMES[k]: round(ms64[k] / max(n64[k], 1), 3) for k in np.argsort(-ms64)[:8]},
         "class_ms_mixed": {hfx.CLASS_NAMES[k]: round(msmx[k] / max(nmx[k], 1), 3) for k in np.argsort(-msmx)[:8]},
         "scf": {"energy": r["energy"], "iterations": r["iterations"]},
-        "autotune": None if tuning is None else {k: [v["task_quartets"], v["xcd_stripe"]] for k, v in tuning.items()},
+        "autotune": None if tuning is None else autotune.summary(tuning),
     }
     if not args.no_batch:
         log("batched builds: 256 clusters of 1-16 waters ...")
         res["batched"] = batched_bench(args, log)
+    if args.large:
+        res["large"] = large_bench(args, log)
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -187,11 +187,18 @@ hfx_status hfx_scf(hfx_ctx *ctx, const hfx_scf_options *opt, hfx_scf_result *res
 hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
 
 /* Per-class scheduling knobs (class index 0..20, or -1 for all): quartets
- * per workgroup task (0: the context's task_quartets) and XCD striping of
- * long ket prefixes (1 on, 0 off, -1 default on).  Re-plans a loaded
- * system; results are unchanged, only the work decomposition moves.  Set by
- * the autotuner (paper_1708_00033_amd/autotune.py). */
-hfx_status hfx_set_class_tuning(hfx_ctx *ctx, int cls, int task_quartets, int xcd_stripe);
+ * per workgroup task (0: the context's task_quartets), XCD striping of long
+ * ket prefixes (1 on, 0 off, -1 default on), the launch form (0: one
+ * workgroup per task; 1: persistent, a resident grid that takes tasks from
+ * eight per-XCD queues through atomic counters, the dynamic load balancing
+ * of algorithms 1-3's ddi_dlbnext) and the digestion (-1: the context's
+ * option; HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL; LDS staging needs
+ * (n_a + n_b) x nbf x 8 bytes <= 160 KiB and falls back to global
+ * otherwise).  Re-plans a loaded system; results are unchanged up to the
+ * order of floating-point sums.  Set by the autotuner
+ * (paper_1708_00033_amd/autotune.py). */
+hfx_status hfx_set_class_tuning(hfx_ctx *ctx, int cls, int task_quartets, int xcd_stripe, int persistent,
+                                int digest);
 
 /* Per-class plan counts: counts[21*4] = {unique quartets, integrals,
  * primitive quartets, workgroup tasks} for each canonical quartet class in
@@ -205,11 +212,11 @@ hfx_status hfx_class_counts(const hfx_ctx *ctx, long long *counts);
 hfx_status hfx_kernel_timing(hfx_ctx *ctx, int enable);
 hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 
-/* Launches of a build: one per (quartet class, ket primitive count).  info[9]
- * = {class index, ket primitives per pair, workgroups (one task each),
- * unique quartets, primitive quartets, integrals, timed launches, digestion
- * mode, work-items per workgroup}; *ms = summed event time of the timed
- * launches. */
+/* Launches of a build: one per (quartet class, ket primitive count).
+ * info[11] = {class index, ket primitives per pair, workgroup tasks, unique
+ * quartets, primitive quartets, integrals, timed launches, digestion mode,
+ * work-items per workgroup, persistent (0/1), workgroups launched at the
+ * current precision}; *ms = summed event time of the timed launches. */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 
@@ -236,8 +243,9 @@ hfx_status hfx_sad_density(hfx_ctx *ctx, double *D);
  * Features: 164 FP32 per pair = one-hot element of A (O, H), of B, 32 radial
  * Gaussians exp(-eta (R_AB - mu_k)^2) fc(R_AB) (mu_k = 0.5 .. 6 A in 31
  * steps, eta = 1 / (2 dmu^2), fc = (cos(pi R / 6 A) + 1) / 2), then the
- * environments of A and of B (for O then H neighbours: the radial functions
- * summed over the atoms of that element other than the atom itself). */
+ * environments of A and of B (for O then H neighbours: log(1 + the radial
+ * functions summed over the atoms of that element other than the atom
+ * itself)). */
 
 /* Pair list, frames and features of the loaded single molecule (device,
  * owned by ctx until the next load).  counts[3] (optional): pairs per type. */
@@ -259,7 +267,8 @@ hfx_status hfx_guess_assemble_dev(hfx_ctx *ctx, const float *dT, const double *d
  * packed): W1[256x164] b1[256] W2[256x256] b2 W3[256x256] b3, heads
  * H0[225x256] c0 H1[30x256] c1 H2[4x256] c2 (W: out x in, row-major), then
  * the feature mean[164], feature scale[164] and target scales[3]: input
- * (x - mean) / scale, block = output x target scale of the pair's type. */
+ * (x - mean) / scale clipped to [-4, 4], block = output x target scale of
+ * the pair's type. */
 hfx_status hfx_guess_create(int device, hfx_guess **out);
 void hfx_guess_destroy(hfx_guess *g);
 long long hfx_guess_param_count(void);

@@ -1,8 +1,10 @@
 """Autotuner for the per-class work decomposition of the Fock build.
 
-For every quartet class the library exposes two scheduling knobs
-(``hfx_set_class_tuning``): quartets per workgroup task and XCD striping of
-long ket prefixes.  Results do not depend on them.  The tuner times each
+For every quartet class the library exposes four scheduling knobs
+(``hfx_set_class_tuning``): quartets per workgroup task, XCD striping of
+long ket prefixes, the launch form (one workgroup per task, or a persistent
+resident grid fed by per-XCD atomic work counters) and the digestion (bra
+rows staged in LDS, or global atomics).  Results do not depend on them.  The tuner times each
 candidate setting for all classes at once with the library's per-launch HIP
 events, keeps each class's fastest setting, applies it and returns the table
 (JSON-serialisable, keyed by class name).
@@ -16,17 +18,25 @@ import numpy as np
 
 from . import hfx
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = (
-    (2048, 0), (2048, 1), (8192, 0), (8192, 1), (32768, 0), (32768, 1))
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
+    (2048, 0, 0, -1), (2048, 1, 0, -1), (8192, 0, 0, -1), (8192, 1, 0, -1), (32768, 0, 0, -1), (32768, 1, 0, -1),
+    (2048, 1, 1, -1), (8192, 1, 1, -1), (8192, 0, 0, 1), (32768, 0, 0, 1))
 
 
-PREFERRED: Tuple[int, int] = (32768, 0)
+PREFERRED: Tuple[int, int, int, int] = (32768, 0, 0, -1)
+_PAD = (0, 0, 0, -1)
+
+
+def _full(c) -> Tuple[int, int, int, int]:
+    c = tuple(int(x) for x in c)
+    return c + _PAD[len(c):]
 
 
 def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
-             candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, reps: int = 2,
-             sync=None, prefer: Tuple[int, int] = PREFERRED, margin: float = 0.03) -> Dict[str, dict]:
-    """Return {class name: {"task_quartets", "xcd_stripe", "ms", "candidates_ms"}}.
+             candidates: Sequence[Tuple[int, ...]] = DEFAULT_CANDIDATES, reps: int = 2,
+             sync=None, prefer: Tuple[int, ...] = PREFERRED, margin: float = 0.03) -> Dict[str, dict]:
+    """Return {class name: {"task_quartets", "xcd_stripe", "persistent", "digest", "ms", "candidates_ms"}}.
+    A candidate is (task_quartets, xcd_stripe[, persistent[, digest]]).
 
     A class keeps the ``prefer`` setting (when it is a candidate) unless another
     candidate is faster by more than ``margin`` (relative): timing noise then
@@ -35,8 +45,10 @@ def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
         import torch
         sync = torch.cuda.synchronize
     times = np.full((len(candidates), 21), np.inf)
-    for ci, (tq, st) in enumerate(candidates):
-        ctx.set_class_tuning(-1, tq, st)
+    cands = [_full(c) for c in candidates]
+    prefer = _full(prefer)
+    for ci, (tq, st, pe, dg) in enumerate(cands):
+        ctx.set_class_tuning(-1, tq, st, pe, dg)
         ctx.build_fock_dev(dD_ptr, dF_ptr, stream)   # warm-up
         sync()
         ctx.kernel_timing(True)
@@ -49,12 +61,13 @@ def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
     table = {}
     for k in range(21):
         best = int(np.argmin(times[:, k]))
-        if tuple(prefer) in [tuple(c) for c in candidates]:
-            pi = [tuple(c) for c in candidates].index(tuple(prefer))
+        if prefer in cands:
+            pi = cands.index(prefer)
             if times[pi, k] <= times[best, k] * (1.0 + margin):
                 best = pi
-        tq, st = candidates[best]
-        table[hfx.CLASS_NAMES[k]] = {"task_quartets": int(tq), "xcd_stripe": int(st),
+        tq, st, pe, dg = cands[best]
+        table[hfx.CLASS_NAMES[k]] = {"task_quartets": int(tq), "xcd_stripe": int(st), "persistent": int(pe),
+                                      "digest": int(dg),
                                       "ms": float(times[best, k]),
                                       "candidates_ms": [round(float(x), 4) for x in times[:, k]]}
     apply(ctx, table)
@@ -63,7 +76,8 @@ def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
 
 def apply(ctx: "hfx.Context", table: Dict[str, dict]) -> None:
     for name, v in table.items():
-        ctx.set_class_tuning(hfx.CLASS_NAMES.index(name), int(v["task_quartets"]), int(v["xcd_stripe"]))
+        ctx.set_class_tuning(hfx.CLASS_NAMES.index(name), int(v["task_quartets"]), int(v["xcd_stripe"]),
+                             int(v.get("persistent", 0)), int(v.get("digest", -1)))
 
 
 def save(table: Dict[str, dict], path: str) -> None:
@@ -76,5 +90,6 @@ def load(path: str) -> Dict[str, dict]:
         return json.load(fh)
 
 
-def summary(table: Dict[str, dict], classes: Iterable[str] = ()) -> Dict[str, Tuple[int, int]]:
-    return {k: (v["task_quartets"], v["xcd_stripe"]) for k, v in table.items() if not classes or k in classes}
+def summary(table: Dict[str, dict], classes: Iterable[str] = ()) -> Dict[str, Tuple[int, int, int, int]]:
+    return {k: (v["task_quartets"], v["xcd_stripe"], v.get("persistent", 0), v.get("digest", -1))
+            for k, v in table.items() if not classes or k in classes}

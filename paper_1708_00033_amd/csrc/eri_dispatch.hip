@@ -14,16 +14,33 @@ static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPT
 
 #define HFX_WG 256
 
-extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_bytes,
+// nblocks workgroups: the task count (static launch) or the resident grid
+// (persistent launch, args->work set).
+extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int nblocks, size_t lds_bytes,
                                        hipStream_t stream, const ClassArgs* args) {
-    if (ntask <= 0) return hipSuccess;
-    const void* fn = kClassLookup[cid](mode * 2 + mixed);
+    if (nblocks <= 0) return hipSuccess;
+    const void* fn = kClassLookup[cid]((args->work ? 4 : 0) + mode * 2 + mixed);
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
     void* kargs[] = {(void*)args};
-    return hipLaunchKernel(fn, dim3(ntask), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+    return hipLaunchKernel(fn, dim3(nblocks), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+}
+
+// Workgroups of one class kernel that fit on the device at once.
+extern "C" int hfx_class_resident_blocks(int cid, int mode, int mixed, size_t lds_bytes) {
+    const void* fn = kClassLookup[cid](4 + mode * 2 + mixed);
+    if (lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
+        return 0;
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEriClassInfo[cid].wgs, lds_bytes) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * ncu;
 }
 
 extern "C" int hfx_class_wgs(int cid) { return kEriClassInfo[cid].wgs; }

@@ -302,11 +302,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // kets all lie at or beyond split[r] are evaluated in FP32 and widened before
 // digestion).
 template <class E, int MODE, int MIXED>
-__global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
+__device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     extern __shared__ double lds[];
-    const int4 task = a.tasks[blockIdx.x];
     const int r = task.x, s0 = task.y;
     if (r < 0) return;                                        // padding task (XCD striping)
     if (a.nshards > 1 && r % a.nshards != a.shard) return;   // whole workgroup: uniform exit
@@ -402,6 +401,36 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     }
 }
 
+// Static launch: workgroup i runs task i.
+template <class E, int MODE, int MIXED>
+__global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
+    class_task<E, MODE, MIXED>(a, a.tasks[blockIdx.x]);
+}
+
+// Persistent launch: a resident grid; a workgroup on XCD x (workgroup index
+// mod 8, the hardware's round-robin placement) takes entries of XCD x's
+// queue through an atomic counter, then drains the other queues in turn, so
+// no XCD idles while another still has work (the dynamic load balancing of
+// ddi_dlbnext in algorithms 1-3).  A separate kernel so that the static
+// form keeps its register allocation.
+template <class E, int MODE, int MIXED>
+__global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
+    __shared__ int next_entry;
+    const int x0 = blockIdx.x & 7;
+    for (int q = 0; q < 8;) {
+        const int x = (x0 + q) & 7;
+        if (threadIdx.x == 0) next_entry = (int)atomicAdd(a.work + x, 1ull);
+        __syncthreads();
+        const int k = next_entry;
+        __syncthreads();
+        if (k >= a.qlen) {
+            ++q;
+            continue;
+        }
+        class_task<E, MODE, MIXED>(a, a.tasks[8 * k + x]);
+    }
+}
+
 // Schwarz bound of every pair of one pair class: Q = sqrt(max (mn|mn)) with
 // the component normalisation s_m s_n applied (always FP64).
 // 1/sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!) of Cartesian component c of shell l.
@@ -444,12 +473,17 @@ template <class E>
 struct ClassKernels {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
+    // variant = 4 persistent + 2 mode + mixed
     static const void* get(int variant) {
         if constexpr (kOnlyFp64Global) {
-            return variant >= 2 ? (const void*)k_class<E, 1, 0> : (const void*)k_class<E, 0, 0>;
+            static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 1, 0>,
+                                       (const void*)k_class_persist<E, 0, 0>, (const void*)k_class_persist<E, 1, 0>};
+            return t[(variant >= 4 ? 2 : 0) + ((variant & 3) >= 2 ? 1 : 0)];
         } else {
-            static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 0, 1>,
-                                       (const void*)k_class<E, 1, 0>, (const void*)k_class<E, 1, 1>};
+            static const void* t[8] = {(const void*)k_class<E, 0, 0>,         (const void*)k_class<E, 0, 1>,
+                                       (const void*)k_class<E, 1, 0>,         (const void*)k_class<E, 1, 1>,
+                                       (const void*)k_class_persist<E, 0, 0>, (const void*)k_class_persist<E, 0, 1>,
+                                       (const void*)k_class_persist<E, 1, 0>, (const void*)k_class_persist<E, 1, 1>};
             return t[variant];
         }
     }

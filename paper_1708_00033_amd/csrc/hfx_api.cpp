@@ -99,6 +99,7 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
 
 static void release_system(hfx_ctx* c) {
     hfx_guess_release(c);
+    dfree(c->d_work);
     if (c->graph_exec) {
         (void)hipGraphExecDestroy(c->graph_exec);
         c->graph_exec = nullptr;
@@ -303,8 +304,17 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.ntask = (int)tasks.size();
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
-    P.mode = (c->opt.digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024) ? 0 : 1;
+    const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
+    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024) ? 0 : 1;
     if (P.ntask == 0) return HFX_OK;
+    P.persist = c->tune_persist[P.cid] > 0;
+    for (int mx = 0; mx < 2; ++mx) {
+        const size_t lds = P.mode == 0 ? P.lds_bytes : 0;
+        int nb = hfx_class_resident_blocks(P.cid, P.mode, mx && !P.fp64_only, lds);
+        if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
+        nb = std::min(nb, P.ntask);
+        P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
+    }
     HIPCK(dalloc(&P.d_nket, nbra));
     HIPCK(dalloc(&P.d_kseg, nbra));
     HIPCK(dalloc(&P.d_split, nbra));
@@ -324,6 +334,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
 // (Re)build every launch plan from the stored Q-sorted lists with the
 // current per-class tuning.
 static hfx_status replan(hfx_ctx* c) {
+    dfree(c->d_work);
     for (auto& p : c->plans) {
         dfree(p.d_nket);
         dfree(p.d_kseg);
@@ -346,6 +357,7 @@ static hfx_status replan(hfx_ctx* c) {
     for (int i = 0; i < 21; ++i) rank[order[i]] = i;
     std::stable_sort(c->plans.begin(), c->plans.end(),
                      [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
+    HIPCK(dalloc(&c->d_work, 8 * std::max<size_t>(c->plans.size(), 1)));
     if (c->timing)
         for (auto& p : c->plans) {
             HIPCK(hipEventCreate(&p.ev0));
@@ -354,16 +366,21 @@ static hfx_status replan(hfx_ctx* c) {
     return HFX_OK;
 }
 
-extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartets, int xcd_stripe) {
+extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartets, int xcd_stripe,
+                                           int persistent, int digest) {
     if (!c) return HFX_ERR_INVALID_ARG;
     if (cid < -1 || cid >= 21) return hfx_fail(c, HFX_ERR_INVALID_ARG, "class index out of range");
     if (task_quartets != 0 && (task_quartets < 256 || task_quartets % 256 != 0 || task_quartets > (1 << 24)))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be 0 or a multiple of 256 in [256, 2^24]");
     if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
+    if (persistent < 0 || persistent > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0 or 1");
+    if (digest < -1 || digest > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0 or 1");
     for (int k = 0; k < 21; ++k)
         if (cid == -1 || cid == k) {
             c->tune_tq[k] = task_quartets;
             c->tune_stripe[k] = xcd_stripe;
+            c->tune_persist[k] = persistent;
+            c->tune_digest[k] = digest;
         }
     if (!c->loaded) return HFX_OK;
     HIPCK(hipSetDevice(c->opt.device));
@@ -859,6 +876,9 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[6] = p.launches;
     info[7] = p.mode;
     info[8] = hfx_class_wgs(p.cid);
+    info[9] = p.persist ? 1 : 0;
+    const bool mx = c->opt.precision == HFX_PREC_MIXED && !p.fp64_only;
+    info[10] = p.persist ? p.nblocks[mx ? 1 : 0] : p.ntask;
     if (ms) *ms = p.ms;
     return HFX_OK;
 }
@@ -878,6 +898,9 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
                               c->d_dmax, st));
     HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
     for (auto& KL : c->ketlists) HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
+    bool any_persist = false;
+    for (const auto& P : c->plans) any_persist |= P.persist;
+    if (any_persist) HIPCK(hfx_fill_u64(c->d_work, 8 * (int)c->plans.size(), st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
@@ -906,8 +929,11 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.ck = ck;
         a.shard = shard;
         a.nshards = nshards;
+        a.work = P.persist ? c->d_work + 8 * pi : nullptr;
+        a.qlen = P.ntask / 8;
+        const int nblocks = P.persist ? P.nblocks[mx ? 1 : 0] : P.ntask;
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, P.ntask, P.mode == 0 ? P.lds_bytes : 0, st, &a));
+        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, nblocks, P.mode == 0 ? P.lds_bytes : 0, st, &a));
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));
             P.pending = true;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,8 @@ struct SubPlan {
     double ms = 0.0;
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
+    bool persist = false;     // persistent launch through per-XCD work counters
+    int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / mixed kernel
 };
 
 struct ClassTotals {
@@ -96,6 +99,10 @@ struct hfx_ctx {
     int tune_tq[21] = {0};                       // 0: opt.task_quartets
     int tune_stripe[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
                            -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: default (striped)
+    int tune_persist[21] = {0};                  // 1: persistent launch
+    int tune_digest[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                           -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: opt.digest
+    unsigned long long* d_work = nullptr;        // 8 queue counters per plan
     std::vector<double> Qshell;         // nshell x nshell Schwarz bounds (host)
     double* d_boys64 = nullptr;
     float* d_boys32 = nullptr;
@@ -112,6 +119,8 @@ struct hfx_ctx {
     rocblas_handle blas = nullptr;
     hipGraphExec_t graph_exec = nullptr;   // captured build (hfx_graph_capture)
     GuessPairsDev* guess = nullptr;        // hfx_guess_setup
+    // SAD: atomic densities by element and basis (kept across loads)
+    std::map<std::string, std::vector<double>> sad_cache;
     // timing
     bool timing = false;
     hipStream_t last_stream = nullptr;
@@ -149,8 +158,9 @@ hipError_t hfx_scale_cols(const double* U, const double* w, const int* keep, int
                           hipStream_t st);
 hipError_t hfx_weight_cols(const double* C, const double* occ, int n, int nk, double* out, hipStream_t st);
 // eri_dispatch.hip
-hipError_t hfx_launch_class(int cid, int mode, int mixed, int ntask, size_t lds_bytes, hipStream_t stream,
+hipError_t hfx_launch_class(int cid, int mode, int mixed, int nblocks, size_t lds_bytes, hipStream_t stream,
                             const ClassArgs* args);
+int hfx_class_resident_blocks(int cid, int mode, int mixed, size_t lds_bytes);
 int hfx_class_wgs(int cid);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);

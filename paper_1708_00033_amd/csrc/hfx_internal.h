@@ -43,7 +43,11 @@ struct ClassArgs {
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
     int nket_list, knprim;
     const int* __restrict__ split;      // per bra: kets below this list position use FP64
-    const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0) per workgroup; bra -1: empty
+    const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0); bra -1: empty.  Task 8k + x is
+                                        // entry k of XCD x's queue
+    unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
+                                            // launch); null: one task per workgroup
+    int qlen;                           // entries per XCD queue (tasks = 8 qlen)
     const long long* __restrict__ moff; // per molecule: element offset of its blocks in D', W
     const double* __restrict__ boys64;
     const float* __restrict__ boys32;

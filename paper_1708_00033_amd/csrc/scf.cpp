@@ -377,15 +377,22 @@ static hfx_status scf_core(hfx_ctx* c, const hfx_scf_options& o, double occ_pair
 static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
     const int n = c->nbf;
     Dsad.assign((size_t)n * n, 0.0);
-    std::map<int, std::vector<double>> cache;
-    std::map<int, int> cache_n;
     for (int a = 0; a < c->natom; ++a) {
         const int z = c->Z[a];
         std::vector<int> sh;
         for (int s = 0; s < c->nshell; ++s)
             if (c->shell_atom[s] == a) sh.push_back(s);
         if (sh.empty()) continue;
-        if (!cache.count(z)) {
+        // key: element and the raw shells (l, exponents, coefficients)
+        std::string key(reinterpret_cast<const char*>(&z), sizeof(int));
+        for (int s : sh) {
+            key.append(reinterpret_cast<const char*>(&c->shell_exps_l[s]), sizeof(int));
+            key.append(reinterpret_cast<const char*>(c->raw_exps[s].data()), c->raw_exps[s].size() * sizeof(double));
+            key.append(reinterpret_cast<const char*>(c->raw_coefs[s].data()),
+                       c->raw_coefs[s].size() * sizeof(double));
+            key.push_back('|');
+        }
+        if (!c->sad_cache.count(key)) {
             hfx_options ao = c->opt;
             ao.precision = HFX_PREC_FP64;
             ao.log_level = 0;
@@ -432,11 +439,10 @@ static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
             (void)hipFree(dDa);
             hfx_destroy(sub);
             if (s != HFX_OK) return hfx_fail(c, s, "SAD: atomic SCF failed: " + m);
-            cache[z] = Da;
-            cache_n[z] = na;
+            c->sad_cache[key] = Da;
         }
-        const auto& Da = cache[z];
-        const int na = cache_n[z];
+        const auto& Da = c->sad_cache[key];
+        const int na = (int)std::lround(std::sqrt((double)Da.size()));
         const int o0 = c->shells[sh.front()].bf;
         int nloc = 0;
         for (int s : sh) nloc += (c->shells[s].l + 1) * (c->shells[s].l + 2) / 2;

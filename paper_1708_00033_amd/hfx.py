@@ -102,7 +102,7 @@ _sigs = {
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
     "hfx_class_counts": ([_ctx_p, C.POINTER(C.c_longlong)], C.c_int),
-    "hfx_set_class_tuning": ([_ctx_p, C.c_int, C.c_int, C.c_int], C.c_int),
+    "hfx_set_class_tuning": ([_ctx_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
     "hfx_kernel_timing": ([_ctx_p, C.c_int], C.c_int),
     "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_plan_count": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
@@ -368,14 +368,16 @@ class Context:
         self._check(hfx_guess_apply(self.ptr, model.ptr, C.c_void_p(dD_ptr), C.c_void_p(stream), C.byref(used)))
         return bool(used.value)
 
-    def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1):
-        self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe))
+    def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1, persistent: int = 0,
+                         digest: int = -1):
+        self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe, persistent, digest))
 
     def apply_tuning(self, table: dict):
-        """table: {class index or name: {"task_quartets": int, "xcd_stripe": int}}"""
+        """table: {class index or name: {"task_quartets", "xcd_stripe", "persistent", "digest"}}"""
         for k, v in table.items():
             cid = CLASS_NAMES.index(k) if isinstance(k, str) and not k.isdigit() else int(k)
-            self.set_class_tuning(cid, int(v.get("task_quartets", 0)), int(v.get("xcd_stripe", -1)))
+            self.set_class_tuning(cid, int(v.get("task_quartets", 0)), int(v.get("xcd_stripe", -1)),
+                                  int(v.get("persistent", 0)), int(v.get("digest", -1)))
 
     def class_counts(self) -> np.ndarray:
         a = np.zeros(21 * 4, dtype=np.int64)
@@ -386,17 +388,18 @@ class Context:
         self._check(hfx_kernel_timing(self.ptr, int(enable)))
 
     def plans(self):
-        """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, wgs, ms)."""
+        """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, wgs,
+        persistent, blocks, ms)."""
         n = C.c_int()
         self._check(hfx_plan_count(self.ptr, C.byref(n)))
         out = []
         for i in range(n.value):
-            info = (C.c_longlong * 9)()
+            info = (C.c_longlong * 11)()
             ms = C.c_double()
             self._check(hfx_plan_info(self.ptr, i, info, C.byref(ms)))
             out.append(dict(cls=int(info[0]), ket_nprim=int(info[1]), tasks=int(info[2]), quartets=int(info[3]),
                             prim=int(info[4]), integrals=int(info[5]), launches=int(info[6]), mode=int(info[7]),
-                            wgs=int(info[8]), ms=ms.value))
+                            wgs=int(info[8]), persistent=int(info[9]), blocks=int(info[10]), ms=ms.value))
         return out
 
     def kernel_times(self):

@@ -33,15 +33,16 @@ def test_batch_build_equals_individual_builds():
     for m, D in zip(mols, Ds):
         F, _ = hfx.Context().load(m).build_fock(D)
         refs.append(F)
-    for digest in (0, 1):
+    for digest, persistent in ((0, 0), (1, 0), (0, 1)):
         bctx = hfx.Context(digest=digest).load_batch(mols)
+        bctx.set_class_tuning(-1, 2048, 1, persistent)
         nbf, nocc, off, tot = bctx.layout
         assert list(nbf) == [m.nbf for m in mols]
         assert tot == sum(m.nbf ** 2 for m in mols)
         Fb, st = bctx.build_fock(_ragged(Ds))
         for i, m in enumerate(mols):
             blk = Fb[off[i]:off[i] + nbf[i] ** 2].reshape(nbf[i], nbf[i])
-            assert np.abs(blk - refs[i]).max() < 1e-11, (digest, i)
+            assert np.abs(blk - refs[i]).max() < 1e-11, (digest, persistent, i)
         S, H, enuc = bctx.core()
         So, Ho, _ = hfx.Context().load(mols[3]).core()
         assert np.abs(S[off[3]:off[3] + nbf[3] ** 2].reshape(nbf[3], nbf[3]) - So).max() < 1e-13
@@ -63,7 +64,10 @@ def test_batch_against_oracle_and_mixed():
         assert np.abs(blk - (T + V + 2 * J - K)).max() < 1e-6
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_graph_replay_matches_eager(persistent):
+    """Replays of a captured build (persistent launches reset their work
+    counters with a fill kernel inside the graph) equal the eager build."""
     import torch
     hfx = _hfx()
     for target in ("single", "batch"):
@@ -74,6 +78,7 @@ def test_graph_replay_matches_eager():
         else:
             ctx.load_batch(_mols())
             n = ctx.layout[3]
+        ctx.set_class_tuning(-1, 2048, 1, persistent)
         stream = torch.cuda.Stream()
         D = torch.tensor(np.random.default_rng(3).uniform(-0.1, 0.1, n), device="cuda")
         with torch.cuda.stream(stream):

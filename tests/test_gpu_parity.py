@@ -252,14 +252,16 @@ def test_scheduling_knobs_do_not_change_results():
     ctx.set_class_tuning(-1, 256, 0)
     ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, ref.data_ptr(), s)
     out = torch.empty_like(D)
-    for tq, st in [(8192, 1), (1024, 1), (32768, 0)]:
-        ctx.set_class_tuning(-1, tq, st)
+    for tq, st, pe, dg in [(8192, 1, 0, -1), (1024, 1, 0, -1), (32768, 0, 0, -1), (2048, 1, 1, -1),
+                           (256, 0, 1, -1), (32768, 1, 1, -1), (8192, 0, 0, 1), (2048, 1, 1, 1)]:
+        ctx.set_class_tuning(-1, tq, st, pe, dg)
         ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
         torch.cuda.synchronize()
-        assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item(), (tq, st)
+        assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item(), (tq, st, pe, dg)
     from paper_1708_00033_amd import autotune
     F = torch.empty_like(D)
-    table = autotune.autotune(ctx, D.data_ptr(), F.data_ptr(), s, candidates=((512, 0), (4096, 1)), reps=1)
+    table = autotune.autotune(ctx, D.data_ptr(), F.data_ptr(), s, candidates=((512, 0), (4096, 1, 1), (2048, 0, 0, 1)),
+                              reps=1)
     assert set(table) == set(_hfx().CLASS_NAMES)
     ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
     torch.cuda.synchronize()
