@@ -2,7 +2,8 @@
 //   F_m(T) = int_0^1 t^{2m} e^{-T t^2} dt
 // evaluated in long double from the everywhere-convergent positive series
 //   F_m(T) = e^{-T} sum_{k>=0} (2T)^k / ((2m+1)(2m+3)...(2m+2k+1)),
-// stored per order L as rows F_{L+j}(T_k)/j!, j = 0..7 (Taylor coefficients).
+// stored per order L as rows F_{L+j}(T_k)/j!, j = 0..7 (Taylor coefficients),
+// the order-L block at position boys_block(L).
 #include <cmath>
 
 #include "hfx_internal.h"
@@ -26,7 +27,7 @@ void hfx_boys_table(double* tab) {
             long double fact = 1.0L;
             for (int j = 0; j < BOYS_ROW; ++j) {
                 if (j > 0) fact *= j;
-                tab[((size_t)L * BOYS_NT + k) * BOYS_ROW + j] = (double)(F[L + j] / fact);
+                tab[((size_t)boys_block(L) * BOYS_NT + k) * BOYS_ROW + j] = (double)(F[L + j] / fact);
             }
         }
     }

@@ -301,14 +301,42 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One class, one digestion mode, one precision policy (MIXED = 1: waves whose
 // kets all lie at or beyond split[r] are evaluated in FP32 and widened before
 // digestion).
+//
+// LDS of a class kernel: the class's Boys rows (FP64, then FP32 for MIXED),
+// then (MODE 0) the bra rows F_I, F_J of the current task.
+template <class E, int MIXED>
+struct LdsLayout {
+    static constexpr int L = E::LA + E::LB + E::LC + E::LD;
+    static constexpr int T64 = boys_entries(L);              // doubles
+    static constexpr int T32 = MIXED ? boys_entries(L) : 0;  // floats
+    static constexpr int ROWS = T64 + T32 / 2;               // offset of the bra rows, doubles
+};
+
+// Uniform per workgroup: padding tasks (XCD striping) and other shards' bras do nothing.
+__device__ __forceinline__ bool task_active(const ClassArgs& a, const int4 task) {
+    return task.x >= 0 && (a.nshards <= 1 || task.x % a.nshards == a.shard);
+}
+
+template <class E, int MIXED>
+__device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, float* t32) {
+    using LL = LdsLayout<E, MIXED>;
+    const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
+    for (int i = threadIdx.x; i < LL::T64; i += E::WGS) t64[i] = g64[i];
+    if constexpr (MIXED) {
+        const float* __restrict__ g32 = a.boys32 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
+        for (int i = threadIdx.x; i < LL::T32; i += E::WGS) t32[i] = g32[i];
+    }
+    __syncthreads();
+}
+
 template <class E, int MODE, int MIXED>
-__device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) {
+__device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, const double* t64,
+                                           const float* t32) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     const int r = task.x, s0 = task.y;
-    if (r < 0) return;                                        // padding task (XCD striping)
-    if (a.nshards > 1 && r % a.nshards != a.shard) return;   // whole workgroup: uniform exit
+    if (!task_active(a, task)) return;
     const PairInfo bra = a.bra[r];
     // the bra's molecule: its blocks of D' and W, leading dimension ld
     const int N = bra.ld;
@@ -316,10 +344,10 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) 
     double* __restrict__ Wm = a.W + a.moff[bra.mol];
     const int send = task.z;                                  // kets [s0, send) of the list
     const int split = MIXED ? a.split[r] : send;
-    double* FI = lds;
-    double* FJ = lds + NA * N;
+    double* FI = lds + LdsLayout<E, MIXED>::ROWS;
+    double* FJ = FI + NA * N;
     if constexpr (MODE == 0) {
-        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) lds[i] = 0.0;
+        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) FI[i] = 0.0;
         __syncthreads();
     }
     double dab[NAB], jab[NAB];
@@ -342,7 +370,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) 
 #pragma unroll 1
             for (int k = 0; k < NA; ++k) {
                 E::template run_pass<double>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim,
-                                             bra.AB, ket.AB, a.boys64, Ik);
+                                             bra.AB, ket.AB, t64, Ik);
                 digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N);
             }
             ++n64;
@@ -354,12 +382,12 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) 
         const int wave_first = __builtin_amdgcn_readfirstlane(s - (int)(threadIdx.x & 63));
         if (!MIXED || wave_first < split) {
             E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
-                                    ket.AB, a.boys64, I);
+                                    ket.AB, t64, I);
             ++n64;
         } else {
             float If[NI];
             E::template run<float>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
-                                   ket.AB, a.boys32, If);
+                                   ket.AB, t32, If);
 #pragma unroll
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
@@ -391,7 +419,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) 
     if constexpr (MODE == 0) {
         __syncthreads();
         for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) {
-            const double v = lds[i];
+            const double v = FI[i];
             if (v != 0.0) {
                 const int row = i < NA * N ? bra.bfa + i / N : bra.bfb + (i - NA * N) / N;
                 const int col = i < NA * N ? i % N : (i - NA * N) % N;
@@ -404,7 +432,13 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task) 
 // Static launch: workgroup i runs task i.
 template <class E, int MODE, int MIXED>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
-    class_task<E, MODE, MIXED>(a, a.tasks[blockIdx.x]);
+    extern __shared__ __align__(16) double lds[];
+    const int4 task = a.tasks[blockIdx.x];
+    if (!task_active(a, task)) return;
+    double* t64 = lds;
+    float* t32 = reinterpret_cast<float*>(lds + LdsLayout<E, MIXED>::T64);
+    load_boys_lds<E, MIXED>(a, t64, t32);
+    class_task<E, MODE, MIXED>(a, task, t64, t32);
 }
 
 // Persistent launch: a resident grid; a workgroup on XCD x (workgroup index
@@ -415,7 +449,11 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
 // form keeps its register allocation.
 template <class E, int MODE, int MIXED>
 __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
+    extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
+    double* t64 = lds;
+    float* t32 = reinterpret_cast<float*>(lds + LdsLayout<E, MIXED>::T64);
+    load_boys_lds<E, MIXED>(a, t64, t32);   // once per resident workgroup
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -427,7 +465,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, MIXED>(a, a.tasks[8 * k + x]);
+        class_task<E, MODE, MIXED>(a, a.tasks[8 * k + x], t64, t32);
     }
 }
 
@@ -449,7 +487,8 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
     double I[NA * NB * NA * NB];
     // ket read from the array-of-structures layout: field stride 1, primitive stride 10 doubles
     E::template run<double>(prim + pr.prim_off, pr.nprim, (const double*)(prim + pr.prim_off), 1,
-                            (int)(sizeof(PrimPair) / sizeof(double)), pr.nprim, pr.AB, pr.AB, boys, I);
+                            (int)(sizeof(PrimPair) / sizeof(double)), pr.nprim, pr.AB, pr.AB,
+                            boys + (size_t)boys_block(E::LA + E::LB + E::LC + E::LD) * BOYS_NT * BOYS_ROW, I);
     double mx = 0.0;
 #pragma unroll
     for (int m = 0; m < NA; ++m)

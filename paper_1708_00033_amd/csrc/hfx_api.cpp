@@ -200,14 +200,12 @@ extern "C" hfx_status hfx_configure(hfx_ctx* c, const hfx_options* o) {
     if (s != HFX_OK) return s;
     if (o->device != c->opt.device || o->schwarz_tau != c->opt.schwarz_tau)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "device and schwarz_tau cannot change after hfx_create");
-    const bool new_plan = o->task_quartets != c->opt.task_quartets;
+    const bool new_plan = o->task_quartets != c->opt.task_quartets || o->digest != c->opt.digest;
     c->opt = *o;
     if (new_plan && c->loaded) {
         HIPCK(hipSetDevice(c->opt.device));
         return replan(c);
     }
-    // digestion mode may change without a new plan
-    for (auto& p : c->plans) p.mode = (c->opt.digest == HFX_DIGEST_LDS && p.lds_bytes <= 160 * 1024) ? 0 : 1;
     return HFX_OK;
 }
 
@@ -304,12 +302,16 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.ntask = (int)tasks.size();
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
+    const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
+    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);
+    P.lds_tab[1] = P.lds_tab[0] + (P.fp64_only ? 0 : (size_t)boys_entries(Ltot) * sizeof(float));
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
-    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes <= 160 * 1024) ? 0 : 1;
+    // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
+    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[1] <= 160 * 1024 - 256) ? 0 : 1;
     if (P.ntask == 0) return HFX_OK;
     P.persist = c->tune_persist[P.cid] > 0;
     for (int mx = 0; mx < 2; ++mx) {
-        const size_t lds = P.mode == 0 ? P.lds_bytes : 0;
+        const size_t lds = P.lds(mx != 0);
         int nb = hfx_class_resident_blocks(P.cid, P.mode, mx && !P.fp64_only, lds);
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
@@ -933,7 +935,7 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.qlen = P.ntask / 8;
         const int nblocks = P.persist ? P.nblocks[mx ? 1 : 0] : P.ntask;
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, nblocks, P.mode == 0 ? P.lds_bytes : 0, st, &a));
+        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, nblocks, P.lds(mx), st, &a));
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));
             P.pending = true;

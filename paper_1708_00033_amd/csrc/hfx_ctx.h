@@ -37,7 +37,8 @@ struct SubPlan {
     int* d_split = nullptr;
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
-    size_t lds_bytes = 0;
+    size_t lds_bytes = 0;     // bra rows F_I, F_J (LDS digestion)
+    size_t lds_tab[2] = {0, 0};   // Boys rows in LDS for the FP64 / mixed kernel
     int mode = 0;             // digestion actually used (LDS may fall back to global)
     // timing (when enabled): events around this launch, summed milliseconds
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -45,6 +46,7 @@ struct SubPlan {
     double ms = 0.0;
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
+    size_t lds(bool mx) const { return (mode == 0 ? lds_bytes : 0) + lds_tab[mx ? 1 : 0]; }
     bool persist = false;     // persistent launch through per-XCD work counters
     int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / mixed kernel
 };

@@ -64,10 +64,14 @@ struct ClassArgs {
 #define HFX_CONST_AS __attribute__((address_space(4)))
 
 // ---- Boys function tables ---------------------------------------------------
-// For every order L (0..BOYS_NL-1) one table of 64-byte rows:
-//   tab[(L * BOYS_NT + k) * 8 + j] = F_{L+j}(T_k) / j!,  T_k = k * BOYS_DT,
-// so that F_L(T) = sum_j tab[..j] (T_k - T)^j about the nearest grid point
-// (dF_m/dT = -F_{m+1}); one aligned row is one cache line.
+// For every order L (0..BOYS_NL-1) one block of 64-byte rows:
+//   block_L[k * 8 + j] = F_{L+j}(T_k) / j!,  T_k = k * BOYS_DT,
+// so that F_L(T) = sum_j block_L[k*8 + j] (T_k - T)^j about the nearest grid
+// point (dF_m/dT = -F_{m+1}); one aligned row is one cache line.  Blocks are
+// stored in the order 1, 0, 2, 3, ... (boys_block) so that the order-0 rows
+// directly follow the order-1 rows: a class of total angular momentum L
+// needs one contiguous range (two blocks for L = 1), which the class kernels
+// copy into LDS.
 #define BOYS_DT 0.1
 #define BOYS_INV_DT 10.0
 #define BOYS_TMAX 40.0
@@ -78,6 +82,10 @@ struct ClassArgs {
 #define BOYS_ORDER32 5   // Taylor terms, FP32 (remainder < 3e-9 F)
 
 void hfx_boys_table(double* tab);   // host, BOYS_NL * BOYS_NT * BOYS_ROW entries
+
+__host__ __device__ constexpr int boys_block(int L) { return L == 0 ? 1 : (L == 1 ? 0 : L); }
+// table entries a class of total angular momentum L reads (from its block on)
+__host__ __device__ constexpr int boys_entries(int L) { return (L == 1 ? 2 : 1) * BOYS_NT * BOYS_ROW; }
 
 __device__ __forceinline__ double hfx_sqrt(double x) { return sqrt(x); }
 // 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps
@@ -128,15 +136,16 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 // (for L = 1 both orders come from their tables, no exponential needed).
 // Above: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to FP64 there) and the upward recursion
 // F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m.
+// tab: the order-L block (followed by the order-0 block when L = 1).
 template <typename R, int L>
 __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) {
     constexpr int NO = BoysOrder<R>::value;
     if (T < R(BOYS_TMAX)) {
         const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
         const R d = R(k) * R(BOYS_DT) - T;
-        F[L] = boys_taylor<NO>(tab + ((size_t)L * BOYS_NT + k) * BOYS_ROW, d);
+        F[L] = boys_taylor<NO>(tab + k * BOYS_ROW, d);
         if constexpr (L == 1) {
-            F[0] = boys_taylor<NO>(tab + (size_t)k * BOYS_ROW, d);
+            F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * BOYS_ROW, d);
         } else if constexpr (L > 1) {
             const R e = hfx_exp(-T);
             const R t2 = R(2) * T;

@@ -184,7 +184,7 @@ __global__ void k_one_electron(const ShellDev* __restrict__ sh, int nshell, cons
                 const double PC[3] = {P[0] - atoms[4 * c], P[1] - atoms[4 * c + 1], P[2] - atoms[4 * c + 2]};
                 const double Tc = p * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
                 double F[5];
-                boys_eval<double, 4>(Tc, F, boys);
+                boys_eval<double, 4>(Tc, F, boys + (size_t)boys_block(4) * BOYS_NT * BOYS_ROW);
                 // e laid out as [lvl][comp] with offsets 0,1,4,10,20 ; m in [0..L-lvl]
                 double th[35][5];
                 const double pre = 2.0 * M_PI / p * kab;
