@@ -140,6 +140,7 @@ def batched_bench(args, log):
         tg = time_builds(lambda: bctx.graph_launch(sp), args.steps)
         graph_err = (F - F64).abs().max().item()
         bctx.configure(precision=hfx.HFX_PREC_MIXED)
+        ptab = autotune.autotune_precision(bctx, D.data_ptr(), F.data_ptr(), sp, sync=stream.synchronize)
         tmx = time_builds(lambda: bctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp), args.steps)
         mixed_err = (F - F64).abs().max().item()
         cmsmx = class_ms()
@@ -165,17 +166,19 @@ def batched_bench(args, log):
             "speedup_batched_vs_one_by_one": tseq / t64, "speedup_mixed_vs_fp64": t64 / tmx,
             "class_ms_fp64": cms64, "class_ms_mixed": cmsmx,
             "mixed_quartets_fp32": int(stm.quartets_fp32), "mixed_quartets_fp64": int(stm.quartets_fp64),
+            "mixed_fp32_classes": [k for k, v in ptab.items() if v["fp32"]],
             "autotune": autotune.summary(tuning)}
 
 
 def large_bench(args, log):
-    """512 waters (9728 basis functions), Schwarz tau 1e-11: FP64 and mixed
-    builds from a rank-2560 projector density, optionally full SCF in both
-    precisions (--large-scf)."""
+    """512 waters (9728 basis functions), Schwarz tau 1e-11: one GPU's share
+    (bra pairs r with r mod G = 0) of a G-GPU build, FP64 and mixed, from a
+    rank-2560 projector density; with --large-scf also full SCF."""
     import numpy as np
     import torch
     import workloads as W
     from paper_1708_00033_amd import hfx
+    G = args.large_shards
     mol = W.cluster512_config()
     t0 = time.time()
     ctx = hfx.Context(device=0, schwarz_tau=1e-11).load(mol)
@@ -185,28 +188,33 @@ def large_bench(args, log):
     log(f"512 waters loaded in {t_load:.1f} s: nbf={ctx.nbf} quartets={quartets:.4e}")
     dev = torch.device("cuda:0")
     D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 33), device=dev)
-    F64 = torch.empty_like(D)
-    Fmx = torch.empty_like(D)
+    G64 = torch.empty_like(D)
+    Gmx = torch.empty_like(D)
     sp = torch.cuda.current_stream(dev).cuda_stream
-    out = {"workload": "512-water jittered lattice cluster, seed 3, 5120 shells, 9728 basis functions, "
-                       "Schwarz tau 1e-11, projector density of rank 2560",
+    out = {"workload": f"512-water jittered lattice cluster, seed 3, 5120 shells, 9728 basis functions, "
+                       f"Schwarz tau 1e-11, projector density of rank 2560; one GPU's share (1/{G} of the bra "
+                       f"pairs) of a {G}-GPU build",
            "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
-           "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load}
-    for prec, Fo, tag in ((hfx.HFX_PREC_FP64, F64, "fp64"), (hfx.HFX_PREC_MIXED, Fmx, "mixed")):
+           "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load, "shards": G,
+           "digest_modes": sorted(set(p["mode"] for p in ctx.plans()))}
+    for prec, Go, tag in ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed")):
         ctx.configure(precision=prec)
         ctx.kernel_timing(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        st = ctx.build_fock_dev(D.data_ptr(), Fo.data_ptr(), sp, stats=True)
+        st = ctx.build_2e_shard_dev(D.data_ptr(), 2.0, 1.0, 0, G, Go.data_ptr(), sp, stats=True)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t
         ms, n = ctx.kernel_times()
         ctx.kernel_timing(False)
-        out[tag] = {"build_s": dt, "quartets_per_s": quartets / dt, "quartets_fp32": int(st.quartets_fp32),
+        q = int(st.quartets_fp64 + st.quartets_fp32)
+        out[tag] = {"share_build_s": dt, "share_quartets": q, "quartets_per_s": q / dt,
+                    "quartets_fp32": int(st.quartets_fp32),
                     "class_ms": {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}}
-        log(f"512 waters {tag} build: {dt:.2f} s, {quartets / dt:.3e} quartets/s")
-    out["mixed"]["max_abs_dF_vs_fp64"] = (Fmx - F64).abs().max().item()
-    out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(torch.sum(D * (Fmx - F64)).item())
-    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["build_s"] / out["mixed"]["build_s"]
+        log(f"512 waters {tag} share build: {dt:.2f} s, {q:.3e} quartets, {q / dt:.3e} quartets/s")
+    out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
+    out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(0.5 * torch.sum(D * (Gmx - G64)).item())
+    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed"]["share_build_s"]
     if args.large_scf:
         for prec, tag in ((hfx.HFX_PREC_FP64, "scf_fp64"), (hfx.HFX_PREC_MIXED, "scf_mixed")):
             ctx.configure(precision=prec)
@@ -230,6 +238,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
     ap.add_argument("--large", action="store_true", help="also time FP64 and mixed builds of 512 waters")
     ap.add_argument("--large-scf", action="store_true", help="with --large: full SCF in both precisions")
+    ap.add_argument("--large-shards", type=int, default=8, help="with --large: time one GPU's share of this many")
     ap.add_argument("--only-large", action="store_true", help="run only the 512-water part")
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
     ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
@@ -319,6 +328,11 @@ def main():
         return dt, ms, n, plans, st
 
     dt64, ms64, n64, plans64, st64 = timed(args.steps, F64, hfx.HFX_PREC_FP64)
+    fp32_classes = None
+    if not args.no_autotune:   # per class: FP32 kernel on where it is faster
+        ctx.configure(precision=hfx.HFX_PREC_MIXED)
+        ptab = autotune.autotune_precision(ctx, D.data_ptr(), Fmx.data_ptr(), sptr)
+        fp32_classes = [k for k, v in ptab.items() if v["fp32"]]
     dtmx, msmx, nmx, plansmx, stmx = timed(args.steps, Fmx, hfx.HFX_PREC_MIXED)
     quartets = int(counts[:, 0].sum())
     value = quartets * args.steps / dt64
@@ -366,6 +380,7 @@ def main():
         "mixed": {"value": value_mx, "unit": "quartets/s", "ms_per_step": dtmx / args.steps * 1e3,
                   "speedup_vs_fp64": dt64 / dtmx, "fp32_tau": 1e-7, "quartets_fp32": int(stmx.quartets_fp32),
                   "quartets_fp64": int(stmx.quartets_fp64), "max_abs_dF_vs_fp64": Fd,
+                  "fp32_classes": fp32_classes,
                   "dE_vs_fp64_at_fixed_D": dE},
         "roofline": {"bound": "alu", "kernel": kname, "class": hfx.CLASS_NAMES[dom["cls"]],
                      "ket_nprim": dom["ket_nprim"], "achieved": achieved,

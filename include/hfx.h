@@ -74,10 +74,9 @@ typedef struct {
     int device;            /* HIP device ordinal */
     double schwarz_tau;    /* quartet kept iff Q_ab Q_cd >= tau (default 1e-10) */
     int precision;         /* HFX_PREC_FP64 or HFX_PREC_MIXED */
-    double fp32_tau;       /* MIXED: a quartet may be evaluated in FP32 only if
-                              Q_ab Q_cd max|D| < fp32_tau (default 1e-7); the
-                              choice is made per 64 consecutive kets of a bra
-                              (one wavefront), FP64 unless all of them qualify */
+    double fp32_tau;       /* MIXED: FP32 iff Q_ab Q_cd max|D| < fp32_tau (default
+                              1e-7); the classes with a d-d bra and a d-d or d-p
+                              ket stay FP64 */
     int digest;            /* HFX_DIGEST_LDS (bra rows staged in LDS) or HFX_DIGEST_GLOBAL */
     int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
@@ -171,9 +170,11 @@ hfx_status hfx_graph_launch(hfx_ctx *ctx, void *stream);
  * bra shell pairs r with r % nshards == shard (r = position in each class's
  * Schwarz-ordered bra list).  Summing the nshards results gives the full
  * two-electron matrix (the partial Fock matrices that the paper's
- * ddi_gsumf reduces in algorithms 1-3). */
+ * ddi_gsumf reduces in algorithms 1-3).  stats (optional, synchronises):
+ * the shard's quartet counts; integral and primitive totals are the whole
+ * build's. */
 hfx_status hfx_build_2e_shard_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, int shard,
-                                  int nshards, double *dG, void *stream);
+                                  int nshards, double *dG, void *stream, hfx_fock_stats *stats);
 
 /* Closed-shell SCF to convergence (section 3, eq. 1): guess, Fock build,
  * Pulay DIIS, eigensolve of X^T F X, aufbau density.  D_out, C_out
@@ -200,6 +201,11 @@ hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
 hfx_status hfx_set_class_tuning(hfx_ctx *ctx, int cls, int task_quartets, int xcd_stripe, int persistent,
                                 int digest);
 
+/* Mixed builds (class index 0..20, or -1 for all): 1 (default) evaluates
+ * the class's FP32-eligible quartets with its FP32 kernel, 0 keeps the class
+ * in FP64 (never less accurate).  Chosen per class by the autotuner. */
+hfx_status hfx_set_class_precision(hfx_ctx *ctx, int cls, int fp32);
+
 /* Per-class plan counts: counts[21*4] = {unique quartets, integrals,
  * primitive quartets, workgroup tasks} for each canonical quartet class in
  * the order (ss|ss), (ps|ss), (ps|ps), (pp|ss), ..., (dd|dd). */
@@ -215,8 +221,9 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 /* Launches of a build: one per (quartet class, ket primitive count).
  * info[11] = {class index, ket primitives per pair, workgroup tasks, unique
  * quartets, primitive quartets, integrals, timed launches, digestion mode,
- * work-items per workgroup, persistent (0/1), workgroups launched at the
- * current precision}; *ms = summed event time of the timed launches. */
+ * work-items per workgroup, persistent (0/1), workgroups of the FP64
+ * kernel}; *ms = summed event time of the timed launches (a mixed build
+ * times its FP64 and FP32 kernels together). */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 

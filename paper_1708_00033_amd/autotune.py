@@ -74,6 +74,35 @@ def autotune(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int,
     return table
 
 
+def autotune_precision(ctx: "hfx.Context", dD_ptr: int, dF_ptr: int, stream: int, reps: int = 2, sync=None,
+                       margin: float = 0.02) -> Dict[str, dict]:
+    """For a context configured for mixed builds: time every class with its
+    FP32 kernel on and off, keep FP32 where it is faster by more than
+    ``margin`` (FP64 is never less accurate), apply and return
+    {class name: {"fp32", "ms_fp32", "ms_fp64"}}."""
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
+    times = np.full((2, 21), np.inf)
+    for on in (0, 1):
+        ctx.set_class_precision(-1, on)
+        ctx.build_fock_dev(dD_ptr, dF_ptr, stream)
+        sync()
+        ctx.kernel_timing(True)
+        for _ in range(reps):
+            ctx.build_fock_dev(dD_ptr, dF_ptr, stream)
+        sync()
+        ms, n = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        times[on] = ms / np.maximum(n, 1)
+    table = {}
+    for k in range(21):
+        on = int(times[1, k] < times[0, k] * (1.0 - margin))
+        ctx.set_class_precision(k, on)
+        table[hfx.CLASS_NAMES[k]] = {"fp32": on, "ms_fp32": float(times[1, k]), "ms_fp64": float(times[0, k])}
+    return table
+
+
 def apply(ctx: "hfx.Context", table: Dict[str, dict]) -> None:
     for name, v in table.items():
         ctx.set_class_tuning(hfx.CLASS_NAMES.index(name), int(v["task_quartets"]), int(v["xcd_stripe"]),

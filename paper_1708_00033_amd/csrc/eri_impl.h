@@ -298,17 +298,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One class, one digestion mode, one precision policy (MIXED = 1: waves whose
-// kets all lie at or beyond split[r] are evaluated in FP32 and widened before
-// digestion).
+// One class, one digestion mode, one precision (FP32 = 0: FP64 evaluation;
+// FP32 = 1: FP32 evaluation widened to FP64 before digestion).  A mixed
+// build launches both over complementary ket ranges of every task: the FP64
+// kernel below split[r], the FP32 kernel from split[r] on.
 //
-// LDS of a class kernel: the class's Boys rows (FP64, then FP32 for MIXED),
+// LDS of a class kernel: the class's Boys rows in the kernel's precision,
 // then (MODE 0) the bra rows F_I, F_J of the current task.
-template <class E, int MIXED>
+template <class E, int FP32>
 struct LdsLayout {
     static constexpr int L = E::LA + E::LB + E::LC + E::LD;
-    static constexpr int T64 = boys_entries(L);              // doubles
-    static constexpr int T32 = MIXED ? boys_entries(L) : 0;  // floats
+    static constexpr int T64 = FP32 ? 0 : boys_entries(L);   // doubles
+    static constexpr int T32 = FP32 ? boys_entries(L) : 0;   // floats
     static constexpr int ROWS = T64 + T32 / 2;               // offset of the bra rows, doubles
 };
 
@@ -317,34 +318,38 @@ __device__ __forceinline__ bool task_active(const ClassArgs& a, const int4 task)
     return task.x >= 0 && (a.nshards <= 1 || task.x % a.nshards == a.shard);
 }
 
-template <class E, int MIXED>
+template <class E, int FP32>
 __device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, float* t32) {
-    using LL = LdsLayout<E, MIXED>;
-    const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-    for (int i = threadIdx.x; i < LL::T64; i += E::WGS) t64[i] = g64[i];
-    if constexpr (MIXED) {
+    using LL = LdsLayout<E, FP32>;
+    if constexpr (FP32) {
         const float* __restrict__ g32 = a.boys32 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
         for (int i = threadIdx.x; i < LL::T32; i += E::WGS) t32[i] = g32[i];
+    } else {
+        const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
+        for (int i = threadIdx.x; i < LL::T64; i += E::WGS) t64[i] = g64[i];
     }
     __syncthreads();
 }
 
-template <class E, int MODE, int MIXED>
+template <class E, int MODE, int FP32>
 __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, const double* t64,
                                            const float* t32) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     extern __shared__ __align__(16) double lds[];
-    const int r = task.x, s0 = task.y;
+    const int r = task.x;
     if (!task_active(a, task)) return;
+    // kets [s0, send) of the list; a mixed build's part keeps one side of split[r]
+    int s0 = task.y, send = task.z;
+    if (a.part == 1) send = min(send, a.split[r]);
+    else if (a.part == 2) s0 = max(s0, a.split[r]);
+    if (s0 >= send) return;                                   // uniform: nothing of this part here
     const PairInfo bra = a.bra[r];
     // the bra's molecule: its blocks of D' and W, leading dimension ld
     const int N = bra.ld;
     const double* __restrict__ Dm = a.D + a.moff[bra.mol];
     double* __restrict__ Wm = a.W + a.moff[bra.mol];
-    const int send = task.z;                                  // kets [s0, send) of the list
-    const int split = MIXED ? a.split[r] : send;
-    double* FI = lds + LdsLayout<E, MIXED>::ROWS;
+    double* FI = lds + LdsLayout<E, FP32>::ROWS;
     double* FJ = FI + NA * N;
     if constexpr (MODE == 0) {
         for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) FI[i] = 0.0;
@@ -377,10 +382,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, 
             continue;
         }
         double I[NI];
-        // precision per wavefront: FP32 only when every ket of the wave lies
-        // at or beyond the split (no divergent FP64/FP32 waves)
-        const int wave_first = __builtin_amdgcn_readfirstlane(s - (int)(threadIdx.x & 63));
-        if (!MIXED || wave_first < split) {
+        if constexpr (!FP32) {
             E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
                                     ket.AB, t64, I);
             ++n64;
@@ -430,15 +432,15 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, 
 }
 
 // Static launch: workgroup i runs task i.
-template <class E, int MODE, int MIXED>
+template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     const int4 task = a.tasks[blockIdx.x];
     if (!task_active(a, task)) return;
     double* t64 = lds;
-    float* t32 = reinterpret_cast<float*>(lds + LdsLayout<E, MIXED>::T64);
-    load_boys_lds<E, MIXED>(a, t64, t32);
-    class_task<E, MODE, MIXED>(a, task, t64, t32);
+    float* t32 = reinterpret_cast<float*>(lds);
+    load_boys_lds<E, FP32>(a, t64, t32);
+    class_task<E, MODE, FP32>(a, task, t64, t32);
 }
 
 // Persistent launch: a resident grid; a workgroup on XCD x (workgroup index
@@ -447,13 +449,13 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
 // no XCD idles while another still has work (the dynamic load balancing of
 // ddi_dlbnext in algorithms 1-3).  A separate kernel so that the static
 // form keeps its register allocation.
-template <class E, int MODE, int MIXED>
+template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
     double* t64 = lds;
-    float* t32 = reinterpret_cast<float*>(lds + LdsLayout<E, MIXED>::T64);
-    load_boys_lds<E, MIXED>(a, t64, t32);   // once per resident workgroup
+    float* t32 = reinterpret_cast<float*>(lds);
+    load_boys_lds<E, FP32>(a, t64, t32);   // once per resident workgroup
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -465,7 +467,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, MIXED>(a, a.tasks[8 * k + x], t64, t32);
+        class_task<E, MODE, FP32>(a, a.tasks[8 * k + x], t64, t32);
     }
 }
 
@@ -502,17 +504,16 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
 }
 
 
-// Kernel variants of one class: digestion mode x precision policy.  Classes
-// with integral blocks of HFX_ROLLED_DIGEST_MIN or more (d-d bra with a d-d or
-// d-p ket) exist only in FP64 (both digestion modes): their register
-// allocation is the build-time bottleneck and they carry a negligible share
-// of the quartets, so MIXED requests run the FP64 kernel (the more accurate
-// choice).
+// Kernel variants of one class: launch form x digestion mode x precision.
+// Classes with integral blocks of HFX_ROLLED_DIGEST_MIN or more (d-d bra with
+// a d-d or d-p ket) exist only in FP64: their register allocation is the
+// build-time bottleneck and they carry a negligible share of the quartets,
+// so mixed builds evaluate them in FP64 (the more accurate choice).
 template <class E>
 struct ClassKernels {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
-    // variant = 4 persistent + 2 mode + mixed
+    // variant = 4 persistent + 2 mode + fp32
     static const void* get(int variant) {
         if constexpr (kOnlyFp64Global) {
             static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 1, 0>,
@@ -528,8 +529,8 @@ struct ClassKernels {
     }
 };
 
-// Per-class translation unit: evaluator wrapper, the four kernel variants
-// (digestion mode x precision policy), the Schwarz kernel and C lookups.
+// Per-class translation unit: evaluator wrapper, the kernel variants, the
+// Schwarz kernel and C lookups.
 #define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_)                                               \
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \

@@ -303,16 +303,16 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
     const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
-    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);
-    P.lds_tab[1] = P.lds_tab[0] + (P.fp64_only ? 0 : (size_t)boys_entries(Ltot) * sizeof(float));
+    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);   // FP64 kernel
+    P.lds_tab[1] = (size_t)boys_entries(Ltot) * sizeof(float);    // FP32 kernel of a mixed build
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
-    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[1] <= 160 * 1024 - 256) ? 0 : 1;
+    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;
     if (P.ntask == 0) return HFX_OK;
     P.persist = c->tune_persist[P.cid] > 0;
-    for (int mx = 0; mx < 2; ++mx) {
+    for (int mx = 0; mx < (P.fp64_only ? 1 : 2); ++mx) {
         const size_t lds = P.lds(mx != 0);
-        int nb = hfx_class_resident_blocks(P.cid, P.mode, mx && !P.fp64_only, lds);
+        int nb = hfx_class_resident_blocks(P.cid, P.mode, mx, lds);
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
@@ -359,7 +359,7 @@ static hfx_status replan(hfx_ctx* c) {
     for (int i = 0; i < 21; ++i) rank[order[i]] = i;
     std::stable_sort(c->plans.begin(), c->plans.end(),
                      [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
-    HIPCK(dalloc(&c->d_work, 8 * std::max<size_t>(c->plans.size(), 1)));
+    HIPCK(dalloc(&c->d_work, 16 * std::max<size_t>(c->plans.size(), 1)));   // FP64 and FP32 launches
     if (c->timing)
         for (auto& p : c->plans) {
             HIPCK(hipEventCreate(&p.ev0));
@@ -387,6 +387,15 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     if (!c->loaded) return HFX_OK;
     HIPCK(hipSetDevice(c->opt.device));
     return replan(c);
+}
+
+extern "C" hfx_status hfx_set_class_precision(hfx_ctx* c, int cid, int fp32) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (cid < -1 || cid >= 21) return hfx_fail(c, HFX_ERR_INVALID_ARG, "class index out of range");
+    if (fp32 < 0 || fp32 > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "fp32 must be 0 or 1");
+    for (int k = 0; k < 21; ++k)
+        if (cid == -1 || cid == k) c->tune_fp32[k] = fp32;
+    return HFX_OK;
 }
 
 extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int* Z, const double* xyz,
@@ -879,8 +888,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[7] = p.mode;
     info[8] = hfx_class_wgs(p.cid);
     info[9] = p.persist ? 1 : 0;
-    const bool mx = c->opt.precision == HFX_PREC_MIXED && !p.fp64_only;
-    info[10] = p.persist ? p.nblocks[mx ? 1 : 0] : p.ntask;
+    info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
     if (ms) *ms = p.ms;
     return HFX_OK;
 }
@@ -902,12 +910,12 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
     for (auto& KL : c->ketlists) HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
     bool any_persist = false;
     for (const auto& P : c->plans) any_persist |= P.persist;
-    if (any_persist) HIPCK(hfx_fill_u64(c->d_work, 8 * (int)c->plans.size(), st));
+    if (any_persist) HIPCK(hfx_fill_u64(c->d_work, 16 * (int)c->plans.size(), st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
         const int cid = P.cid;
-        const bool mx = mixed && !P.fp64_only;
+        const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid];
         if (mx)
             HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_kseg, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
                             st));
@@ -931,11 +939,17 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.ck = ck;
         a.shard = shard;
         a.nshards = nshards;
-        a.work = P.persist ? c->d_work + 8 * pi : nullptr;
+        a.work = P.persist ? c->d_work + 16 * pi : nullptr;
         a.qlen = P.ntask / 8;
-        const int nblocks = P.persist ? P.nblocks[mx ? 1 : 0] : P.ntask;
+        a.part = mx ? 1 : 0;
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        HIPCK(hfx_launch_class(cid, P.mode, mx ? 1 : 0, nblocks, P.lds(mx), st, &a));
+        HIPCK(hfx_launch_class(cid, P.mode, 0, P.persist ? P.nblocks[0] : P.ntask, P.lds(false), st, &a));
+        if (mx) {   // the same tasks' kets from split[r] on, in FP32
+            ClassArgs b = a;
+            b.part = 2;
+            b.work = P.persist ? c->d_work + 16 * pi + 8 : nullptr;
+            HIPCK(hfx_launch_class(cid, P.mode, 1, P.persist ? P.nblocks[1] : P.ntask, P.lds(true), st, &b));
+        }
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));
             P.pending = true;
@@ -988,12 +1002,12 @@ extern "C" hfx_status hfx_build_2e_dev(hfx_ctx* c, const double* dD, double cj, 
 }
 
 extern "C" hfx_status hfx_build_2e_shard_dev(hfx_ctx* c, const double* dD, double cj, double ck, int shard,
-                                             int nshards, double* dG, void* stream) {
+                                             int nshards, double* dG, void* stream, hfx_fock_stats* stats) {
     if (!c || !dD || !dG) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     if (nshards < 1 || shard < 0 || shard >= nshards) return hfx_fail(c, HFX_ERR_INVALID_ARG, "bad shard");
     if (!std::isfinite(cj) || !std::isfinite(ck)) return hfx_fail(c, HFX_ERR_INVALID_ARG, "non-finite cj/ck");
     HIPCK(hipSetDevice(c->opt.device));
-    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, nullptr, shard, nshards);
+    return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, stats, shard, nshards);
 }
 
 // ---- HIP graph of one build -------------------------------------------------------

@@ -38,7 +38,7 @@ struct SubPlan {
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;     // bra rows F_I, F_J (LDS digestion)
-    size_t lds_tab[2] = {0, 0};   // Boys rows in LDS for the FP64 / mixed kernel
+    size_t lds_tab[2] = {0, 0};   // Boys rows in LDS for the FP64 / FP32 kernel
     int mode = 0;             // digestion actually used (LDS may fall back to global)
     // timing (when enabled): events around this launch, summed milliseconds
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -48,7 +48,7 @@ struct SubPlan {
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
     size_t lds(bool mx) const { return (mode == 0 ? lds_bytes : 0) + lds_tab[mx ? 1 : 0]; }
     bool persist = false;     // persistent launch through per-XCD work counters
-    int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / mixed kernel
+    int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / FP32 kernel
 };
 
 struct ClassTotals {
@@ -102,6 +102,8 @@ struct hfx_ctx {
     int tune_stripe[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
                            -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: default (striped)
     int tune_persist[21] = {0};                  // 1: persistent launch
+    int tune_fp32[21] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                         1, 1, 1, 1, 1, 1, 1, 1, 1, 1};   // mixed builds: FP32 kernel for eligible quartets
     int tune_digest[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
                            -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: opt.digest
     unsigned long long* d_work = nullptr;        // 8 queue counters per plan

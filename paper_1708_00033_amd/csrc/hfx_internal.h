@@ -42,12 +42,14 @@ struct ClassArgs {
     const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
     int nket_list, knprim;
-    const int* __restrict__ split;      // per bra: kets below this list position use FP64
+    const int* __restrict__ split;      // per bra: kets below this list position use FP64 (mixed builds)
     const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0); bra -1: empty.  Task 8k + x is
                                         // entry k of XCD x's queue
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
                                             // launch); null: one task per workgroup
     int qlen;                           // entries per XCD queue (tasks = 8 qlen)
+    int part;                           // mixed builds: 1 = kets before split[r] (FP64 kernel),
+                                        // 2 = kets from split[r] on (FP32 kernel); 0 = all kets
     const long long* __restrict__ moff; // per molecule: element offset of its blocks in D', W
     const double* __restrict__ boys64;
     const float* __restrict__ boys32;

@@ -98,11 +98,12 @@ _sigs = {
     "hfx_build_2e_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                           C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_build_2e_shard_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p,
-                                C.c_void_p], C.c_int),
+                                C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
     "hfx_class_counts": ([_ctx_p, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_set_class_tuning": ([_ctx_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "hfx_set_class_precision": ([_ctx_p, C.c_int, C.c_int], C.c_int),
     "hfx_kernel_timing": ([_ctx_p, C.c_int], C.c_int),
     "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_plan_count": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
@@ -293,9 +294,11 @@ class Context:
         return st
 
     def build_2e_shard_dev(self, dD_ptr: int, cj: float, ck: float, shard: int, nshards: int, dG_ptr: int,
-                           stream: int = 0):
+                           stream: int = 0, stats: bool = False):
+        st = hfx_fock_stats() if stats else None
         self._check(hfx_build_2e_shard_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, shard, nshards, C.c_void_p(dG_ptr),
-                                           C.c_void_p(stream)))
+                                           C.c_void_p(stream), C.byref(st) if stats else None))
+        return st
 
     def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, model: "GuessNet" = None, **kw):
         o = default_scf_options(**kw)
@@ -371,6 +374,9 @@ class Context:
     def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1, persistent: int = 0,
                          digest: int = -1):
         self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe, persistent, digest))
+
+    def set_class_precision(self, cls: int, fp32: int):
+        self._check(hfx_set_class_precision(self.ptr, cls, fp32))
 
     def apply_tuning(self, table: dict):
         """table: {class index or name: {"task_quartets", "xcd_stripe", "persistent", "digest"}}"""

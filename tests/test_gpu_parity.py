@@ -118,17 +118,44 @@ def test_mixed_precision_dimer(dimer):
     assert abs(r["energy"] - r64["energy"]) < 1e-6
 
 
-def test_mixed_precision_wavefronts_16_waters():
-    """FP32 is chosen per wavefront of kets; a 16-water cluster has long ket
-    runs beyond the split, so a large share goes FP32, within tolerance."""
+@pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1)])
+def test_mixed_precision_16_waters(persistent, digest):
+    """A mixed build runs an FP64 kernel before each bra's split and an FP32
+    kernel from it on; a 16-water cluster puts a large share in FP32.  Both
+    launch forms and both digestions agree with FP64 within tolerance."""
     m = W.water_cluster(16, 77)
     D = W.random_orthonormal_density(m.nbf, m.nocc, 5)
     F64, s64 = _hfx().Context().load(m).build_fock(D)
-    Fmx, smx = _hfx().Context(precision=1).load(m).build_fock(D)
+    ctx = _hfx().Context(precision=1).load(m)
+    ctx.set_class_tuning(-1, 2048, 1, persistent, digest)
+    Fmx, smx = ctx.build_fock(D)
     assert smx.quartets_fp32 + smx.quartets_fp64 == s64.quartets_fp64
     assert smx.quartets_fp32 > 0.2 * s64.quartets_fp64
     assert np.abs(Fmx - F64).max() < 1e-6
     assert abs(np.sum(D * (Fmx - F64))) < 1e-6
+
+
+def test_precision_autotuner_keeps_tolerance():
+    """Per-class FP32 choice (autotuned or forced off) changes only which
+    eligible quartets run in FP32: FP64-only equals the FP64 build."""
+    import torch
+    from paper_1708_00033_amd import autotune
+    m = W.water_cluster(16, 78)
+    D = W.random_orthonormal_density(m.nbf, m.nocc, 6)
+    F64, s64 = _hfx().Context().load(m).build_fock(D)
+    ctx = _hfx().Context(precision=1).load(m)
+    dD = torch.tensor(D, device="cuda")
+    dF = torch.empty_like(dD)
+    s = torch.cuda.current_stream().cuda_stream
+    table = autotune.autotune_precision(ctx, dD.data_ptr(), dF.data_ptr(), s, reps=1)
+    assert set(table) == set(_hfx().CLASS_NAMES)
+    Fmx, smx = ctx.build_fock(D)
+    assert smx.quartets_fp32 + smx.quartets_fp64 == s64.quartets_fp64
+    assert np.abs(Fmx - F64).max() < 1e-6
+    ctx.set_class_precision(-1, 0)
+    Fo, so = ctx.build_fock(D)
+    assert so.quartets_fp32 == 0
+    assert np.abs(Fo - F64).max() <= 1e-13 * np.abs(F64).max()
 
 
 def test_invalid_inputs():
