@@ -156,6 +156,16 @@ def batched_bench(args, log):
                 c.build_fock_dev(d.data_ptr(), f.data_ptr(), sp)
         tseq = time_builds(one_by_one, max(1, args.steps // 2))
         seq_err = (F - F64).abs().max().item()
+        # SCF: all 256 in lockstep vs the first 32 one molecule at a time
+        stream.synchronize()
+        t = time.perf_counter()
+        bres, _ = bctx.batch_scf()
+        t_bscf = time.perf_counter() - t
+        t = time.perf_counter()
+        sres = [c.scf() for c in ctxs[:32]]
+        t_sscf32 = time.perf_counter() - t
+        dE = max(abs(b["energy"] - r["energy"]) for b, r in zip(bres[:32], sres))
+        log(f"batched SCF of 256 clusters: {t_bscf:.1f} s; 32 single SCFs: {t_sscf32:.1f} s")
     return {"workload": "256 water clusters, sizes ~U{1..16} (seed 2), molecule i seed 2e6+i, s/p/d basis",
             "molecules": len(mols), "basis_functions": int(nbf.sum()), "quartets_per_build": quartets,
             "load_s": t_load,
@@ -165,6 +175,11 @@ def batched_bench(args, log):
             "one_context_per_molecule_ms": tseq * 1e3, "one_context_per_molecule_max_abs_diff": seq_err,
             "speedup_batched_vs_one_by_one": tseq / t64, "speedup_mixed_vs_fp64": t64 / tmx,
             "class_ms_fp64": cms64, "class_ms_mixed": cmsmx,
+            "scf": {"batched_s": t_bscf, "batched_converged": int(sum(r["converged"] for r in bres)),
+                    "batched_max_iterations": int(max(r["iterations"] for r in bres)),
+                    "one_by_one_first32_s": t_sscf32, "one_by_one_256_estimate_s": t_sscf32 * 8,
+                    "speedup_batched_vs_one_by_one_est": t_sscf32 * 8 / t_bscf,
+                    "max_abs_dE_first32": dE},
             "mixed_quartets_fp32": int(stm.quartets_fp32), "mixed_quartets_fp64": int(stm.quartets_fp64),
             "mixed_fp32_classes": [k for k, v in ptab.items() if v["fp32"]],
             "autotune": autotune.summary(tuning)}

@@ -183,6 +183,17 @@ hfx_status hfx_build_2e_shard_dev(hfx_ctx *ctx, const double *dD, double cj, dou
 hfx_status hfx_scf(hfx_ctx *ctx, const hfx_scf_options *opt, hfx_scf_result *res, double *D_out,
                    double *C_out, double *eps_out);
 
+/* SCF of every molecule of a batch (hfx_load_batch) in lockstep: per
+ * iteration one batched Fock build for all molecules, then per molecule the
+ * energy and Pulay DIIS, and one batched eigensolve (rocSOLVER, each
+ * X^T F X padded to the largest molecule).  guess: SAD or CORE, or
+ * opt->D0 as a ragged host density (hfx_batch_layout offsets); the learned
+ * guess runs per molecule (hfx_scf).  res[nmol]: per molecule (times are
+ * the whole batch's).  D_out (optional): ragged host densities.  A
+ * converged molecule keeps its density while the others iterate.  Returns
+ * HFX_ERR_NOT_CONVERGED (with res filled) if any molecule did not converge. */
+hfx_status hfx_batch_scf(hfx_ctx *ctx, const hfx_scf_options *opt, hfx_scf_result *res, double *D_out);
+
 /* Change precision / digestion / task size of a loaded context (schwarz_tau
  * and device must stay as created). */
 hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);

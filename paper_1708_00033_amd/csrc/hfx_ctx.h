@@ -161,6 +161,9 @@ hipError_t hfx_lincomb(const double* const* M, const double* c, int m, size_t n,
 hipError_t hfx_scale_cols(const double* U, const double* w, const int* keep, int n, int nk, double* out,
                           hipStream_t st);
 hipError_t hfx_weight_cols(const double* C, const double* occ, int n, int nk, double* out, hipStream_t st);
+hipError_t hfx_pad_blocks(const double* src, const long long* moff, const int* dim, int nmol, int NP, double pad,
+                          double* dst, hipStream_t st);
+hipError_t hfx_pad_rest(const int* dim, int nmol, int NP, double pad, double* dst, hipStream_t st);
 // eri_dispatch.hip
 hipError_t hfx_launch_class(int cid, int mode, int mixed, int nblocks, size_t lds_bytes, hipStream_t stream,
                             const ClassArgs* args);

@@ -3,6 +3,8 @@
 // small SCF helpers.  All are HBM-bound elementwise passes or tiny.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "hfx_internal.h"
 
 #define MISC_WG 256
@@ -332,6 +334,34 @@ __global__ void k_scale_cols(const double* __restrict__ U, const double* __restr
     }
 }
 
+// Batched eigensolves over molecules of different sizes: slot m (NP x NP) of
+// dst holds molecule m's block (n_m x n_m) in its top-left corner, `pad` on
+// the rest of the diagonal and zeros elsewhere, so that the slot's
+// eigenpairs are the block's plus (pad, unit vectors), sorted after them.
+__global__ void k_pad_blocks(const double* __restrict__ src, const long long* __restrict__ moff,
+                             const int* __restrict__ dim, int NP, double pad, double* __restrict__ dst) {
+    const int mol = blockIdx.y;
+    const int n = dim[mol];
+    const size_t tot = (size_t)NP * NP;
+    double* __restrict__ d = dst + (size_t)mol * tot;
+    for (size_t i = (size_t)blockIdx.x * MISC_WG + threadIdx.x; i < tot; i += (size_t)gridDim.x * MISC_WG) {
+        const int r = (int)(i / NP), col = (int)(i % NP);
+        d[i] = (r < n && col < n) ? src[moff[mol] + (size_t)r * n + col] : (r == col ? pad : 0.0);
+    }
+}
+
+// Outside the top-left k_m x k_m block of every slot: pad on the diagonal, zeros elsewhere.
+__global__ void k_pad_rest(const int* __restrict__ dim, int NP, double pad, double* __restrict__ dst) {
+    const int mol = blockIdx.y;
+    const int k = dim[mol];
+    const size_t tot = (size_t)NP * NP;
+    double* __restrict__ d = dst + (size_t)mol * tot;
+    for (size_t i = (size_t)blockIdx.x * MISC_WG + threadIdx.x; i < tot; i += (size_t)gridDim.x * MISC_WG) {
+        const int r = (int)(i / NP), col = (int)(i % NP);
+        if (r >= k || col >= k) d[i] = (r == col) ? pad : 0.0;
+    }
+}
+
 // C (column-major n x nmo) -> weighted density D = sum_k occ_k C_k C_k^T
 __global__ void k_weight_cols(const double* __restrict__ C, const double* __restrict__ occ, int n, int nk,
                               double* __restrict__ out) {
@@ -422,6 +452,17 @@ hipError_t hfx_lincomb(const double* const* M, const double* c, int m, size_t n,
 hipError_t hfx_scale_cols(const double* U, const double* w, const int* keep, int n, int nk, double* out,
                           hipStream_t st) {
     hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((size_t)n * nk)), dim3(MISC_WG), 0, st, U, w, keep, n, nk, out);
+    return hipGetLastError();
+}
+hipError_t hfx_pad_blocks(const double* src, const long long* moff, const int* dim, int nmol, int NP, double pad,
+                          double* dst, hipStream_t st) {
+    const unsigned gx = (unsigned)std::min<size_t>(((size_t)NP * NP + MISC_WG - 1) / MISC_WG, 1024);
+    hipLaunchKernelGGL(k_pad_blocks, dim3(gx, nmol), dim3(MISC_WG), 0, st, src, moff, dim, NP, pad, dst);
+    return hipGetLastError();
+}
+hipError_t hfx_pad_rest(const int* dim, int nmol, int NP, double pad, double* dst, hipStream_t st) {
+    const unsigned gx = (unsigned)std::min<size_t>(((size_t)NP * NP + MISC_WG - 1) / MISC_WG, 1024);
+    hipLaunchKernelGGL(k_pad_rest, dim3(gx, nmol), dim3(MISC_WG), 0, st, dim, NP, pad, dst);
     return hipGetLastError();
 }
 hipError_t hfx_weight_cols(const double* C, const double* occ, int n, int nk, double* out, hipStream_t st) {

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "hfx_ctx.h"
@@ -120,6 +121,28 @@ std::vector<double> fractional_occupation(const std::vector<double>& eps, double
         i = j + 1;
     }
     return occ;
+}
+
+// DIIS Gram matrix B (row-major m x m, oldest vector first) of a ring buffer
+// of dmax slots starting at head: make room for a new newest vector, dropping
+// the oldest when full.  On return B is m x m with a zero last row and column
+// for the new vector, stored in ring slot *slot.
+void diis_make_room(std::vector<double>& B, int& m, int& head, int dmax, int* slot) {
+    if (m < dmax) {
+        *slot = (head + m) % dmax;
+        std::vector<double> nb((size_t)(m + 1) * (m + 1), 0.0);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) nb[i * (m + 1) + j] = B[i * m + j];
+        B.swap(nb);
+        ++m;
+    } else {
+        *slot = head;
+        head = (head + 1) % dmax;
+        std::vector<double> nb((size_t)m * m, 0.0);
+        for (int i = 1; i < m; ++i)
+            for (int j = 1; j < m; ++j) nb[(i - 1) * m + (j - 1)] = B[i * m + j];
+        B.swap(nb);
+    }
 }
 
 double host_sum(const std::vector<double>& v, int n) {
@@ -268,39 +291,19 @@ static hfx_status scf_core(hfx_ctx* c, const hfx_scf_options& o, double occ_pair
             HIPCK(hfx_antisym(T2.p, n, T1.p, st));
             BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, nk, n, &one, T1.p, n, X.p, n,
                                  &zero, T2.p, n));
-            // push: slot for the new vector
             int slot;
-            if (m < dmax) {
-                slot = (head + m) % dmax;
-                ++m;
-            } else {   // drop the oldest
-                slot = head;
-                head = (head + 1) % dmax;
-                std::vector<double> nb((size_t)m * m);
-                for (int i = 1; i < m; ++i)
-                    for (int j = 1; j < m; ++j) nb[(i - 1) * m + (j - 1)] = B[i * m + j];
-                B.swap(nb);
-            }
+            diis_make_room(B, m, head, dmax, &slot);
             double* eslot = Eh.p + (size_t)slot * nk * nk;
             BLASCK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nk, nk, n, &one, X.p, n, T2.p,
                                  n, &zero, eslot, nk));
             HIPCK(hipMemcpy(Fh.p + (size_t)slot * nn, F.p, nn * 8, hipMemcpyDeviceToDevice));
-            B.resize((size_t)m * m, 0.0);
-            {   // rebuild B with the new last row/column
-                std::vector<double> nb((size_t)m * m, 0.0);
-                const int mo = (int)std::sqrt((double)B.size());
-                (void)mo;
-                for (int i = 0; i < m - 1; ++i)
-                    for (int j = 0; j < m - 1; ++j) nb[i * m + j] = B[i * (m) + j];
-                for (int i = 0; i < m; ++i) {
-                    const int si = (head + i) % dmax;
-                    int np2 = hfx_dot_partial(Eh.p + (size_t)si * nk * nk, eslot, (size_t)nk * nk, 0, part.p, st);
-                    HIPCK(hipMemcpy(parth.data(), part.p, np2 * 8, hipMemcpyDeviceToHost));
-                    const double v = host_sum(parth, np2);
-                    nb[i * m + (m - 1)] = v;
-                    nb[(m - 1) * m + i] = v;
-                }
-                B.swap(nb);
+            for (int i = 0; i < m; ++i) {   // the new last row and column of B
+                const int si = (head + i) % dmax;
+                int np2 = hfx_dot_partial(Eh.p + (size_t)si * nk * nk, eslot, (size_t)nk * nk, 0, part.p, st);
+                HIPCK(hipMemcpy(parth.data(), part.p, np2 * 8, hipMemcpyDeviceToHost));
+                const double v = host_sum(parth, np2);
+                B[i * m + (m - 1)] = v;
+                B[(m - 1) * m + i] = v;
             }
             // extrapolate with the newest m' <= m vectors; drop the oldest while ill-conditioned
             int use = m;
@@ -373,15 +376,21 @@ static hfx_status scf_core(hfx_ctx* c, const hfx_scf_options& o, double occ_pair
     return HFX_OK;
 }
 
-// SAD: block-diagonal superposition of per-element atomic densities.
+// SAD: block-diagonal superposition of per-element atomic densities, in the
+// ragged per-molecule layout (a single molecule: one nbf x nbf block).
 static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
-    const int n = c->nbf;
-    Dsad.assign((size_t)n * n, 0.0);
+    Dsad.assign(c->nelem, 0.0);
+    std::vector<std::vector<int>> atom_shells(c->natom);
+    for (int s = 0; s < c->nshell; ++s) atom_shells[c->shell_atom[s]].push_back(s);
+    std::vector<int> atom_mol(c->natom, 0);
+    for (int m = 0; m < c->nmol; ++m)
+        for (int a = 0; a < c->mol[m].natom; ++a) atom_mol[c->mol[m].aoff + a] = m;
     for (int a = 0; a < c->natom; ++a) {
         const int z = c->Z[a];
-        std::vector<int> sh;
-        for (int s = 0; s < c->nshell; ++s)
-            if (c->shell_atom[s] == a) sh.push_back(s);
+        const std::vector<int>& sh = atom_shells[a];
+        const MolInfo& M = c->mol[atom_mol[a]];
+        const int n = M.nbf;
+        double* Dm = Dsad.data() + M.moff;
         if (sh.empty()) continue;
         // key: element and the raw shells (l, exponents, coefficients)
         std::string key(reinterpret_cast<const char*>(&z), sizeof(int));
@@ -448,7 +457,7 @@ static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
         for (int s : sh) nloc += (c->shells[s].l + 1) * (c->shells[s].l + 2) / 2;
         if (nloc != na) return hfx_fail(c, HFX_ERR_INVALID_ARG, "SAD: atoms of one element must share a basis");
         for (int i = 0; i < na; ++i)
-            for (int j = 0; j < na; ++j) Dsad[(size_t)(o0 + i) * n + o0 + j] = Da[(size_t)i * na + j];
+            for (int j = 0; j < na; ++j) Dm[(size_t)(o0 + i) * n + o0 + j] = Da[(size_t)i * na + j];
     }
     return HFX_OK;
 }
@@ -526,4 +535,326 @@ extern "C" hfx_status hfx_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_re
     }
     if (eps_out) std::memcpy(eps_out, epsh.data(), epsh.size() * sizeof(double));
     return run.converged ? HFX_OK : hfx_fail(c, HFX_ERR_NOT_CONVERGED, "hfx_scf: not converged within max_iter");
+}
+
+// ---- batched SCF ------------------------------------------------------------------------
+// Every molecule of a batch iterates in lockstep: one batched Fock build for
+// all of them per iteration, then per molecule the energy, Pulay DIIS and
+// X^T F X (the steps of the single-molecule driver above), and one batched
+// eigensolve for all molecules: each X^T F X sits in the top-left corner of
+// an NP x NP slot padded with a large diagonal, so its eigenpairs come first
+// and the padding's (unit vectors) after them.
+namespace {
+
+constexpr double kPadDiag = 1.0e6;   // far above any orbital energy or overlap eigenvalue (hartree)
+
+struct MolScf {
+    int n = 0, nk = 0, nocc = 0;
+    long long moff = 0;
+    double enuc = 0.0;
+    DevBuf X, T1, T2, Dn, Fx, C, Fh, Eh;
+    std::vector<double> B;   // DIIS Gram matrix of the m stored vectors (oldest first)
+    int m = 0, head = 0;
+    double energy = 0.0, e_old = 0.0;
+    bool have_old = false, converged = false;
+    int iterations = 0, ndropped = 0;
+};
+
+double dev_sum(hfx_ctx* c, int np, DevBuf& part, std::vector<double>& parth, bool& ok) {
+    ok = hipMemcpy(parth.data(), part.p, np * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    (void)c;
+    return host_sum(parth, np);
+}
+
+}  // namespace
+
+extern "C" hfx_status hfx_batch_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_result* res, double* D_out) {
+    if (!c || !res) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_batch_scf: nothing loaded");
+    hfx_scf_options o;
+    if (opt) o = *opt; else hfx_default_scf_options(&o);
+    if (o.max_iter < 1 || o.diis_max < 0 || o.diis_max > 32 || !(o.e_tol > 0) || !(o.d_rms_tol > 0) ||
+        !(o.lindep > 0) || !(o.lindep < 1.0))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: invalid options");
+    if (o.guess == HFX_GUESS_LEARNED && !o.D0)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: the learned guess runs per molecule (hfx_scf)");
+    HIPCK(hipSetDevice(c->opt.device));
+    auto t0 = std::chrono::steady_clock::now();
+    const int nmol = c->nmol;
+    const size_t ne = c->nelem;
+    rocblas_handle h = c->blas;
+    hipStream_t st = 0;
+    BLASCK(rocblas_set_stream(h, st));
+    BLASCK(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+    const double one = 1.0, zero = 0.0;
+
+    // ---- guess ----
+    DevBuf D;
+    HIPCK(D.alloc(ne));
+    bool core = false;
+    int guess_used = o.guess;
+    if (o.D0) {
+        for (size_t i = 0; i < ne; ++i)
+            if (!std::isfinite(o.D0[i])) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: non-finite D0");
+        HIPCK(hipMemcpy(D.p, o.D0, ne * 8, hipMemcpyHostToDevice));
+        guess_used = -1;
+    } else if (o.guess == HFX_GUESS_CORE) {
+        core = true;
+    } else if (o.guess == HFX_GUESS_SAD) {
+        std::vector<double> Ds;
+        hfx_status s = sad_guess(c, Ds);
+        if (s != HFX_OK) return s;
+        HIPCK(hipMemcpy(D.p, Ds.data(), ne * 8, hipMemcpyHostToDevice));
+    } else {
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: unknown guess");
+    }
+
+    // ---- orthogonalisers from one batched eigensolve of the S blocks ----
+    const int NP = std::max(1, c->max_ld);
+    const size_t slot = (size_t)NP * NP;
+    DevBuf P, Wv, Ew;
+    HIPCK(P.alloc(slot * nmol));
+    HIPCK(Wv.alloc((size_t)NP * nmol));
+    HIPCK(Ew.alloc((size_t)NP * nmol));
+    rocblas_int* info = nullptr;
+    HIPCK(hipMalloc((void**)&info, nmol * sizeof(rocblas_int)));
+    struct InfoFree { rocblas_int* p; ~InfoFree() { if (p) (void)hipFree(p); } } info_free{info};
+    std::vector<rocblas_int> infoh(nmol);
+    auto batched_eig = [&]() -> hfx_status {
+        BLASCK(rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, NP, P.p, NP,
+                                                (rocblas_stride)slot, Wv.p, NP, Ew.p, NP, info, nmol));
+        HIPCK(hipMemcpy(infoh.data(), info, nmol * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+        return HFX_OK;
+    };
+    HIPCK(hfx_pad_blocks(c->d_S, c->d_moff, c->d_mdim, nmol, NP, kPadDiag, P.p, st));
+    hfx_status s = batched_eig();
+    if (s != HFX_OK) return s;
+    for (int m = 0; m < nmol; ++m)
+        if (infoh[m] != 0) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: overlap eigensolve failed");
+    std::vector<double> wh((size_t)NP * nmol);
+    HIPCK(hipMemcpy(wh.data(), Wv.p, wh.size() * 8, hipMemcpyDeviceToHost));
+    const int dmax = std::max(0, o.diis_max);
+    std::vector<std::unique_ptr<MolScf>> mols;
+    std::vector<int> kdim(nmol);
+    for (int m = 0; m < nmol; ++m) {
+        auto M = std::make_unique<MolScf>();
+        const MolInfo& I = c->mol[m];
+        M->n = I.nbf;
+        M->nocc = I.nocc;
+        M->moff = I.moff;
+        M->enuc = I.enuc;
+        const int n = M->n;
+        std::vector<int> keep;
+        for (int i = 0; i < n; ++i)
+            if (wh[(size_t)m * NP + i] >= o.lindep) keep.push_back(i);
+        M->nk = (int)keep.size();
+        M->ndropped = n - M->nk;
+        if (M->nk < std::max(1, M->nocc))
+            return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: overlap matrix too singular for the occupied space");
+        kdim[m] = M->nk;
+        const int nk = M->nk;
+        DevBuf U, Us;
+        HIPCK(U.alloc((size_t)n * n));
+        HIPCK(Us.alloc((size_t)n * nk));
+        HIPCK(hipMemcpy2D(U.p, (size_t)n * 8, P.p + (size_t)m * slot, (size_t)NP * 8, (size_t)n * 8, n,
+                          hipMemcpyDeviceToDevice));
+        int* dk = nullptr;
+        HIPCK(hipMalloc((void**)&dk, nk * sizeof(int)));
+        HIPCK(hipMemcpy(dk, keep.data(), nk * sizeof(int), hipMemcpyHostToDevice));
+        hipError_t e = hfx_scale_cols(U.p, Wv.p + (size_t)m * NP, dk, n, nk, Us.p, st);
+        (void)hipFree(dk);
+        HIPCK(e);
+        HIPCK(M->X.alloc((size_t)n * nk));
+        if (nk == n) {
+            BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, Us.p, n, U.p, n,
+                                 &zero, M->X.p, n));
+        } else {
+            HIPCK(hipMemcpy(M->X.p, Us.p, (size_t)n * nk * 8, hipMemcpyDeviceToDevice));
+        }
+        const size_t nn = (size_t)n * n;
+        HIPCK(M->T1.alloc(nn));
+        HIPCK(M->T2.alloc(nn));
+        HIPCK(M->Dn.alloc(nn));
+        HIPCK(M->Fx.alloc(nn));
+        HIPCK(M->C.alloc((size_t)n * std::max(1, M->nocc)));
+        HIPCK(M->Fh.alloc(nn * std::max(1, dmax)));
+        HIPCK(M->Eh.alloc((size_t)nk * nk * std::max(1, dmax)));
+        mols.push_back(std::move(M));
+    }
+    int* dkdim = nullptr;
+    HIPCK(hipMalloc((void**)&dkdim, nmol * sizeof(int)));
+    struct IntFree { int* p; ~IntFree() { if (p) (void)hipFree(p); } } kdim_free{dkdim};
+    HIPCK(hipMemcpy(dkdim, kdim.data(), nmol * sizeof(int), hipMemcpyHostToDevice));
+    HIPCK(hfx_pad_blocks(c->d_S, c->d_moff, c->d_mdim, nmol, NP, kPadDiag, P.p, st));   // finite start in every slot
+
+    DevBuf F, part;
+    HIPCK(F.alloc(ne));
+    HIPCK(part.alloc(4096));
+    std::vector<double> parth(4096);
+    bool ok = true;
+
+    // X^T M X into molecule m's slot
+    auto project = [&](MolScf& M, const double* Mat, int m) -> hfx_status {
+        BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M.n, M.nk, M.n, &one, Mat, M.n, M.X.p,
+                             M.n, &zero, M.T1.p, M.n));
+        BLASCK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, M.nk, M.nk, M.n, &one, M.X.p, M.n,
+                             M.T1.p, M.n, &zero, P.p + (size_t)m * slot, NP));
+        return HFX_OK;
+    };
+    // aufbau density of molecule m from its solved slot, into Dn
+    auto density = [&](MolScf& M, int m) -> hfx_status {
+        if (infoh[m] != 0) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: eigensolver did not converge");
+        BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, M.n, M.nocc, M.nk, &one, M.X.p, M.n,
+                             P.p + (size_t)m * slot, NP, &zero, M.C.p, M.n));
+        BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M.n, M.n, M.nocc, &one, M.C.p,
+                             M.n, M.C.p, M.n, &zero, M.Dn.p, M.n));
+        return HFX_OK;
+    };
+    if (core) {
+        for (int m = 0; m < nmol; ++m) {
+            s = project(*mols[m], c->d_H + mols[m]->moff, m);
+            if (s != HFX_OK) return s;
+        }
+        HIPCK(hfx_pad_rest(dkdim, nmol, NP, kPadDiag, P.p, st));
+        s = batched_eig();
+        if (s != HFX_OK) return s;
+        for (int m = 0; m < nmol; ++m) {
+            MolScf& M = *mols[m];
+            s = density(M, m);
+            if (s != HFX_OK) return s;
+            HIPCK(hipMemcpy(D.p + M.moff, M.Dn.p, (size_t)M.n * M.n * 8, hipMemcpyDeviceToDevice));
+        }
+    }
+
+    double t_fock = 0.0;
+    int nconv = 0;
+    for (int it = 1; it <= o.max_iter && nconv < nmol; ++it) {
+        auto tf = std::chrono::steady_clock::now();
+        s = hfx_build_internal(c, D.p, 2.0, 1.0, c->d_H, F.p, st, nullptr, 0, 1);
+        if (s != HFX_OK) return s;
+        HIPCK(hipStreamSynchronize(st));
+        t_fock += std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
+        for (int m = 0; m < nmol; ++m) {
+            MolScf& M = *mols[m];
+            if (M.converged) continue;
+            const int n = M.n, nk = M.nk;
+            const size_t nn = (size_t)n * n;
+            const double* Dm = D.p + M.moff;
+            const double* Fm = F.p + M.moff;
+            const double* Sm = c->d_S + M.moff;
+            int np = hfx_energy_partial(Dm, c->d_H + M.moff, Fm, nn, part.p, st);
+            const double Ek = dev_sum(c, np, part, parth, ok) + M.enuc;
+            if (!ok) return hfx_fail(c, HFX_ERR_DEVICE, "hfx_batch_scf: copy failed");
+            if (!std::isfinite(Ek)) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: non-finite energy");
+            M.energy = Ek;
+            M.iterations = it;
+            const double* Fuse = Fm;
+            if (dmax > 0) {   // Pulay DIIS on X^T (F D S - S D F) X, as in the single-molecule driver
+                BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, Fm, n, Dm, n,
+                                     &zero, M.T1.p, n));
+                BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, M.T1.p, n, Sm, n,
+                                     &zero, M.T2.p, n));
+                HIPCK(hfx_antisym(M.T2.p, n, M.T1.p, st));
+                BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, nk, n, &one, M.T1.p, n,
+                                     M.X.p, n, &zero, M.T2.p, n));
+                int sl;
+                diis_make_room(M.B, M.m, M.head, dmax, &sl);
+                double* eslot = M.Eh.p + (size_t)sl * nk * nk;
+                BLASCK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nk, nk, n, &one, M.X.p, n,
+                                     M.T2.p, n, &zero, eslot, nk));
+                HIPCK(hipMemcpy(M.Fh.p + (size_t)sl * nn, Fm, nn * 8, hipMemcpyDeviceToDevice));
+                for (int i = 0; i < M.m; ++i) {   // the new last row and column of B
+                    const int si = (M.head + i) % dmax;
+                    int np2 = hfx_dot_partial(M.Eh.p + (size_t)si * nk * nk, eslot, (size_t)nk * nk, 0, part.p, st);
+                    const double v = dev_sum(c, np2, part, parth, ok);
+                    if (!ok) return hfx_fail(c, HFX_ERR_DEVICE, "hfx_batch_scf: copy failed");
+                    M.B[i * M.m + (M.m - 1)] = v;
+                    M.B[(M.m - 1) * M.m + i] = v;
+                }
+                int use = M.m;
+                std::vector<double> coef;
+                while (use >= 2) {
+                    const int q = use + 1;
+                    std::vector<double> A((size_t)q * q, 0.0);
+                    for (int i = 0; i < use; ++i)
+                        for (int j = 0; j < use; ++j) A[i * q + j] = M.B[i * M.m + j];
+                    for (int i = 0; i < use; ++i) A[i * q + use] = A[use * q + i] = -1.0;
+                    std::vector<double> ev = small_sym_eigs(A, q);
+                    double amax = 0.0, amin = 1e300;
+                    for (double e : ev) {
+                        amax = std::max(amax, std::fabs(e));
+                        amin = std::min(amin, std::fabs(e));
+                    }
+                    std::vector<double> rhs(q, 0.0);
+                    rhs[use] = -1.0;
+                    if (amin > 0.0 && amax / amin <= 1e14 && small_solve(A, rhs, q)) {
+                        coef.assign(rhs.begin(), rhs.begin() + use);
+                        break;
+                    }
+                    M.head = (M.head + 1) % dmax;   // drop the oldest vector
+                    std::vector<double> nb((size_t)(M.m - 1) * (M.m - 1));
+                    for (int i = 1; i < M.m; ++i)
+                        for (int j = 1; j < M.m; ++j) nb[(i - 1) * (M.m - 1) + (j - 1)] = M.B[i * M.m + j];
+                    M.B.swap(nb);
+                    --M.m;
+                    use = M.m;
+                }
+                if (!coef.empty()) {
+                    std::vector<const double*> ptrs(M.m);
+                    for (int i = 0; i < M.m; ++i) ptrs[i] = M.Fh.p + (size_t)((M.head + i) % dmax) * nn;
+                    const double** dptrs = nullptr;
+                    double* dcoef = nullptr;
+                    HIPCK(hipMalloc((void**)&dptrs, M.m * sizeof(double*)));
+                    HIPCK(hipMalloc((void**)&dcoef, M.m * sizeof(double)));
+                    HIPCK(hipMemcpy(dptrs, ptrs.data(), M.m * sizeof(double*), hipMemcpyHostToDevice));
+                    HIPCK(hipMemcpy(dcoef, coef.data(), M.m * sizeof(double), hipMemcpyHostToDevice));
+                    hipError_t e = hfx_lincomb(dptrs, dcoef, M.m, nn, M.Fx.p, st);
+                    if (e == hipSuccess) e = hipStreamSynchronize(st);
+                    (void)hipFree(dptrs);
+                    (void)hipFree(dcoef);
+                    HIPCK(e);
+                    Fuse = M.Fx.p;
+                }
+            }
+            s = project(M, Fuse, m);
+            if (s != HFX_OK) return s;
+        }
+        HIPCK(hfx_pad_rest(dkdim, nmol, NP, kPadDiag, P.p, st));
+        s = batched_eig();
+        if (s != HFX_OK) return s;
+        for (int m = 0; m < nmol; ++m) {
+            MolScf& M = *mols[m];
+            if (M.converged) continue;
+            s = density(M, m);
+            if (s != HFX_OK) return s;
+            const size_t nn = (size_t)M.n * M.n;
+            double* Dm = D.p + M.moff;
+            int np = hfx_dot_partial(M.Dn.p, Dm, nn, 1, part.p, st);
+            const double drms = std::sqrt(dev_sum(c, np, part, parth, ok) / (double)nn);
+            if (!ok) return hfx_fail(c, HFX_ERR_DEVICE, "hfx_batch_scf: copy failed");
+            HIPCK(hipMemcpy(Dm, M.Dn.p, nn * 8, hipMemcpyDeviceToDevice));
+            if (M.have_old && std::fabs(M.energy - M.e_old) < o.e_tol && drms < o.d_rms_tol) {
+                M.converged = true;
+                ++nconv;
+            }
+            M.e_old = M.energy;
+            M.have_old = true;
+        }
+        if (c->opt.log_level > 0)
+            std::fprintf(stderr, "[hfx batch scf] it %3d  converged %d / %d\n", it, nconv, nmol);
+    }
+    const double t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int m = 0; m < nmol; ++m) {
+        const MolScf& M = *mols[m];
+        res[m].energy = M.energy;
+        res[m].e_nuc = M.enuc;
+        res[m].iterations = M.iterations;
+        res[m].converged = M.converged ? 1 : 0;
+        res[m].guess_used = guess_used;
+        res[m].ndropped = M.ndropped;
+        res[m].t_fock_s = t_fock;
+        res[m].t_total_s = t_total;
+    }
+    if (D_out) HIPCK(hipMemcpy(D_out, D.p, ne * 8, hipMemcpyDeviceToHost));
+    return nconv == nmol ? HFX_OK : hfx_fail(c, HFX_ERR_NOT_CONVERGED, "hfx_batch_scf: not converged within max_iter");
 }

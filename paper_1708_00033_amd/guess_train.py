@@ -78,7 +78,15 @@ def evaluate(net, mols, hfx, tag):
         ctx.load(m)
         r0 = ctx.scf()
         r1 = ctx.scf(model=net)
+        import torch
+        Dsad = ctx.sad_density()
+        dD = torch.tensor(Dsad, device="cuda")
+        ctx.guess_apply(net, dD.data_ptr(), 0)
+        torch.cuda.synchronize()
+        err_sad = float(np.linalg.norm(Dsad - r0["D"]))
+        err_nn = float(np.linalg.norm(dD.cpu().numpy() - r0["D"]))
         row = dict(waters=m.natom // 3, nbf=ctx.nbf, sad_iterations=r0["iterations"],
+                   start_density_error_sad=err_sad, start_density_error_learned=err_nn,
                    learned_iterations=r1["iterations"], sad_time_s=r0["t_total_s"], learned_time_s=r1["t_total_s"],
                    energy_sad=r0["energy"], energy_learned=r1["energy"],
                    dE=r1["energy"] - r0["energy"], guess_used=r1["guess_used"],
@@ -86,13 +94,15 @@ def evaluate(net, mols, hfx, tag):
         out.append(row)
         log(f"{tag} {j}: {row['waters']} waters, SAD {row['sad_iterations']} it {row['sad_time_s']:.2f} s, "
             f"learned {row['learned_iterations']} it {row['learned_time_s']:.2f} s, dE {row['dE']:.2e}, "
-            f"guess_used {row['guess_used']}")
+            f"guess_used {row['guess_used']}, |D0 - D| SAD {err_sad:.3f} learned {err_nn:.3f}")
     ctx.close()
     return out
 
 
 def _means(ev):
-    return dict(sad_iterations=float(np.mean([r["sad_iterations"] for r in ev])),
+    return dict(start_density_error_sad=float(np.mean([r["start_density_error_sad"] for r in ev])),
+                start_density_error_learned=float(np.mean([r["start_density_error_learned"] for r in ev])),
+                sad_iterations=float(np.mean([r["sad_iterations"] for r in ev])),
                 learned_iterations=float(np.mean([r["learned_iterations"] for r in ev])),
                 sad_time_s=float(np.mean([r["sad_time_s"] for r in ev])),
                 learned_time_s=float(np.mean([r["learned_time_s"] for r in ev])),

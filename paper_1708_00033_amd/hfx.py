@@ -100,6 +100,7 @@ _sigs = {
     "hfx_build_2e_shard_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p,
                                 C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
+    "hfx_batch_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
     "hfx_class_counts": ([_ctx_p, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_set_class_tuning": ([_ctx_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
@@ -370,6 +371,29 @@ class Context:
         used = C.c_int()
         self._check(hfx_guess_apply(self.ptr, model.ptr, C.c_void_p(dD_ptr), C.c_void_p(stream), C.byref(used)))
         return bool(used.value)
+
+    def batch_scf(self, D0: Optional[np.ndarray] = None, **kw):
+        """Lockstep SCF of a loaded batch: list of per-molecule dicts and the
+        ragged converged densities."""
+        o = default_scf_options(**kw)
+        keep = None
+        if D0 is not None:
+            keep = np.ascontiguousarray(D0, dtype=np.float64)
+            o.D0 = _d(keep)
+        if self.layout is None:     # a single molecule is a batch of one
+            nbf, off, tot = [self.nbf], [0], self.nbf * self.nbf
+        else:
+            nbf, _, off, tot = self.layout
+        nmol = len(nbf)
+        res = (hfx_scf_result * nmol)()
+        D = np.zeros(int(tot))
+        st = hfx_batch_scf(self.ptr, C.byref(o), res, _d(D))
+        if st not in (HFX_OK, HFX_ERR_NOT_CONVERGED):
+            self._check(st)
+        out = [dict(energy=r.energy, e_nuc=r.e_nuc, iterations=r.iterations, converged=bool(r.converged),
+                    guess_used=r.guess_used, ndropped=r.ndropped, t_total_s=r.t_total_s, t_fock_s=r.t_fock_s)
+               for r in res]
+        return out, D
 
     def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1, persistent: int = 0,
                          digest: int = -1):

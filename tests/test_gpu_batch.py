@@ -96,3 +96,23 @@ def test_graph_replay_matches_eager(persistent):
                 # eager work and a host sync between replays
                 ctx.build_fock_dev(D.data_ptr(), Fe.data_ptr(), stream.cuda_stream)
                 stream.synchronize()
+
+
+@pytest.mark.parametrize("guess", ["sad", "core"])
+def test_batch_scf_matches_single_scf(guess):
+    """Lockstep batched SCF (one batched build and one batched eigensolve per
+    iteration) reaches each molecule's own SCF solution."""
+    hfx = _hfx()
+    mols = [W.water_cluster(n, 950 + i) for i, n in enumerate([1, 3, 2, 5])] + [W.dimer_config()]
+    g = hfx.HFX_GUESS_SAD if guess == "sad" else hfx.HFX_GUESS_CORE
+    ctx = hfx.Context().load_batch(mols)
+    res, D = ctx.batch_scf(guess=g, e_tol=1e-10, d_rms_tol=1e-8)
+    nbf, nocc, off, _ = ctx.layout
+    for i, m in enumerate(mols):
+        r = hfx.Context().load(m).scf(guess=g, e_tol=1e-10, d_rms_tol=1e-8)
+        assert res[i]["converged"] and r["converged"], i
+        assert abs(res[i]["energy"] - r["energy"]) < 1e-8, (i, res[i]["energy"], r["energy"])
+        blk = D[off[i]:off[i] + nbf[i] ** 2].reshape(nbf[i], nbf[i])
+        assert np.abs(blk - r["D"]).max() < 1e-5, i
+        if guess == "sad":
+            assert abs(res[i]["iterations"] - r["iterations"]) <= 1, (i, res[i]["iterations"], r["iterations"])
