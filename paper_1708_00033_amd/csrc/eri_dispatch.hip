@@ -16,26 +16,29 @@ static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPT
 
 // nblocks workgroups: the task count (static launch) or the resident grid
 // (persistent launch, args->work set).
-extern "C" hipError_t hfx_launch_class(int cid, int mode, int mixed, int nblocks, size_t lds_bytes,
+extern "C" int hfx_class_wgs(int cid, int alt) { return alt ? kEriClassInfo[cid].wgs_alt : kEriClassInfo[cid].wgs; }
+
+// alt: the class's alternative workgroup size (kEriClassInfo.wgs_alt).
+extern "C" hipError_t hfx_launch_class(int cid, int alt, int mode, int mixed, int nblocks, size_t lds_bytes,
                                        hipStream_t stream, const ClassArgs* args) {
     if (nblocks <= 0) return hipSuccess;
-    const void* fn = kClassLookup[cid]((args->work ? 4 : 0) + mode * 2 + mixed);
+    const void* fn = kClassLookup[cid]((alt ? 8 : 0) + (args->work ? 4 : 0) + mode * 2 + mixed);
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
     void* kargs[] = {(void*)args};
-    return hipLaunchKernel(fn, dim3(nblocks), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+    return hipLaunchKernel(fn, dim3(nblocks), dim3(hfx_class_wgs(cid, alt)), kargs, lds_bytes, stream);
 }
 
 // Workgroups of one class kernel that fit on the device at once.
-extern "C" int hfx_class_resident_blocks(int cid, int mode, int mixed, size_t lds_bytes) {
-    const void* fn = kClassLookup[cid](4 + mode * 2 + mixed);
+extern "C" int hfx_class_resident_blocks(int cid, int alt, int mode, int mixed, size_t lds_bytes) {
+    const void* fn = kClassLookup[cid]((alt ? 8 : 0) + 4 + mode * 2 + mixed);
     if (lds_bytes > 64 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
         return 0;
     int per_cu = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEriClassInfo[cid].wgs, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hfx_class_wgs(cid, alt), lds_bytes) != hipSuccess)
         return 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -43,7 +46,6 @@ extern "C" int hfx_class_resident_blocks(int cid, int mode, int mixed, size_t ld
     return per_cu * ncu;
 }
 
-extern "C" int hfx_class_wgs(int cid) { return kEriClassInfo[cid].wgs; }
 
 extern "C" hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim,
                                          const double* boys, double* Q, hipStream_t stream) {

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
 // build-time bottleneck and they carry a negligible share of the quartets,
 // so mixed builds evaluate them in FP64 (the more accurate choice).
 template <class E>
-struct ClassKernels {
+struct ClassKernelsOne {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
     // variant = 4 persistent + 2 mode + fp32
@@ -529,9 +529,21 @@ struct ClassKernels {
     }
 };
 
+// variant bit 3: the class's alternative workgroup size (EA; the same kernels
+// when EA has E's size).
+template <class E, class EA>
+struct ClassKernels {
+    static const void* get(int variant) {
+        if constexpr (EA::WGS != E::WGS) {
+            if (variant & 8) return ClassKernelsOne<EA>::get(variant & 7);
+        }
+        return ClassKernelsOne<E>::get(variant & 7);
+    }
+};
+
 // Per-class translation unit: evaluator wrapper, the kernel variants, the
 // Schwarz kernel and C lookups.
-#define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_)                                               \
+#define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_, wgs_alt_)                                               \
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = false;                                                          \
@@ -543,12 +555,17 @@ struct ClassKernels {
                      R(cd[2]), tab, out);                                                              \
         }                                                                                              \
     };                                                                                                 \
-    extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \
+    struct Eval##cid##A : Eval##cid {                                                                   \
+        static constexpr int WGS = wgs_alt_;                                                           \
+    };                                                                                                 \
+    extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
+        return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
+    }                                                                                                  \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }
 
 // Per-class translation unit of a large class: the full evaluator (Schwarz
 // bounds) plus the per-component passes used by the class kernels.
-#define HFX_CLASS_TU_PASSES(cid, fname, la_, lb_, lc_, ld_, wgs_)                                        \
+#define HFX_CLASS_TU_PASSES(cid, fname, la_, lb_, lc_, ld_, wgs_, wgs_alt_)                                        \
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = true;                                                           \
@@ -568,5 +585,10 @@ struct ClassKernels {
                             R(cd[1]), R(cd[2]), tab, out);                                             \
         }                                                                                              \
     };                                                                                                 \
-    extern "C" const void* hfx_class_kernel_##cid(int variant) { return ClassKernels<Eval##cid>::get(variant); } \
+    struct Eval##cid##A : Eval##cid {                                                                   \
+        static constexpr int WGS = wgs_alt_;                                                           \
+    };                                                                                                 \
+    extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
+        return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
+    }                                                                                                  \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }

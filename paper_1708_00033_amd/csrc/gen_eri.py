@@ -38,10 +38,23 @@ import sys
 PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 PAIR_NAMES = ["ss", "ps", "pp", "ds", "dp", "dd"]
 CLASSES = [(B, K) for B in range(6) for K in range(B + 1)]
-# Workgroup size per class: 512 lanes where the kernel needs <= 256 VGPRs, so
-# that classes whose LDS rows limit the workgroups per CU still reach 32
-# waves per CU; 256 for the register-heavy classes.
-WG512 = {0, 1, 2, 3, 4, 6, 7, 9, 10}
+# Workgroup size per class.  LDS (the class's Boys rows plus the bra rows of
+# the task) allows one workgroup per CU for most classes at ~1,200 basis
+# functions, so the workgroup size sets the waves per CU: 1024 lanes where the
+# kernel fits in 128 VGPRs without spilling ((ps|ss), (ds|ss): 4 waves per
+# SIMD), 512 where it fits in 256, 256 for the register-heavy classes.
+WG1024 = {1, 6}
+WG512 = {0, 2, 3, 4, 7, 9, 10}
+
+
+def wg_size(cid):
+    return 1024 if cid in WG1024 else (512 if cid in WG512 else 256)
+
+
+def wg_alt(cid):
+    """Second workgroup size, used when two workgroups of it fit in LDS
+    (small molecules: short ket ranges leave 1024-lane groups idle)."""
+    return 512 if cid in WG1024 else wg_size(cid)
 
 
 def cart(l):
@@ -203,9 +216,9 @@ class ClassGen:
         lines.append("    const R Q0 = R(kq[2 * kfs]), Q1 = R(kq[3 * kfs]), Q2 = R(kq[4 * kfs]);")
         lines.append("    const R QC0 = R(kq[5 * kfs]), QC1 = R(kq[6 * kfs]), QC2 = R(kq[7 * kfs]);")
         lines.append("    // bra primitives (uniform across the workgroup)")
-        # unrolling the bra loop gives independent Boys/recurrence chains to
-        # interleave; only worth its code size (and compile time) for low L
-        lines.append("#pragma unroll 3" if L <= 2 else "#pragma unroll 1")
+        # a rolled bra loop measured as fast as an unrolled one for low L (the
+        # waves per SIMD hide the recurrence latency) and compiles faster
+        lines.append("#pragma unroll 1")
         lines.append("    for (int ib = 0; ib < nbp; ++ib) {")
         lines.append("      // uniform address in the constant address space: scalar loads")
         lines.append("      const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + ib);")
@@ -281,15 +294,15 @@ def main(out_dir):
         macro = "HFX_CLASS_TU_PASSES" if cid in PASS_CLASSES else "HFX_CLASS_TU"
         tu = [f"// Generated by gen_eri.py: kernels of class {cid} ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}).",
               f'#include "eri_class_{cid:02d}.h"', '#include "../eri_impl.h"', "",
-              f"{macro}({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {512 if cid in WG512 else 256})", ""]
+              f"{macro}({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {wg_size(cid)}, {wg_alt(cid)})", ""]
         with open(os.path.join(out_dir, f"eri_class_{cid:02d}.hip"), "w") as fh:
             fh.write("\n".join(tu))
         table.append((cid, B, K, la, lb, lc, ld, g.flops, g.hrr_flops, fname))
     parts = ["// Generated by gen_eri.py: class table.", "#pragma once", "",
-             "struct EriClassInfo { int B, K, la, lb, lc, ld, vrr_flops_per_prim, hrr_flops, wgs; };",
+             "struct EriClassInfo { int B, K, la, lb, lc, ld, vrr_flops_per_prim, hrr_flops, wgs, wgs_alt; };",
              "static const EriClassInfo kEriClassInfo[21] = {"]
     for (cid, B, K, la, lb, lc, ld, fl, hfl, fname) in table:
-        parts.append(f"  {{{B}, {K}, {la}, {lb}, {lc}, {ld}, {fl}, {hfl}, {512 if cid in WG512 else 256}}},  // {fname}")
+        parts.append(f"  {{{B}, {K}, {la}, {lb}, {lc}, {ld}, {fl}, {hfl}, {wg_size(cid)}, {wg_alt(cid)}}},  // {fname}")
     parts.append("};")
     parts.append("")
     parts.append("#define HFX_FOR_EACH_CID(X) " + " ".join(f"X({cid})" for cid in range(21)))

@@ -269,7 +269,19 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     // share of each ket list; short prefixes fill the least loaded queue.
     // Queues are interleaved (task 8k + j = queue j's k-th entry) and padded
     // with empty tasks (r = -1).
-    const int NX = 8, WGS = hfx_class_wgs(class_id(B, K));
+    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
+    P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
+    const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
+    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);   // FP64 kernel
+    P.lds_tab[1] = (size_t)boys_entries(Ltot) * sizeof(float);    // FP32 kernel of a mixed build
+    const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
+    // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
+    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;
+    // workgroup size: the class's alternative (smaller) size when two such
+    // workgroups fit in LDS, else its default (a large group keeps the waves
+    // per CU up when LDS admits one workgroup per CU)
+    P.alt = hfx_class_wgs(P.cid, 1) != hfx_class_wgs(P.cid, 0) && 2 * P.lds(false) <= 160 * 1024 - 512;
+    const int NX = 8, WGS = hfx_class_wgs(P.cid, P.alt);
     std::vector<std::vector<int4>> queue(NX);
     std::vector<long long> load(NX, 0);
     for (int r = 0; r < nbra; ++r) {
@@ -300,19 +312,11 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     if (tasks.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many tasks for one launch");
     P.nbra = nbra;
     P.ntask = (int)tasks.size();
-    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
-    P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
-    const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
-    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);   // FP64 kernel
-    P.lds_tab[1] = (size_t)boys_entries(Ltot) * sizeof(float);    // FP32 kernel of a mixed build
-    const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
-    // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
-    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;
     if (P.ntask == 0) return HFX_OK;
     P.persist = c->tune_persist[P.cid] > 0;
     for (int mx = 0; mx < (P.fp64_only ? 1 : 2); ++mx) {
         const size_t lds = P.lds(mx != 0);
-        int nb = hfx_class_resident_blocks(P.cid, P.mode, mx, lds);
+        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.mode, mx, lds);
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
@@ -886,7 +890,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[5] = p.integrals;
     info[6] = p.launches;
     info[7] = p.mode;
-    info[8] = hfx_class_wgs(p.cid);
+    info[8] = hfx_class_wgs(p.cid, p.alt);
     info[9] = p.persist ? 1 : 0;
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
     if (ms) *ms = p.ms;
@@ -943,12 +947,12 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.qlen = P.ntask / 8;
         a.part = mx ? 1 : 0;
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        HIPCK(hfx_launch_class(cid, P.mode, 0, P.persist ? P.nblocks[0] : P.ntask, P.lds(false), st, &a));
+        HIPCK(hfx_launch_class(cid, P.alt, P.mode, 0, P.persist ? P.nblocks[0] : P.ntask, P.lds(false), st, &a));
         if (mx) {   // the same tasks' kets from split[r] on, in FP32
             ClassArgs b = a;
             b.part = 2;
             b.work = P.persist ? c->d_work + 16 * pi + 8 : nullptr;
-            HIPCK(hfx_launch_class(cid, P.mode, 1, P.persist ? P.nblocks[1] : P.ntask, P.lds(true), st, &b));
+            HIPCK(hfx_launch_class(cid, P.alt, P.mode, 1, P.persist ? P.nblocks[1] : P.ntask, P.lds(true), st, &b));
         }
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));

@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhfx.so")
+# HFX_LIB: another build of the same library (e.g. a tuning experiment)
+LIB_PATH = os.environ.get("HFX_LIB") or os.path.join(_HERE, "libhfx.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1708_00033_amd.build` "
