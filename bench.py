@@ -223,6 +223,8 @@ def large_bench(args, log):
         ms, n = ctx.kernel_times()
         ctx.kernel_timing(False)
         q = int(st.quartets_fp64 + st.quartets_fp32)
+        if G == 1 and q != quartets:
+            raise RuntimeError(f"evaluated {q} quartets, planned {quartets}")
         out[tag] = {"share_build_s": dt, "share_quartets": q, "quartets_per_s": q / dt,
                     "quartets_fp32": int(st.quartets_fp32),
                     "class_ms": {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}}

@@ -29,19 +29,22 @@
 
 
 
+// K update of W[grow][gcol]: MODE 0 into the task's LDS bra row at column
+// lcol (gcol less the column base of its window), MODE 1 straight into W.
 template <int MODE>
-__device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, int col, int N, double v) {
+__device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, int gcol, int N, int lcol, double v) {
     if constexpr (MODE == 0) {
-        atomicAdd(lds_row + col, v);
+        atomicAdd(lds_row + lcol, v);
     } else {
-        atomicAdd(W + (size_t)grow * N + col, v);
+        atomicAdd(W + (size_t)grow * N + gcol, v);
     }
 }
 
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                        const PairInfo& ket, int spos, const double* dab, double* jab, double* FI,
-                                       double* FJ, const double* __restrict__ D, double* __restrict__ W, int N) {
+                                       double* FJ, const double* __restrict__ D, double* __restrict__ W, int N,
+                                       int RS, int cb, int db) {
     const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
@@ -90,7 +93,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int n = 0; n < NB; ++n)
 #pragma unroll
                     for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dbd[n * ND + s];
-                row_add<MODE>(FI + m * N, W, fa + m, fc + l, N, ckg * v);
+                row_add<MODE>(FI + m * RS, W, fa + m, fc + l, N, fc + l - cb, ckg * v);
             }
     }
     // K: W_bd -= ck g sum_{mu lambda} I D_ac
@@ -109,7 +112,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int m = 0; m < NA; ++m)
 #pragma unroll
                     for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dac[m * NC + l];
-                row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v);
+                row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v);
             }
     }
     // K: W_ad -= ck g sum_{nu lambda} I D_bc
@@ -128,7 +131,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int n = 0; n < NB; ++n)
 #pragma unroll
                     for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dbc[n * NC + l];
-                row_add<MODE>(FI + m * N, W, fa + m, fd + s, N, ckg * v);
+                row_add<MODE>(FI + m * RS, W, fa + m, fd + s, N, fd + s - db, ckg * v);
             }
     }
     // K: W_bc -= ck g sum_{mu sigma} I D_ad
@@ -147,7 +150,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int m = 0; m < NA; ++m)
 #pragma unroll
                     for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dad[m * ND + s];
-                row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v);
+                row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v);
             }
     }
 }
@@ -158,7 +161,7 @@ template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_rolled(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                               const PairInfo& ket, const double* dab, double* jab, double* FI,
                                               double* FJ, const double* __restrict__ D, double* __restrict__ W,
-                                              int N) {
+                                              int N, int RS, int cb, int db) {
     const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
 #pragma unroll 1
@@ -186,7 +189,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int s = 0; s < ND; ++s)
                     v1 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
-            row_add<MODE>(FI + m * N, W, fa + m, fc + l, N, ckg * v1);
+            row_add<MODE>(FI + m * RS, W, fa + m, fc + l, N, fc + l - cb, ckg * v1);
         }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n)
@@ -198,7 +201,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int l = 0; l < NC; ++l)
                     v2 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fc + l];
-            row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v2);
+            row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v2);
         }
 #pragma unroll 1
     for (int m = 0; m < NA; ++m)
@@ -210,7 +213,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int l = 0; l < NC; ++l)
                     v3 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
-            row_add<MODE>(FI + m * N, W, fa + m, fd + s, N, ckg * v3);
+            row_add<MODE>(FI + m * RS, W, fa + m, fd + s, N, fd + s - db, ckg * v3);
         }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n)
@@ -222,7 +225,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int s = 0; s < ND; ++s)
                     v4 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fd + s];
-            row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v4);
+            row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v4);
         }
 }
 
@@ -234,7 +237,7 @@ template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_pass(int k, const double* I, double g, const ClassArgs& a,
                                             const PairInfo& bra, const PairInfo& ket, int spos, const double* dab,
                                             double* jab, double* FI, double* FJ, const double* __restrict__ D,
-                                            double* __restrict__ W, int N) {
+                                            double* __restrict__ W, int N, int RS, int cb, int db) {
     const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     constexpr int NCD = NC * ND;
@@ -262,7 +265,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
         for (int n = 0; n < NB; ++n)
 #pragma unroll 1
             for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
-        row_add<MODE>(FI + k * N, W, fa + k, fc + l, N, ckg * v);
+        row_add<MODE>(FI + k * RS, W, fa + k, fc + l, N, fc + l - cb, ckg * v);
     }
 #pragma unroll 1
     for (int s = 0; s < ND; ++s) {   // K: (k, d_s) -= sum_{n l} I D_bc
@@ -271,7 +274,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
         for (int n = 0; n < NB; ++n)
 #pragma unroll 1
             for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
-        row_add<MODE>(FI + k * N, W, fa + k, fd + s, N, ckg * v);
+        row_add<MODE>(FI + k * RS, W, fa + k, fd + s, N, fd + s - db, ckg * v);
     }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n) {
@@ -280,14 +283,14 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
             double v = 0.0;
 #pragma unroll 1
             for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fc + l];
-            row_add<MODE>(FJ + n * N, W, fb + n, fd + s, N, ckg * v);
+            row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v);
         }
 #pragma unroll 1
         for (int l = 0; l < NC; ++l) {   // K: (b_n, c_l) -= sum_s I D_ad
             double v = 0.0;
 #pragma unroll 1
             for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fd + s];
-            row_add<MODE>(FJ + n * N, W, fb + n, fc + l, N, ckg * v);
+            row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v);
         }
     }
 }
@@ -332,27 +335,38 @@ __device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, f
 }
 
 template <class E, int MODE, int FP32>
-__device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, const double* t64,
-                                           const float* t32) {
+__device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, const double* t64, const float* t32) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     extern __shared__ __align__(16) double lds[];
+    const int4 task = a.tasks[ti];
     const int r = task.x;
     if (!task_active(a, task)) return;
-    // kets [s0, send) of the list; a mixed build's part keeps one side of split[r]
+    // kets [s0, send) of the list; a mixed build's part keeps one side of the task's split
     int s0 = task.y, send = task.z;
-    if (a.part == 1) send = min(send, a.split[r]);
-    else if (a.part == 2) s0 = max(s0, a.split[r]);
+    if (a.part == 1) send = min(send, a.split[ti]);
+    else if (a.part == 2) s0 = max(s0, a.split[ti]);
     if (s0 >= send) return;                                   // uniform: nothing of this part here
     const PairInfo bra = a.bra[r];
     // the bra's molecule: its blocks of D' and W, leading dimension ld
     const int N = bra.ld;
     const double* __restrict__ Dm = a.D + a.moff[bra.mol];
     double* __restrict__ Wm = a.W + a.moff[bra.mol];
+    // LDS bra rows of length RS: whole rows, or (column windows) the task's
+    // window of shell c at [0, RS/2) and of shell d at [RS/2, RS) (one region
+    // when both windows coincide); column col sits at col - cb (c) / col - db (d)
+    int RS = N, cb = 0, db = 0, half = N;
+    if (a.win) {
+        RS = a.rs;
+        half = RS / 2;
+        const int wc = task.w & 0xffff, wd = task.w >> 16;
+        cb = wc * a.win;
+        db = wd == wc ? cb : wd * a.win - half;
+    }
     double* FI = lds + LdsLayout<E, FP32>::ROWS;
-    double* FJ = FI + NA * N;
+    double* FJ = FI + NA * RS;
     if constexpr (MODE == 0) {
-        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) FI[i] = 0.0;
+        for (int i = threadIdx.x; i < (NA + NB) * RS; i += E::WGS) FI[i] = 0.0;
         __syncthreads();
     }
     double dab[NAB], jab[NAB];
@@ -376,7 +390,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, 
             for (int k = 0; k < NA; ++k) {
                 E::template run_pass<double>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim,
                                              bra.AB, ket.AB, t64, Ik);
-                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N);
+                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
             }
             ++n64;
             continue;
@@ -395,18 +409,19 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, 
             ++n32;
         }
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ, Dm, Wm, N);
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N);
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
     }
-    // bra J block: wave reduction, one add per wave
+    // bra J block: wave reduction, one global add per wave (column bfb may lie
+    // outside the task's windows)
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int mn = 0; mn < NAB; ++mn) {
         const double v = wave_sum(jab[mn]);
         if (lane == 0) {
             const int m = mn / NB, n = mn % NB;
-            row_add<MODE>(FI + m * N, Wm, bra.bfa + m, bra.bfb + n, N, 2.0 * a.cj * v);
+            atomicAdd(Wm + (size_t)(bra.bfa + m) * N + bra.bfb + n, 2.0 * a.cj * v);
         }
     }
     // quartet counters (one atomic per wave)
@@ -420,27 +435,30 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int4 task, 
     }
     if constexpr (MODE == 0) {
         __syncthreads();
-        for (int i = threadIdx.x; i < (NA + NB) * N; i += E::WGS) {
+        for (int i = threadIdx.x; i < (NA + NB) * RS; i += E::WGS) {
             const double v = FI[i];
             if (v != 0.0) {
-                const int row = i < NA * N ? bra.bfa + i / N : bra.bfb + (i - NA * N) / N;
-                const int col = i < NA * N ? i % N : (i - NA * N) % N;
-                atomicAdd(Wm + (size_t)row * N + col, v);
+                const int row = i < NA * RS ? bra.bfa + i / RS : bra.bfb + (i - NA * RS) / RS;
+                const int lc = i < NA * RS ? i % RS : (i - NA * RS) % RS;
+                const int col = lc + (lc < half ? cb : db);
+                if (col < N) atomicAdd(Wm + (size_t)row * N + col, v);
             }
         }
     }
 }
 
-// Static launch: workgroup i runs task i.
+// Static launch: workgroup i runs task task_off + i (a plan's tasks may span
+// several launches: a grid is limited to 2^32 work-items).
 template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
-    const int4 task = a.tasks[blockIdx.x];
+    const int ti = a.task_off + (int)blockIdx.x;
+    const int4 task = a.tasks[ti];
     if (!task_active(a, task)) return;
     double* t64 = lds;
     float* t32 = reinterpret_cast<float*>(lds);
     load_boys_lds<E, FP32>(a, t64, t32);
-    class_task<E, MODE, FP32>(a, task, t64, t32);
+    class_task<E, MODE, FP32>(a, ti, t64, t32);
 }
 
 // Persistent launch: a resident grid; a workgroup on XCD x (workgroup index
@@ -467,7 +485,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, FP32>(a, a.tasks[8 * k + x], t64, t32);
+        class_task<E, MODE, FP32>(a, 8 * k + x, t64, t32);
     }
 }
 

@@ -121,8 +121,6 @@ static void release_system(hfx_ctx* c) {
     c->host_ket.clear();
     c->host_kpos.clear();
     for (auto& p : c->plans) {
-        dfree(p.d_nket);
-        dfree(p.d_kseg);
         dfree(p.d_split);
         dfree(p.d_tasks);
         if (p.ev0) (void)hipEventDestroy(p.ev0);
@@ -134,7 +132,9 @@ static void release_system(hfx_ctx* c) {
     dfree(c->d_moff);
     dfree(c->d_mdim);
     dfree(c->d_mboff);
-    c->kseg.clear();
+    c->kgroup.clear();
+    c->kmolg.clear();
+    c->kwcode.clear();
     dfree(c->d_S);
     dfree(c->d_H);
     dfree(c->d_W);
@@ -234,32 +234,38 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     const double tau = c->opt.schwarz_tau;
     const int TQ = c->tune_tq[P.cid] > 0 ? c->tune_tq[P.cid] : c->opt.task_quartets;
     const bool stripe = c->tune_stripe[P.cid] >= 0 ? c->tune_stripe[P.cid] != 0 : true;
-    // bra r (molecule m) meets the kets of its own molecule: [seg[m], seg[m+1])
-    const std::vector<int>& seg = c->kseg[li];
-    std::vector<int> nket(bras.size(), 0);
-    std::vector<int2> kseg(bras.size(), make_int2(0, 0));
+    // bra r (molecule m) meets the kets of its own molecule's groups; in
+    // each group the kets with Q_s Q_r >= tau are a prefix (Q descending),
+    // and for B == K so are the kets not after the bra in the class order
+    const std::vector<int>& gs = c->kgroup[li];
+    const std::vector<int>& mg = c->kmolg[li];
+    const std::vector<int>& wcode = c->kwcode[li];
     const int nbra = (int)bras.size();
-    for (size_t r = 0; r < bras.size(); ++r) {
+    struct Run { int r, g, n; };
+    std::vector<Run> runs;
+    for (int r = 0; r < nbra; ++r) {
         const double qr = bras[r].Q;
-        const int kb = seg[bras[r].mol], ke = seg[bras[r].mol + 1];
-        int lo = kb, hi = ke;   // kets with Q_s Q_r >= tau: a prefix of the segment
-        while (lo < hi) {
-            const int mid = (lo + hi) / 2;
-            if (kets[mid].Q * qr >= tau) lo = mid + 1; else hi = mid;
-        }
-        int n = lo - kb;
-        if (B == K) {   // kets at or before the bra in the class order: a prefix too
-            int l2 = kb, h2 = ke;
-            while (l2 < h2) {
-                const int mid = (l2 + h2) / 2;
-                if (ket_pos[mid] <= bra_pos[r]) l2 = mid + 1; else h2 = mid;
+        for (int g = mg[bras[r].mol]; g < mg[bras[r].mol + 1]; ++g) {
+            const int kb = gs[g], ke = gs[g + 1];
+            int lo = kb, hi = ke;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (kets[mid].Q * qr >= tau) lo = mid + 1; else hi = mid;
             }
-            n = std::min(n, l2 - kb);
+            int n = lo - kb;
+            if (B == K) {
+                int l2 = kb, h2 = ke;
+                while (l2 < h2) {
+                    const int mid = (l2 + h2) / 2;
+                    if (ket_pos[mid] <= bra_pos[r]) l2 = mid + 1; else h2 = mid;
+                }
+                n = std::min(n, l2 - kb);
+            }
+            if (n <= 0) continue;
+            runs.push_back(Run{r, g, n});
+            P.quartets += (long long)n;
+            P.prim += (long long)bras[r].nprim * (long long)KL.kp * (long long)n;
         }
-        nket[r] = n;
-        kseg[r] = make_int2(kb, ke);
-        P.quartets += (long long)n;
-        P.prim += (long long)bras[r].nprim * (long long)KL.kp * (long long)n;
     }
     const int nint = ncart(kPairL[B][0]) * ncart(kPairL[B][1]) * ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
     P.integrals = P.quartets * nint;
@@ -269,7 +275,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     // share of each ket list; short prefixes fill the least loaded queue.
     // Queues are interleaved (task 8k + j = queue j's k-th entry) and padded
     // with empty tasks (r = -1).
-    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->max_ld * sizeof(double);
+    P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->rs * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
     const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
     P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);   // FP64 kernel
@@ -284,21 +290,21 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     const int NX = 8, WGS = hfx_class_wgs(P.cid, P.alt);
     std::vector<std::vector<int4>> queue(NX);
     std::vector<long long> load(NX, 0);
-    for (int r = 0; r < nbra; ++r) {
-        const int n = nket[r], kb = kseg[r].x;
+    for (const Run& ru : runs) {
+        const int r = ru.r, n = ru.n, kb = gs[ru.g], w = wcode[ru.g];
         if (stripe && n >= 2 * NX * WGS) {
             int nch = (n + TQ - 1) / TQ;
             nch = ((nch + NX - 1) / NX) * NX;
             int len = (n + nch - 1) / nch;
             len = ((len + WGS - 1) / WGS) * WGS;
             for (int j = 0, s0 = 0; s0 < n; ++j, s0 += len) {
-                queue[j % NX].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + len), 0));
+                queue[j % NX].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + len), w));
                 load[j % NX] += std::min(len, n - s0);
             }
         } else {
             for (int s0 = 0; s0 < n; s0 += TQ) {
                 const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                queue[q].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + TQ), 0));
+                queue[q].push_back(make_int4(r, kb + s0, kb + std::min(n, s0 + TQ), w));
                 load[q] += std::min(TQ, n - s0);
             }
         }
@@ -321,12 +327,8 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
     }
-    HIPCK(dalloc(&P.d_nket, nbra));
-    HIPCK(dalloc(&P.d_kseg, nbra));
-    HIPCK(dalloc(&P.d_split, nbra));
+    HIPCK(dalloc(&P.d_split, tasks.size()));
     HIPCK(dalloc(&P.d_tasks, tasks.size()));
-    HIPCK(hipMemcpy(P.d_nket, nket.data(), nbra * sizeof(int), hipMemcpyHostToDevice));
-    HIPCK(hipMemcpy(P.d_kseg, kseg.data(), nbra * sizeof(int2), hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(P.d_tasks, tasks.data(), tasks.size() * sizeof(int4), hipMemcpyHostToDevice));
     ClassTotals& T = c->totals[P.cid];
     T.quartets += P.quartets;
@@ -342,8 +344,6 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
 static hfx_status replan(hfx_ctx* c) {
     dfree(c->d_work);
     for (auto& p : c->plans) {
-        dfree(p.d_nket);
-        dfree(p.d_kseg);
         dfree(p.d_split);
         dfree(p.d_tasks);
         if (p.ev0) (void)hipEventDestroy(p.ev0);
@@ -659,10 +659,19 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
         HIPCK(dalloc(&c->d_pairs[B], L.size()));
         if (!L.empty()) HIPCK(hipMemcpy(c->d_pairs[B], L.data(), L.size() * sizeof(PairInfo), hipMemcpyHostToDevice));
     }
-    // ---- ket lists: one per pair class and primitive count (molecule segments) ----
+    // ---- ket lists: one per pair class and primitive count, in groups ----
+    // Large molecules: the bra rows staged in LDS cover two column windows
+    // of kWindow basis functions (shell c's and shell d's), so kets are
+    // grouped by (molecule, window of c, window of d), Q descending within
+    // a group; small ones stage whole rows (one group per molecule).
+    constexpr int kWindowAbove = 2048, kWindow = 768, kWindowPad = 8;   // pad: a shell's extent past its window
+    c->win = c->max_ld > kWindowAbove ? kWindow : 0;
+    c->rs = c->win ? 2 * (c->win + kWindowPad) : c->max_ld;
     std::vector<std::vector<PairInfo>> klist;
     std::vector<std::vector<double>> kpos;
-    c->kseg.clear();
+    c->kgroup.clear();
+    c->kmolg.clear();
+    c->kwcode.clear();
     for (int K = 0; K < 6; ++K) {
         std::vector<int> nps;
         for (auto& p : all[K])
@@ -681,9 +690,37 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
                 }
             KL.n = (int)sub.size();
             const size_t n = sub.size();
-            std::vector<int> seg(nmol + 1, 0);   // molecule m's kets: [seg[m], seg[m+1])
-            for (size_t s = 0; s < n; ++s) seg[sub[s].mol + 1]++;
-            for (int m = 0; m < nmol; ++m) seg[m + 1] += seg[m];
+            auto wc_of = [&](const PairInfo& p) { return c->win ? p.bfa / c->win : 0; };
+            auto wd_of = [&](const PairInfo& p) { return c->win ? p.bfb / c->win : 0; };
+            if (c->win) {   // stable: Q order kept within (molecule, wc, wd)
+                std::vector<size_t> idx(n);
+                for (size_t i = 0; i < n; ++i) idx[i] = i;
+                std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+                    const PairInfo &u = sub[x], &v = sub[y];
+                    if (u.mol != v.mol) return u.mol < v.mol;
+                    if (wc_of(u) != wc_of(v)) return wc_of(u) < wc_of(v);
+                    return wd_of(u) < wd_of(v);
+                });
+                std::vector<PairInfo> s2(n);
+                std::vector<double> p2(n);
+                for (size_t i = 0; i < n; ++i) {
+                    s2[i] = sub[idx[i]];
+                    p2[i] = sp[idx[i]];
+                }
+                sub.swap(s2);
+                sp.swap(p2);
+            }
+            std::vector<int> gstart, molg(nmol + 1, 0), wcode;
+            for (size_t s = 0; s < n; ++s) {
+                const int w = wc_of(sub[s]) | (wd_of(sub[s]) << 16);
+                if (s == 0 || sub[s].mol != sub[s - 1].mol || w != wcode.back()) {
+                    gstart.push_back((int)s);
+                    wcode.push_back(w);
+                    molg[sub[s].mol + 1] = (int)gstart.size();
+                }
+            }
+            gstart.push_back((int)n);
+            for (int m = 0; m < nmol; ++m) molg[m + 1] = std::max(molg[m + 1], molg[m]);   // molecules without kets
             std::vector<double> q(n), soa((size_t)9 * kp * n);
             for (size_t s = 0; s < n; ++s) {
                 q[s] = sub[s].Q;
@@ -704,7 +741,9 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
             c->ketlists.push_back(KL);
             klist.push_back(std::move(sub));
             kpos.push_back(std::move(sp));
-            c->kseg.push_back(std::move(seg));
+            c->kgroup.push_back(std::move(gstart));
+            c->kmolg.push_back(std::move(molg));
+            c->kwcode.push_back(std::move(wcode));
         }
     }
     c->host_bra.assign(all.begin(), all.end());
@@ -921,7 +960,7 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         const int cid = P.cid;
         const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid];
         if (mx)
-            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_kseg, P.d_nket, P.nbra, c->opt.fp32_tau, c->d_dmax, P.d_split,
+            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_tasks, P.ntask, c->opt.fp32_tau, c->d_dmax, P.d_split,
                             st));
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
@@ -931,6 +970,8 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.nket_list = KL.n;
         a.knprim = KL.kp;
         a.split = P.d_split;
+        a.win = c->win;
+        a.rs = c->rs;
         a.moff = c->d_moff;
         a.tasks = P.d_tasks;
         a.boys64 = c->d_boys64;
@@ -946,13 +987,32 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.work = P.persist ? c->d_work + 16 * pi : nullptr;
         a.qlen = P.ntask / 8;
         a.part = mx ? 1 : 0;
+        a.task_off = 0;
+        // a static grid of ntask workgroups is cut into launches of at most
+        // kMaxGroups (2^20 x 1024 lanes < 2^32 work-items; a multiple of 8
+        // keeps workgroup i on XCD i mod 8 in step with the task queues)
+        constexpr int kMaxGroups = 1 << 20;
+        auto launch = [&](ClassArgs& x, int fp32) -> hfx_status {
+            if (P.persist) {
+                HIPCK(hfx_launch_class(cid, P.alt, P.mode, fp32, P.nblocks[fp32], P.lds(fp32 != 0), st, &x));
+                return HFX_OK;
+            }
+            for (int off = 0; off < P.ntask; off += kMaxGroups) {
+                x.task_off = off;
+                HIPCK(hfx_launch_class(cid, P.alt, P.mode, fp32, std::min(kMaxGroups, P.ntask - off), P.lds(fp32 != 0),
+                                       st, &x));
+            }
+            return HFX_OK;
+        };
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        HIPCK(hfx_launch_class(cid, P.alt, P.mode, 0, P.persist ? P.nblocks[0] : P.ntask, P.lds(false), st, &a));
-        if (mx) {   // the same tasks' kets from split[r] on, in FP32
+        hfx_status ls = launch(a, 0);
+        if (ls != HFX_OK) return ls;
+        if (mx) {   // the same tasks' kets from their split on, in FP32
             ClassArgs b = a;
             b.part = 2;
             b.work = P.persist ? c->d_work + 16 * pi + 8 : nullptr;
-            HIPCK(hfx_launch_class(cid, P.alt, P.mode, 1, P.persist ? P.nblocks[1] : P.ntask, P.lds(true), st, &b));
+            ls = launch(b, 1);
+            if (ls != HFX_OK) return ls;
         }
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));

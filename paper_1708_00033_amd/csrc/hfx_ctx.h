@@ -32,9 +32,7 @@ struct SubPlan {
     int cid = 0, B = 0, K = 0, list = 0;
     int nbra = 0;             // bras with at least one ket
     int ntask = 0;
-    int* d_nket = nullptr;
-    int2* d_kseg = nullptr;   // per bra: its molecule's segment of the ket list
-    int* d_split = nullptr;
+    int* d_split = nullptr;   // per task: first ket evaluated in FP32 (mixed builds)
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;     // bra rows F_I, F_J (LDS digestion)
@@ -80,7 +78,13 @@ struct hfx_ctx {
     long long* d_moff = nullptr;
     int* d_mdim = nullptr;
     int* d_mboff = nullptr;
-    std::vector<std::vector<int>> kseg;   // per ket list: molecule segment starts (nmol + 1)
+    // Per ket list, groups of kets sharing (molecule, column window of shell c,
+    // column window of shell d), Q descending within a group: group starts
+    // (ngroup + 1), each molecule's first group (nmol + 1), window code per
+    // group (wc | wd << 16).  Without windows a group is a molecule.
+    std::vector<std::vector<int>> kgroup, kmolg, kwcode;
+    int win = 0;                          // column window (0: whole rows, no windows)
+    int rs = 0;                           // LDS row length of the bra rows (doubles)
     std::vector<int> Z;
     std::vector<double> axyz;
     std::vector<ShellHost> shells;
@@ -146,8 +150,8 @@ hipError_t hfx_prepare_density(const double* D, const double* cs, int nmol, cons
                                const int* mboff, int max_ld, double* Dp, unsigned long long* dmax_bits, hipStream_t st);
 hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
-hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int2* kseg, const int* nket, int nbra,
-                     double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st);
+hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int4* tasks, int ntask, double fp32_tau,
+                     const unsigned long long* dmax_bits, int* split, hipStream_t st);
 hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,
                            double* W, hipStream_t st);
 hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int nmol, const long long* moff,

@@ -42,9 +42,11 @@ struct ClassArgs {
     const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
     int nket_list, knprim;
-    const int* __restrict__ split;      // per bra: kets below this list position use FP64 (mixed builds)
-    const int4* __restrict__ tasks;     // (bra index, first ket, end ket, 0); bra -1: empty.  Task 8k + x is
-                                        // entry k of XCD x's queue
+    const int* __restrict__ split;      // per task: kets below this list position use FP64 (mixed builds)
+    const int4* __restrict__ tasks;     // (bra index, first ket, end ket, window code wc | wd << 16); bra -1:
+                                        // empty.  Task 8k + x is entry k of XCD x's queue
+    int win, rs;                        // column window (0: whole rows) and LDS bra-row length (doubles)
+    int task_off;                       // static launch: workgroup i runs task task_off + i
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
                                             // launch); null: one task per workgroup
     int qlen;                           // entries per XCD queue (tasks = 8 qlen)

@@ -53,23 +53,26 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
-// FP64/FP32 split per bra r: within its molecule's ket segment [kb, ke) the
-// kets s with Q_r Q_s max|D| >= fp32_tau come first (Q descending);
-// split[r] = kb + min(their count, nket[r]) is a list position.
+// FP64/FP32 split per task (bra r, kets [s0, s1) of one group): the kets s
+// with Q_r Q_s max|D| >= fp32_tau come first (Q descending within a group);
+// split[t] is the list position of the first FP32 ket (s1 if none).
 __global__ void k_split(const PairInfo* __restrict__ bra, const double* __restrict__ ketq,
-                        const int2* __restrict__ kseg, const int* __restrict__ nket, int nbra, double fp32_tau,
+                        const int4* __restrict__ tasks, int ntask, double fp32_tau,
                         const unsigned long long* __restrict__ dmax_bits, int* __restrict__ split) {
-    const int r = blockIdx.x * MISC_WG + threadIdx.x;
-    if (r >= nbra) return;
-    const double dmax = __longlong_as_double((long long)*dmax_bits);
-    const double qr = bra[r].Q * dmax;
-    const int kb = kseg[r].x, ke = kseg[r].y;
-    int lo = kb, hi = ke;
+    const int t = blockIdx.x * MISC_WG + threadIdx.x;
+    if (t >= ntask) return;
+    const int4 tk = tasks[t];
+    if (tk.x < 0) {
+        split[t] = 0;
+        return;
+    }
+    const double qr = bra[tk.x].Q * __longlong_as_double((long long)*dmax_bits);
+    int lo = tk.y, hi = tk.z;   // Q descending within a task's kets: the FP32 ones are a suffix
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (ketq[mid] * qr >= fp32_tau) lo = mid + 1; else hi = mid;
     }
-    split[r] = kb + min(lo - kb, nket[r]);
+    split[t] = lo;
 }
 
 // F = H + s_m s_n (W + W^T) / 8 per molecule block (H may be null: two-electron
@@ -401,11 +404,11 @@ hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u64, dim3((n + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, p, n);
     return hipGetLastError();
 }
-hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int2* kseg, const int* nket, int nbra,
-                     double fp32_tau, const unsigned long long* dmax_bits, int* split, hipStream_t st) {
-    if (nbra <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_split, dim3((nbra + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, kseg, nket,
-                       nbra, fp32_tau, dmax_bits, split);
+hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int4* tasks, int ntask, double fp32_tau,
+                     const unsigned long long* dmax_bits, int* split, hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split, dim3((ntask + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, tasks,
+                       ntask, fp32_tau, dmax_bits, split);
     return hipGetLastError();
 }
 hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,

@@ -268,6 +268,66 @@ def test_cluster64_sampled_blocks():
     assert ls[5] == 2 and ls[3] == 1
 
 
+def test_windowed_lds_digestion_112_waters():
+    """Above 2048 basis functions the LDS bra rows cover two column windows
+    per task (kets grouped by the windows of their shells): the whole J and K
+    equal the global-atomic digestion's, sampled blocks equal the oracle's,
+    and a mixed build (per-task FP32 split) stays within tolerance."""
+    import torch
+    import oracle
+    m = W.water_cluster(112, 5)
+    assert m.nbf > 2048
+    D = W.random_orthonormal_density(m.nbf, m.nocc, 23)
+    dD = torch.tensor(D, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for digest in (0, 1):
+        ctx = _hfx().Context(digest=digest).load(m)
+        J, K = torch.empty_like(dD), torch.empty_like(dD)
+        ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s)
+        ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s)
+        torch.cuda.synchronize()
+        out[digest] = (J.cpu().numpy(), K.cpu().numpy())
+        if digest == 0:
+            assert {p["mode"] for p in ctx.plans()} >= {0}
+    (J0, K0), (J1, K1) = out[0], out[1]
+    assert np.abs(J0 - J1).max() <= 1e-12 * np.abs(J1).max()
+    assert np.abs(K0 - K1).max() <= 1e-12 * np.abs(K1).max()
+    B = oracle.Basis(m)
+    bf = B.shell_bf
+    for a, b in [(0, 3), (5, 5), (700, 1115), (1000, 13)]:
+        Jb, Kb = B.jk_block(a, b, D, 1e-10)
+        na, nb = Jb.shape
+        assert np.abs(J0[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Jb).max() < 1e-10, (a, b)
+        assert np.abs(K0[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Kb).max() < 1e-10, (a, b)
+    ctx = _hfx().Context(precision=1).load(m)
+    G = torch.empty_like(dD)
+    st = ctx.build_2e_dev(dD.data_ptr(), 2.0, 1.0, G.data_ptr(), s, stats=True)
+    torch.cuda.synchronize()
+    assert st.quartets_fp32 > 0
+    assert np.abs(G.cpu().numpy() - (2 * J0 - K0)).max() < 1e-6
+
+
+def test_launch_chunks_cover_every_task():
+    """256-quartet tasks on the 64-water cluster give (ss|ss) more than 2^20
+    workgroups, so its static launches are chunked below the 2^32 work-item
+    grid limit: every planned quartet is evaluated and F is unchanged."""
+    import torch
+    m = W.cluster64_config()
+    ctx = _hfx().Context().load(m)
+    D = torch.tensor(W.random_orthonormal_density(m.nbf, m.nocc, 3), device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    ref = torch.empty_like(D)
+    st0 = ctx.build_fock_dev(D.data_ptr(), ref.data_ptr(), s, stats=True)
+    ctx.set_class_tuning(-1, 256, 0)
+    assert max(p["tasks"] for p in ctx.plans()) > (1 << 20)
+    out = torch.empty_like(D)
+    st1 = ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), s, stats=True)
+    planned = int(ctx.class_counts()[:, 0].sum())
+    assert st0.quartets_fp64 == planned and st1.quartets_fp64 == planned
+    assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+
+
 def test_scheduling_knobs_do_not_change_results():
     """Task size and XCD striping move work between workgroups only."""
     import torch
