@@ -212,7 +212,8 @@ def large_bench(args, log):
            "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
            "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load, "shards": G,
            "digest_modes": sorted(set(p["mode"] for p in ctx.plans()))}
-    for prec, Go, tag in ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed")):
+    for prec, Go, tag in (() if args.large_no_builds else
+                          ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"))):
         ctx.configure(precision=prec)
         ctx.kernel_timing(True)
         torch.cuda.synchronize()
@@ -229,17 +230,17 @@ def large_bench(args, log):
                     "quartets_fp32": int(st.quartets_fp32),
                     "class_ms": {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}}
         log(f"512 waters {tag} share build: {dt:.2f} s, {q:.3e} quartets, {q / dt:.3e} quartets/s")
-    out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
-    out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(0.5 * torch.sum(D * (Gmx - G64)).item())
-    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed"]["share_build_s"]
-    if args.large_scf:
-        for prec, tag in ((hfx.HFX_PREC_FP64, "scf_fp64"), (hfx.HFX_PREC_MIXED, "scf_mixed")):
-            ctx.configure(precision=prec)
-            r = ctx.scf()
-            out[tag] = {"energy": r["energy"], "iterations": r["iterations"], "converged": r["converged"],
-                        "t_total_s": r["t_total_s"], "t_fock_s": r["t_fock_s"]}
-            log(f"512 waters {tag}: E={r['energy']:.10f} it={r['iterations']} {r['t_total_s']:.1f} s")
-        out["scf_mixed"]["dE_vs_fp64"] = out["scf_mixed"]["energy"] - out["scf_fp64"]["energy"]
+    if not args.large_no_builds:
+        out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
+        out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(0.5 * torch.sum(D * (Gmx - G64)).item())
+        out["mixed"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed"]["share_build_s"]
+    scf_runs = {"none": (), "fp64": ("fp64",), "mixed": ("mixed",), "both": ("fp64", "mixed")}[args.large_scf]
+    for tag in scf_runs:
+        ctx.configure(precision=hfx.HFX_PREC_FP64 if tag == "fp64" else hfx.HFX_PREC_MIXED, log_level=1)
+        r = ctx.scf()   # the library prints one line per iteration (progress of a long run)
+        out["scf_" + tag] = {"energy": r["energy"], "iterations": r["iterations"], "converged": r["converged"],
+                             "t_total_s": r["t_total_s"], "t_fock_s": r["t_fock_s"]}
+        log(f"512 waters SCF {tag}: E={r['energy']:.10f} it={r['iterations']} {r['t_total_s']:.1f} s")
     return out
 
 
@@ -254,7 +255,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
     ap.add_argument("--large", action="store_true", help="also time FP64 and mixed builds of 512 waters")
-    ap.add_argument("--large-scf", action="store_true", help="with --large: full SCF in both precisions")
+    ap.add_argument("--large-scf", default="none", choices=["none", "fp64", "mixed", "both"],
+                    help="with --large: full SCF in these precisions")
+    ap.add_argument("--large-no-builds", action="store_true", help="with --large: skip the build timings")
     ap.add_argument("--large-shards", type=int, default=8, help="with --large: time one GPU's share of this many")
     ap.add_argument("--only-large", action="store_true", help="run only the 512-water part")
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
