@@ -306,13 +306,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 // build launches both over complementary ket ranges of every task: the FP64
 // kernel below split[r], the FP32 kernel from split[r] on.
 //
-// LDS of a class kernel: the class's Boys rows in the kernel's precision,
-// then (MODE 0) the bra rows F_I, F_J of the current task.
+// LDS of a class kernel: the class's Boys rows in the kernel's precision
+// (padded rows, BOYS_LROW64 / BOYS_LROW32 apart), then (MODE 0) the bra rows
+// F_I, F_J of the current task.
 template <class E, int FP32>
 struct LdsLayout {
     static constexpr int L = E::LA + E::LB + E::LC + E::LD;
-    static constexpr int T64 = FP32 ? 0 : boys_entries(L);   // doubles
-    static constexpr int T32 = FP32 ? boys_entries(L) : 0;   // floats
+    static constexpr int T64 = FP32 ? 0 : boys_rows(L) * BOYS_LROW64;   // doubles
+    static constexpr int T32 = FP32 ? boys_rows(L) * BOYS_LROW32 : 0;   // floats
     static constexpr int ROWS = T64 + T32 / 2;               // offset of the bra rows, doubles
 };
 
@@ -326,10 +327,12 @@ __device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, f
     using LL = LdsLayout<E, FP32>;
     if constexpr (FP32) {
         const float* __restrict__ g32 = a.boys32 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-        for (int i = threadIdx.x; i < LL::T32; i += E::WGS) t32[i] = g32[i];
+        for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
+            t32[(i / BOYS_ROW) * BOYS_LROW32 + i % BOYS_ROW] = g32[i];
     } else {
         const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-        for (int i = threadIdx.x; i < LL::T64; i += E::WGS) t64[i] = g64[i];
+        for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
+            t64[(i / BOYS_ROW) * BOYS_LROW64 + i % BOYS_ROW] = g64[i];
     }
     __syncthreads();
 }
@@ -388,8 +391,8 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             double Ik[NB * NC * ND];
 #pragma unroll 1
             for (int k = 0; k < NA; ++k) {
-                E::template run_pass<double>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim,
-                                             bra.AB, ket.AB, t64, Ik);
+                E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs,
+                                                          kps, a.knprim, bra.AB, ket.AB, t64, Ik);
                 digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
             }
             ++n64;
@@ -397,13 +400,13 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         }
         double I[NI];
         if constexpr (!FP32) {
-            E::template run<double>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
-                                    ket.AB, t64, I);
+            E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
+                                                 a.knprim, bra.AB, ket.AB, t64, I);
             ++n64;
         } else {
             float If[NI];
-            E::template run<float>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps, a.knprim, bra.AB,
-                                   ket.AB, t32, If);
+            E::template run<float, BOYS_LROW32>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
+                                                a.knprim, bra.AB, ket.AB, t32, If);
 #pragma unroll
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
@@ -565,12 +568,12 @@ struct ClassKernels {
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = false;                                                          \
-        template <typename R>                                                                          \
+        template <typename R, int BS = BOYS_ROW>                                                       \
         __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
                                                    int kfs, int kps, int nkp, const double* ab,        \
                                                    const double* cd, const R* tab, R* out) {           \
-            fname<R>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),   \
-                     R(cd[2]), tab, out);                                                              \
+            fname<R, BS>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),          \
+                         R(cd[1]), R(cd[2]), tab, out);                                                \
         }                                                                                              \
     };                                                                                                 \
     struct Eval##cid##A : Eval##cid {                                                                   \
@@ -587,20 +590,20 @@ struct ClassKernels {
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = true;                                                           \
-        template <typename R>                                                                          \
+        template <typename R, int BS = BOYS_ROW>                                                       \
         __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
                                                    int kfs, int kps, int nkp, const double* ab,        \
                                                    const double* cd, const R* tab, R* out) {           \
-            fname<R>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),   \
-                     R(cd[2]), tab, out);                                                              \
+            fname<R, BS>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),          \
+                         R(cd[1]), R(cd[2]), tab, out);                                                \
         }                                                                                              \
-        template <typename R>                                                                          \
+        template <typename R, int BS = BOYS_ROW>                                                       \
         __device__ __forceinline__ static void run_pass(int k, const PrimPair* bp, int nbp,            \
                                                         const double* kq0, int kfs, int kps, int nkp,  \
                                                         const double* ab, const double* cd,            \
                                                         const R* tab, R* out) {                        \
-            fname##_pass<R>(k, bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),   \
-                            R(cd[1]), R(cd[2]), tab, out);                                             \
+            fname##_pass<R, BS>(k, bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]),          \
+                                R(cd[0]), R(cd[1]), R(cd[2]), tab, out);                               \
         }                                                                                              \
     };                                                                                                 \
     struct Eval##cid##A : Eval##cid {                                                                   \

@@ -203,7 +203,7 @@ class ClassGen:
             self.vrr(e, f, 0)
         lines = []
         L = self.L
-        lines.append(f"template <typename R>\n__device__ __forceinline__ void {fname}(")
+        lines.append(f"template <typename R, int BS = BOYS_ROW>\n__device__ __forceinline__ void {fname}(")
         lines.append("    const PrimPair* __restrict__ bp, int nbp, const double* __restrict__ kq0, int kfs, int kps,")
         lines.append("    int nkp, const R AB0, const R AB1, const R AB2, const R CD0, const R CD1, const R CD2,")
         lines.append("    const R* __restrict__ boys_tab, R* __restrict__ out) {")
@@ -231,7 +231,7 @@ class ClassGen:
         lines.append("      const R T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);")
         lines.append("      const R pref = Kb * Kk * rs;")
         lines.append(f"      R F[{L + 1}];")
-        lines.append(f"      boys_eval<R, {L}>(T, F, boys_tab);")
+        lines.append(f"      boys_eval<R, {L}, BS>(T, F, boys_tab);")
         body = list(self.vrr_code)
         base = [f"const R b{m} = pref * F[{m}];" for m in sorted(self.base_used)]
         if L > 0:
@@ -276,13 +276,13 @@ def main(out_dir):
         if cid in PASS_CLASSES:
             for k in range(ncart(la)):
                 extra.append(ClassGen(la, lb, lc, ld).emit(f"{fname}_p{k}", a_sel=k))
-            sw = ["template <typename R>",
+            sw = ["template <typename R, int BS = BOYS_ROW>",
                   f"__device__ __forceinline__ void {fname}_pass(int k, const PrimPair* __restrict__ bp, int nbp,",
                   "    const double* __restrict__ kq0, int kfs, int kps, int nkp, const R AB0, const R AB1,",
                   "    const R AB2, const R CD0, const R CD1, const R CD2, const R* __restrict__ boys_tab,",
                   "    R* __restrict__ out) {", "  switch (k) {"]
             for k in range(ncart(la)):
-                sw.append(f"    case {k}: {fname}_p{k}<R>(bp, nbp, kq0, kfs, kps, nkp, AB0, AB1, AB2, CD0, CD1, CD2, "
+                sw.append(f"    case {k}: {fname}_p{k}<R, BS>(bp, nbp, kq0, kfs, kps, nkp, AB0, AB1, AB2, CD0, CD1, CD2, "
                           "boys_tab, out); break;")
             sw += ["    default: break;", "  }", "}"]
             extra.append("\n".join(sw))

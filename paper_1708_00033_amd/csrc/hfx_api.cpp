@@ -278,8 +278,8 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->rs * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
     const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
-    P.lds_tab[0] = (size_t)boys_entries(Ltot) * sizeof(double);   // FP64 kernel
-    P.lds_tab[1] = (size_t)boys_entries(Ltot) * sizeof(float);    // FP32 kernel of a mixed build
+    P.lds_tab[0] = (size_t)boys_lds_bytes(Ltot, false);   // FP64 kernel
+    P.lds_tab[1] = (size_t)boys_lds_bytes(Ltot, true);    // FP32 kernel of a mixed build
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
     P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;

@@ -88,8 +88,18 @@ struct ClassArgs {
 void hfx_boys_table(double* tab);   // host, BOYS_NL * BOYS_NT * BOYS_ROW entries
 
 __host__ __device__ constexpr int boys_block(int L) { return L == 0 ? 1 : (L == 1 ? 0 : L); }
-// table entries a class of total angular momentum L reads (from its block on)
-__host__ __device__ constexpr int boys_entries(int L) { return (L == 1 ? 2 : 1) * BOYS_NT * BOYS_ROW; }
+// table rows a class of total angular momentum L reads (from its block on)
+__host__ __device__ constexpr int boys_rows(int L) { return (L == 1 ? 2 : 1) * BOYS_NT; }
+__host__ __device__ constexpr int boys_entries(int L) { return boys_rows(L) * BOYS_ROW; }
+// Row strides of the LDS copy of a class's rows: 80 bytes (FP64) and 48
+// bytes (FP32) instead of 64 and 32, so that the 16-byte reads of lanes at
+// different rows start in 8 distinct groups of 4 of the 32 LDS banks rather
+// than in 2 (64 bytes: 16 banks) or 4 (32 bytes) of them.
+#define BOYS_LROW64 10
+#define BOYS_LROW32 12
+__host__ __device__ constexpr int boys_lds_bytes(int L, bool fp32) {
+    return fp32 ? boys_rows(L) * BOYS_LROW32 * 4 : boys_rows(L) * BOYS_LROW64 * 8;
+}
 
 __device__ __forceinline__ double hfx_sqrt(double x) { return sqrt(x); }
 // 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps
@@ -139,17 +149,19 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 // grid point, then the downward recursion F_m = (2T F_{m+1} + e^{-T})/(2m+1)
 // (for L = 1 both orders come from their tables, no exponential needed).
 // Above: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to FP64 there) and the upward recursion
-// F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m.
-// tab: the order-L block (followed by the order-0 block when L = 1).
-template <typename R, int L>
+// F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m (for L = 1 the
+// exponential term is below rounding and dropped).
+// tab: the order-L block (followed by the order-0 block when L = 1), rows S
+// elements apart.
+template <typename R, int L, int S = BOYS_ROW>
 __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) {
     constexpr int NO = BoysOrder<R>::value;
     if (T < R(BOYS_TMAX)) {
         const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
         const R d = R(k) * R(BOYS_DT) - T;
-        F[L] = boys_taylor<NO>(tab + k * BOYS_ROW, d);
+        F[L] = boys_taylor<NO>(tab + k * S, d);
         if constexpr (L == 1) {
-            F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * BOYS_ROW, d);
+            F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * S, d);
         } else if constexpr (L > 1) {
             const R e = hfx_exp(-T);
             const R t2 = R(2) * T;
@@ -159,7 +171,11 @@ __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) 
     } else {
         const R rt = hfx_rsqrt(T);
         F[0] = R(0.886226925452758013649083741671) * rt;   // sqrt(pi)/2 / sqrt(T)
-        if constexpr (L > 0) {
+        if constexpr (L == 1) {
+            // e^{-T} / F_0(T) < 3.1e-17 for T >= 40, below half an FP64 ulp:
+            // F_1 = F_0 / (2T) without the exponential
+            F[1] = F[0] * (R(0.5) * rt * rt);
+        } else if constexpr (L > 1) {
             const R e = hfx_exp(-T);
             const R h = R(0.5) * rt * rt;
 #pragma unroll
