@@ -42,18 +42,17 @@ __device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, in
 
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
-                                       const PairInfo& ket, int spos, const double* dab, double* jab, double* FI,
+                                       int fc, int fd, int spos, const double* dab, double* jab, double* FI,
                                        double* FJ, const double* __restrict__ D, double* __restrict__ W, int N,
                                        int RS, int cb, int db) {
-    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+    const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
     {
+        // D_cd gathered in ket-list order before the build (coalesced across lanes)
         double dcd[NC * ND];
 #pragma unroll
-        for (int l = 0; l < NC; ++l)
-#pragma unroll
-            for (int s = 0; s < ND; ++s) dcd[l * ND + s] = D[(size_t)(fc + l) * N + fd + s];
+        for (int ls = 0; ls < NC * ND; ++ls) dcd[ls] = a.dket[(size_t)ls * a.nket_list + spos];
 #pragma unroll
         for (int mn = 0; mn < NA * NB; ++mn) {
             double v = 0.0;
@@ -159,17 +158,16 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 // large to keep in registers (the block then lives in scratch).
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_rolled(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
-                                              const PairInfo& ket, const double* dab, double* jab, double* FI,
-                                              double* FJ, const double* __restrict__ D, double* __restrict__ W,
-                                              int N, int RS, int cb, int db) {
-    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+                                              int fc, int fd, int spos, const double* dab, double* jab,
+                                              double* FI, double* FJ, const double* __restrict__ D,
+                                              double* __restrict__ W, int N, int RS, int cb, int db) {
+    const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
 #pragma unroll 1
     for (int mn = 0; mn < NA * NB; ++mn) {
         double v = 0.0;
 #pragma unroll 1
-        for (int ls = 0; ls < NC * ND; ++ls)
-            v += I[mn * NC * ND + ls] * D[(size_t)(fc + ls / ND) * N + fd + ls % ND];
+        for (int ls = 0; ls < NC * ND; ++ls) v += I[mn * NC * ND + ls] * a.dket[(size_t)ls * a.nket_list + spos];
         jab[mn] += g * v;
     }
 #pragma unroll 1
@@ -235,17 +233,17 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 // lives in scratch, 8 NB NC ND bytes per lane).
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_pass(int k, const double* I, double g, const ClassArgs& a,
-                                            const PairInfo& bra, const PairInfo& ket, int spos, const double* dab,
+                                            const PairInfo& bra, int fc, int fd, int spos, const double* dab,
                                             double* jab, double* FI, double* FJ, const double* __restrict__ D,
                                             double* __restrict__ W, int N, int RS, int cb, int db) {
-    const int fa = bra.bfa, fb = bra.bfb, fc = ket.bfa, fd = ket.bfb;
+    const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     constexpr int NCD = NC * ND;
 #pragma unroll 1
     for (int n = 0; n < NB; ++n) {   // J, bra block (mu = k)
         double v = 0.0;
 #pragma unroll 1
-        for (int ls = 0; ls < NCD; ++ls) v += I[n * NCD + ls] * D[(size_t)(fc + ls / ND) * N + fd + ls % ND];
+        for (int ls = 0; ls < NCD; ++ls) v += I[n * NCD + ls] * a.dket[(size_t)ls * a.nket_list + spos];
         jab[k * NB + n] += g * v;
     }
 #pragma unroll 1
@@ -384,16 +382,19 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     const int kps = a.nket_list, kfs = a.nket_list * a.knprim;
     unsigned n64 = 0, n32 = 0;
     for (int s = s0 + (int)threadIdx.x; s < send; s += E::WGS) {
-        const PairInfo ket = a.ket[s];
-        const double g = sbra * (ket.a != ket.b ? 2.0 : 1.0) * ((ket.a == bra.a && ket.b == bra.b) ? 1.0 : 2.0);
+        const int4 kb = a.kbf[s];   // ket's first basis functions and shells
+        const int fc = kb.x, fd = kb.y;
+        const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+        const double* kab = a.ket[s].AB;   // read only by classes with a p or d ket
         if constexpr (E::PASSES) {
             // one Cartesian component of shell a per pass: a small block per pass
             double Ik[NB * NC * ND];
 #pragma unroll 1
             for (int k = 0; k < NA; ++k) {
                 E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs,
-                                                          kps, a.knprim, bra.AB, ket.AB, t64, Ik);
-                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
+                                                          kps, a.knprim, bra.AB, kab, t64, Ik);
+                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
+                                                  db);
             }
             ++n64;
             continue;
@@ -401,20 +402,20 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         double I[NI];
         if constexpr (!FP32) {
             E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
-                                                 a.knprim, bra.AB, ket.AB, t64, I);
+                                                 a.knprim, bra.AB, kab, t64, I);
             ++n64;
         } else {
             float If[NI];
             E::template run<float, BOYS_LROW32>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
-                                                a.knprim, bra.AB, ket.AB, t32, If);
+                                                a.knprim, bra.AB, kab, t32, If);
 #pragma unroll
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
         }
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, ket, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
     // outside the task's windows)

@@ -45,6 +45,8 @@ CLASSES = [(B, K) for B in range(6) for K in range(B + 1)]
 # SIMD), 512 where it fits in 256, 256 for the register-heavy classes.
 WG1024 = {1, 6}
 WG512 = {0, 2, 3, 4, 7, 9, 10}
+# Classes whose bra primitive loop runs two primitives per trip.
+UNROLL2 = set()
 
 
 def wg_size(cid):
@@ -86,8 +88,9 @@ def direction(v):
 
 
 class ClassGen:
-    def __init__(self, la, lb, lc, ld):
+    def __init__(self, la, lb, lc, ld, unroll2=False):
         self.la, self.lb, self.lc, self.ld = la, lb, lc, ld
+        self.unroll2 = unroll2
         self.L = la + lb + lc + ld
         self.vrr_nodes = {}
         self.vrr_code = []
@@ -218,36 +221,58 @@ class ClassGen:
         lines.append("    // bra primitives (uniform across the workgroup)")
         # a rolled bra loop measured as fast as an unrolled one for low L (the
         # waves per SIMD hide the recurrence latency) and compiles faster
-        lines.append("#pragma unroll 1")
-        lines.append("    for (int ib = 0; ib < nbp; ++ib) {")
-        lines.append("      // uniform address in the constant address space: scalar loads")
-        lines.append("      const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + ib);")
-        lines.append("      const R p = R(B[0]), i2p = R(B[1]), Kb = R(B[8]);")
-        lines.append("      const R PA0 = R(B[5]), PA1 = R(B[6]), PA2 = R(B[7]);")
-        lines.append("      const R PQ0 = R(B[2]) - Q0, PQ1 = R(B[3]) - Q1, PQ2 = R(B[4]) - Q2;")
-        lines.append("      const R rs = hfx_rsqrt(p + q);   // 1/sqrt(p+q)")
-        lines.append("      const R ipq = rs * rs;")
-        lines.append("      const R rho = p * q * ipq;")
-        lines.append("      const R T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);")
-        lines.append("      const R pref = Kb * Kk * rs;")
-        lines.append(f"      R F[{L + 1}];")
-        lines.append(f"      boys_eval<R, {L}, BS>(T, F, boys_tab);")
+        # one bra primitive: scalar loads at a uniform address in the constant
+        # address space, then the Boys function and the recurrences
+        blk = ["const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + IB);",
+               "const R p = R(B[0]), i2p = R(B[1]), Kb = R(B[8]);",
+               "const R PA0 = R(B[5]), PA1 = R(B[6]), PA2 = R(B[7]);",
+               "const R PQ0 = R(B[2]) - Q0, PQ1 = R(B[3]) - Q1, PQ2 = R(B[4]) - Q2;",
+               "const R rs = hfx_rsqrt(p + q);   // 1/sqrt(p+q)",
+               "const R ipq = rs * rs;",
+               "const R rho = p * q * ipq;",
+               "const R T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);",
+               "const R pref = Kb * Kk * rs;",
+               f"R F[{L + 1}];",
+               f"boys_eval<R, {L}, BS>(T, F, boys_tab);"]
         body = list(self.vrr_code)
         base = [f"const R b{m} = pref * F[{m}];" for m in sorted(self.base_used)]
         if L > 0:
-            lines.append("      const R WP0 = -q * ipq * PQ0, WP1 = -q * ipq * PQ1, WP2 = -q * ipq * PQ2;")
-            lines.append("      const R WQ0 = p * ipq * PQ0, WQ1 = p * ipq * PQ1, WQ2 = p * ipq * PQ2;")
-            lines.append("      const R rp = q * ipq, rq = p * ipq, i2pq = R(0.5) * ipq;")
-            lines.append("      (void)WP0; (void)WP1; (void)WP2; (void)WQ0; (void)WQ1; (void)WQ2;")
-            lines.append("      (void)rp; (void)rq; (void)i2pq; (void)i2p; (void)i2q;")
-            lines.append("      (void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;")
+            blk += ["const R WP0 = -q * ipq * PQ0, WP1 = -q * ipq * PQ1, WP2 = -q * ipq * PQ2;",
+                    "const R WQ0 = p * ipq * PQ0, WQ1 = p * ipq * PQ1, WQ2 = p * ipq * PQ2;",
+                    "const R rp = q * ipq, rq = p * ipq, i2pq = R(0.5) * ipq;",
+                    "(void)WP0; (void)WP1; (void)WP2; (void)WQ0; (void)WQ1; (void)WQ2;",
+                    "(void)rp; (void)rq; (void)i2pq; (void)i2p; (void)i2q;",
+                    "(void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;"]
         else:
-            lines.append("      (void)i2p; (void)i2q; (void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;")
-        for s in base + body:
-            lines.append("      " + s)
-        for (e, f), a in acc_name.items():
-            lines.append(f"      {a} += {self.vrr_nodes[(e, f, 0)]};")
-        lines.append("    }")
+            blk.append("(void)i2p; (void)i2q; (void)PA0; (void)PA1; (void)PA2; (void)QC0; (void)QC1; (void)QC2;")
+        blk += base + body
+        blk += [f"{a} += {self.vrr_nodes[(e, f, 0)]};" for (e, f), a in acc_name.items()]
+
+        def emit_blk(ind, ib):
+            for x in blk:
+                lines.append(ind + x.replace("IB", ib))
+
+        if self.unroll2:
+            # two bra primitives per trip, in separate scopes of one straight-line
+            # block, so that the scheduler interleaves their independent chains
+            lines.append("    int ib = 0;")
+            lines.append("#pragma unroll 1")
+            lines.append("    for (; ib + 1 < nbp; ib += 2) {")
+            lines.append("      {")
+            emit_blk("        ", "ib")
+            lines.append("      }")
+            lines.append("      {")
+            emit_blk("        ", "(ib + 1)")
+            lines.append("      }")
+            lines.append("    }")
+            lines.append("    if (ib < nbp) {")
+            emit_blk("      ", "ib")
+            lines.append("    }")
+        else:
+            lines.append("#pragma unroll 1")
+            lines.append("    for (int ib = 0; ib < nbp; ++ib) {")
+            emit_blk("      ", "ib")
+            lines.append("    }")
         lines.append("  }")
         lines.append("  (void)AB0; (void)AB1; (void)AB2; (void)CD0; (void)CD1; (void)CD2;")
         lines.extend(hcode)
@@ -269,7 +294,7 @@ def main(out_dir):
     for cid, (B, K) in enumerate(CLASSES):
         la, lb = PAIR_CLASSES[B]
         lc, ld = PAIR_CLASSES[K]
-        g = ClassGen(la, lb, lc, ld)
+        g = ClassGen(la, lb, lc, ld, cid in UNROLL2)
         fname = f"eri_{PAIR_NAMES[B]}_{PAIR_NAMES[K]}"
         body = g.emit(fname)
         extra = []

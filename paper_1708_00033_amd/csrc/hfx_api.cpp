@@ -114,6 +114,8 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_q);
         dfree(L.d_soa);
         dfree(L.d_wket);
+        dfree(L.d_kbf);
+        dfree(L.d_dket);
     }
     c->ketlists.clear();
     c->host_bra.clear();
@@ -722,8 +724,10 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
             gstart.push_back((int)n);
             for (int m = 0; m < nmol; ++m) molg[m + 1] = std::max(molg[m + 1], molg[m]);   // molecules without kets
             std::vector<double> q(n), soa((size_t)9 * kp * n);
+            std::vector<int4> kbf(n);
             for (size_t s = 0; s < n; ++s) {
                 q[s] = sub[s].Q;
+                kbf[s] = make_int4(sub[s].bfa, sub[s].bfb, sub[s].a, sub[s].b);
                 for (int k = 0; k < kp; ++k) {
                     const PrimPair& pp = prim[sub[s].prim_off + k];
                     const double f[9] = {pp.p, pp.inv2p, pp.P[0], pp.P[1], pp.P[2], pp.PA[0], pp.PA[1], pp.PA[2], pp.K};
@@ -735,6 +739,9 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
             HIPCK(dalloc(&KL.d_soa, soa.size()));
             KL.ncd = ncart(kPairL[K][0]) * ncart(kPairL[K][1]);
             HIPCK(dalloc(&KL.d_wket, (size_t)KL.ncd * n));
+            HIPCK(dalloc(&KL.d_dket, (size_t)KL.ncd * n));
+            HIPCK(dalloc(&KL.d_kbf, n));
+            HIPCK(hipMemcpy(KL.d_kbf, kbf.data(), n * sizeof(int4), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_pairs, sub.data(), n * sizeof(PairInfo), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_q, q.data(), n * sizeof(double), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_soa, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -950,7 +957,11 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
     HIPCK(hfx_prepare_density(dD, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, c->d_Dp,
                               c->d_dmax, st));
     HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
-    for (auto& KL : c->ketlists) HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
+    for (auto& KL : c->ketlists) {
+        HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
+        HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), c->d_Dp, c->d_moff,
+                             KL.d_dket, st));
+    }
     bool any_persist = false;
     for (const auto& P : c->plans) any_persist |= P.persist;
     if (any_persist) HIPCK(hfx_fill_u64(c->d_work, 16 * (int)c->plans.size(), st));
@@ -965,6 +976,8 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
         a.ket = KL.d_pairs;
+        a.kbf = KL.d_kbf;
+        a.dket = KL.d_dket;
         a.prim = c->d_prim;
         a.kprim = KL.d_soa;
         a.nket_list = KL.n;

@@ -24,6 +24,8 @@ struct KetList {
     double* d_q = nullptr;
     double* d_soa = nullptr;
     double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
+    double* d_dket = nullptr;   // D'_cd of every ket, gathered per build, same layout
+    int4* d_kbf = nullptr;      // per ket: (bfa, bfb, a, b)
     int ncd = 1;
 };
 
@@ -152,6 +154,8 @@ hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int4* tasks, int ntask, double fp32_tau,
                      const unsigned long long* dmax_bits, int* split, hipStream_t st);
+hipError_t hfx_gather_ket(const PairInfo* kets, int n, int nc, int nd, const double* D, const long long* moff,
+                          double* dket, hipStream_t st);
 hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,
                            double* W, hipStream_t st);
 hipError_t hfx_assemble(const double* H, const double* W, const double* cs, int nmol, const long long* moff,

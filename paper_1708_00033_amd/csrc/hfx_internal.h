@@ -39,6 +39,8 @@ struct PairInfo {
 struct ClassArgs {
     const PairInfo* __restrict__ bra;   // bra pairs of the class, Q descending
     const PairInfo* __restrict__ ket;   // ket pairs (one primitive count), Q descending
+    const int4* __restrict__ kbf;       // per ket: first basis functions and shells (bfa, bfb, a, b)
+    const double* __restrict__ dket;    // per build: D'_cd of every ket, [component][ket position]
     const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
     int nket_list, knprim;
@@ -148,6 +150,8 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 // F[0..L] at T.  Below BOYS_TMAX: Taylor expansion of F_L about the nearest
 // grid point, then the downward recursion F_m = (2T F_{m+1} + e^{-T})/(2m+1)
 // (for L = 1 both orders come from their tables, no exponential needed).
+// For L <= 1 the two regimes are branches; for L >= 2 both are evaluated
+// with one shared exponential and selected per lane.
 // Above: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to FP64 there) and the upward recursion
 // F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m (for L = 1 the
 // exponential term is below rounding and dropped).
@@ -156,31 +160,39 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 template <typename R, int L, int S = BOYS_ROW>
 __device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) {
     constexpr int NO = BoysOrder<R>::value;
-    if (T < R(BOYS_TMAX)) {
-        const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
-        const R d = R(k) * R(BOYS_DT) - T;
-        F[L] = boys_taylor<NO>(tab + k * S, d);
-        if constexpr (L == 1) {
-            F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * S, d);
-        } else if constexpr (L > 1) {
-            const R e = hfx_exp(-T);
-            const R t2 = R(2) * T;
-#pragma unroll
-            for (int m = L - 1; m >= 0; --m) F[m] = (t2 * F[m + 1] + e) * R(1.0 / (2 * m + 1));
-        }
-    } else {
-        const R rt = hfx_rsqrt(T);
-        F[0] = R(0.886226925452758013649083741671) * rt;   // sqrt(pi)/2 / sqrt(T)
-        if constexpr (L == 1) {
+    if constexpr (L <= 1) {
+        if (T < R(BOYS_TMAX)) {
+            const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
+            const R d = R(k) * R(BOYS_DT) - T;
+            F[L] = boys_taylor<NO>(tab + k * S, d);
+            if constexpr (L == 1) F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * S, d);
+        } else {
+            const R rt = hfx_rsqrt(T);
+            F[0] = R(0.886226925452758013649083741671) * rt;   // sqrt(pi)/2 / sqrt(T)
             // e^{-T} / F_0(T) < 3.1e-17 for T >= 40, below half an FP64 ulp:
             // F_1 = F_0 / (2T) without the exponential
-            F[1] = F[0] * (R(0.5) * rt * rt);
-        } else if constexpr (L > 1) {
-            const R e = hfx_exp(-T);
-            const R h = R(0.5) * rt * rt;
-#pragma unroll
-            for (int m = 0; m < L; ++m) F[m + 1] = (R(2 * m + 1) * F[m] - e) * h;
+            if constexpr (L == 1) F[1] = F[0] * (R(0.5) * rt * rt);
         }
+    } else {
+        // both regimes evaluated with one exponential, each lane selects its
+        // own (the lanes of a wave usually straddle BOYS_TMAX); rows clamped
+        // into the table for lanes in the asymptotic regime
+        const bool near = T < R(BOYS_TMAX);
+        const int k = (int)(near ? T * R(BOYS_INV_DT) + R(0.5) : R(0));
+        const R d = R(k) * R(BOYS_DT) - T;
+        const R rt = hfx_rsqrt(T);
+        const R h = R(0.5) * rt * rt;   // 1/(2T)
+        const R e = hfx_exp(-T);
+        R down[L + 1], up[L + 1];
+        down[L] = boys_taylor<NO>(tab + k * S, d);
+        const R t2 = R(2) * T;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) down[m] = (t2 * down[m + 1] + e) * R(1.0 / (2 * m + 1));
+        up[0] = R(0.886226925452758013649083741671) * rt;
+#pragma unroll
+        for (int m = 0; m < L; ++m) up[m + 1] = (R(2 * m + 1) * up[m] - e) * h;
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] = near ? down[m] : up[m];
     }
 }
 

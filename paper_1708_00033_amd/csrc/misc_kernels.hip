@@ -93,6 +93,17 @@ __global__ void k_assemble(const double* __restrict__ H, const double* __restric
     }
 }
 
+// dket[comp][s] = D'_cd of ket pair s of one list (component comp of its
+// block), so that the class kernels read it coalesced by ket position.
+__global__ void k_gather_ket(const PairInfo* __restrict__ kets, int n, int nc, int nd, const double* __restrict__ D,
+                             const long long* __restrict__ moff, double* __restrict__ dket) {
+    const int i = blockIdx.x * MISC_WG + threadIdx.x;
+    if (i >= n * nc * nd) return;
+    const int s = i % n, comp = i / n;
+    const PairInfo p = kets[s];
+    dket[i] = D[(size_t)moff[p.mol] + (size_t)(p.bfa + comp / nd) * p.ld + p.bfb + comp % nd];
+}
+
 // W_cd += wket[comp][s] for every ket pair s of one list: each pair owns its
 // W block, so plain read-modify-write (no atomics) after the class kernels.
 __global__ void k_scatter_ket(const PairInfo* __restrict__ kets, int n, int nc, int nd,
@@ -409,6 +420,14 @@ hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int4* tasks,
     if (ntask <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_split, dim3((ntask + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, bra, ketq, tasks,
                        ntask, fp32_tau, dmax_bits, split);
+    return hipGetLastError();
+}
+hipError_t hfx_gather_ket(const PairInfo* kets, int n, int nc, int nd, const double* D, const long long* moff,
+                          double* dket, hipStream_t st) {
+    const int tot = n * nc * nd;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_ket, dim3((tot + MISC_WG - 1) / MISC_WG), dim3(MISC_WG), 0, st, kets, n, nc, nd, D, moff,
+                       dket);
     return hipGetLastError();
 }
 hipError_t hfx_scatter_ket(const PairInfo* kets, int n, int nc, int nd, const double* wket, const long long* moff,
