@@ -381,24 +381,29 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     const double sbra = bra.a != bra.b ? 2.0 : 1.0;
     const int kps = a.nket_list, kfs = a.nket_list * a.knprim;
     unsigned n64 = 0, n32 = 0;
-    for (int s = s0 + (int)threadIdx.x; s < send; s += E::WGS) {
+    if constexpr (E::PASSES) {
+        // one Cartesian component of shell a per pass, and the passes of a
+        // quartet on different lanes: work item it = k * nq + (s - s0), so a
+        // short task (few kets) still fills NA times as many lanes, and the
+        // lanes of a wave share k
+        const int nq = send - s0;
+        for (int it = (int)threadIdx.x; it < NA * nq; it += E::WGS) {
+            const int k = it / nq, s = s0 + it % nq;
+            const int4 kb = a.kbf[s];
+            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+            double Ik[NB * NC * ND];
+            E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
+                                                      a.knprim, bra.AB, a.ket[s].AB, t64, Ik);
+            digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
+                                              db);
+            if (k == 0) ++n64;
+        }
+    }
+    for (int s = s0 + (int)threadIdx.x; s < send && !E::PASSES; s += E::WGS) {
         const int4 kb = a.kbf[s];   // ket's first basis functions and shells
         const int fc = kb.x, fd = kb.y;
         const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
         const double* kab = a.ket[s].AB;   // read only by classes with a p or d ket
-        if constexpr (E::PASSES) {
-            // one Cartesian component of shell a per pass: a small block per pass
-            double Ik[NB * NC * ND];
-#pragma unroll 1
-            for (int k = 0; k < NA; ++k) {
-                E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs,
-                                                          kps, a.knprim, bra.AB, kab, t64, Ik);
-                digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
-                                                  db);
-            }
-            ++n64;
-            continue;
-        }
         double I[NI];
         if constexpr (!FP32) {
             E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
