@@ -166,10 +166,15 @@ def batched_bench(args, log):
         t_sscf32 = time.perf_counter() - t
         dE = max(abs(b["energy"] - r["energy"]) for b, r in zip(bres[:32], sres))
         log(f"batched SCF of 256 clusters: {t_bscf:.1f} s; 32 single SCFs: {t_sscf32:.1f} s")
+    # whole-build model flops (the roofline model of the class kernels) per second
+    model = class_flop_model()
+    flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     return {"workload": "256 water clusters, sizes ~U{1..16} (seed 2), molecule i seed 2e6+i, s/p/d basis",
             "molecules": len(mols), "basis_functions": int(nbf.sum()), "quartets_per_build": quartets,
             "load_s": t_load,
             "fp64_ms": t64 * 1e3, "fp64_quartets_per_s": quartets / t64,
+            "fp64_model_tflops": flops / t64 / 1e12, "fp64_frac_fp64_peak": flops / t64 / 1e12 / FP64_PEAK_TFLOPS,
+            "mixed_model_tflops": flops / tmx / 1e12, "mixed_frac_fp64_peak": flops / tmx / 1e12 / FP64_PEAK_TFLOPS,
             "graph_replay_ms": tg * 1e3, "graph_max_abs_diff": graph_err,
             "mixed_ms": tmx * 1e3, "mixed_quartets_per_s": quartets / tmx, "mixed_max_abs_dF": mixed_err,
             "one_context_per_molecule_ms": tseq * 1e3, "one_context_per_molecule_max_abs_diff": seq_err,
@@ -401,13 +406,16 @@ def main():
                   "speedup_vs_fp64": dt64 / dtmx, "fp32_tau": 1e-7, "quartets_fp32": int(stmx.quartets_fp32),
                   "quartets_fp64": int(stmx.quartets_fp64), "max_abs_dF_vs_fp64": Fd,
                   "fp32_classes": fp32_classes,
-                  "dE_vs_fp64_at_fixed_D": dE},
+                  "dE_vs_fp64_at_fixed_D": dE,
+                  "build_flops_model_tflops": total_flops / (dtmx / args.steps) / 1e12,
+                  "build_frac_fp64_peak": total_flops / (dtmx / args.steps) / 1e12 / FP64_PEAK_TFLOPS},
         "roofline": {"bound": "alu", "kernel": kname, "class": hfx.CLASS_NAMES[dom["cls"]],
                      "ket_nprim": dom["ket_nprim"], "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch),
                      "quartets_per_launch": dom["quartets"], "primitive_quartets_per_launch": dom["prim"]},
         "build_flops_model_tflops": total_flops / (dt64 / args.steps) / 1e12,
+        "build_frac_fp64_peak": total_flops / (dt64 / args.steps) / 1e12 / FP64_PEAK_TFLOPS,
         "class_ms_fp64": {hfx.CLASS_NAMES[k]: round(ms64[k] / max(n64[k], 1), 3) for k in np.argsort(-ms64)[:8]},
         "class_ms_mixed": {hfx.CLASS_NAMES[k]: round(msmx[k] / max(nmx[k], 1), 3) for k in np.argsort(-msmx)[:8]},
         "scf": {"energy": r["energy"], "iterations": r["iterations"]},
