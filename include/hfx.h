@@ -203,7 +203,9 @@ hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
  * ket prefixes (1 on, 0 off, -1 default on), the launch form (0: one
  * workgroup per task; 1: persistent, a resident grid that takes tasks from
  * eight per-XCD queues through atomic counters, the dynamic load balancing
- * of algorithms 1-3's ddi_dlbnext) and the digestion (-1: the context's
+ * of algorithms 1-3's ddi_dlbnext; 2: persistent with one task per wave,
+ * each wave with its own LDS bra rows, for short tasks; falls back to 1 when
+ * the workgroup's rows do not fit in LDS) and the digestion (-1: the context's
  * option; HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL; LDS staging needs
  * (n_a + n_b) x nbf x 8 bytes <= 160 KiB and falls back to global
  * otherwise).  Re-plans a loaded system; results are unchanged up to the
@@ -232,7 +234,7 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 /* Launches of a build: one per (quartet class, ket primitive count).
  * info[11] = {class index, ket primitives per pair, workgroup tasks, unique
  * quartets, primitive quartets, integrals, timed launches, digestion mode,
- * work-items per workgroup, persistent (0/1), workgroups of the FP64
+ * work-items per workgroup, launch form (0/1/2 as in hfx_set_class_tuning), workgroups of the FP64
  * kernel}; *ms = summed event time of the timed launches (a mixed build
  * times its FP64 and FP32 kernels together). */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);

@@ -18,11 +18,17 @@ static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPT
 // (persistent launch, args->work set).
 extern "C" int hfx_class_wgs(int cid, int alt) { return alt ? kEriClassInfo[cid].wgs_alt : kEriClassInfo[cid].wgs; }
 
-// alt: the class's alternative workgroup size (kEriClassInfo.wgs_alt).
-extern "C" hipError_t hfx_launch_class(int cid, int alt, int mode, int mixed, int nblocks, size_t lds_bytes,
-                                       hipStream_t stream, const ClassArgs* args) {
+// alt: the class's alternative workgroup size (kEriClassInfo.wgs_alt);
+// wave: one task per wave (a persistent launch, args->work set).
+static int class_variant(int alt, int persistent, int wave, int mode, int mixed) {
+    return (wave ? 16 : 0) + (alt ? 8 : 0) + (persistent ? 4 : 0) + mode * 2 + mixed;
+}
+
+extern "C" hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int nblocks,
+                                       size_t lds_bytes, hipStream_t stream, const ClassArgs* args) {
     if (nblocks <= 0) return hipSuccess;
-    const void* fn = kClassLookup[cid]((alt ? 8 : 0) + (args->work ? 4 : 0) + mode * 2 + mixed);
+    if (wave && !args->work) return hipErrorInvalidValue;
+    const void* fn = kClassLookup[cid](class_variant(alt, args->work != nullptr, wave, mode, mixed));
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -32,8 +38,8 @@ extern "C" hipError_t hfx_launch_class(int cid, int alt, int mode, int mixed, in
 }
 
 // Workgroups of one class kernel that fit on the device at once.
-extern "C" int hfx_class_resident_blocks(int cid, int alt, int mode, int mixed, size_t lds_bytes) {
-    const void* fn = kClassLookup[cid]((alt ? 8 : 0) + 4 + mode * 2 + mixed);
+extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes) {
+    const void* fn = kClassLookup[cid](class_variant(alt, 1, wave, mode, mixed));
     if (lds_bytes > 64 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
         return 0;

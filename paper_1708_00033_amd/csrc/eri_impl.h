@@ -335,10 +335,26 @@ __device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, f
     __syncthreads();
 }
 
-template <class E, int MODE, int FP32>
+// LDS ordering point of the lanes that run one task: the workgroup, or (WAVE)
+// the single wave, whose LDS operations are processed in order.
+template <bool WAVE>
+__device__ __forceinline__ void task_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// One task (one bra, a range of its kets) on the lanes of the workgroup or
+// (WAVE) of one wave, whose bra rows are the wave's own LDS region.
+template <class E, int MODE, int FP32, bool WAVE = false>
 __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, const double* t64, const float* t32) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
+    constexpr int NT = WAVE ? 64 : E::WGS;   // lanes of the task
+    const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     extern __shared__ __align__(16) double lds[];
     const int4 task = a.tasks[ti];
     const int r = task.x;
@@ -364,11 +380,12 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         cb = wc * a.win;
         db = wd == wc ? cb : wd * a.win - half;
     }
-    double* FI = lds + LdsLayout<E, FP32>::ROWS;
+    // a wave's region is (NA + NB) a.rs doubles (a.rs >= RS for every molecule of a batch)
+    double* FI = lds + LdsLayout<E, FP32>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB) * a.rs : 0);
     double* FJ = FI + NA * RS;
     if constexpr (MODE == 0) {
-        for (int i = threadIdx.x; i < (NA + NB) * RS; i += E::WGS) FI[i] = 0.0;
-        __syncthreads();
+        for (int i = tid; i < (NA + NB) * RS; i += NT) FI[i] = 0.0;
+        task_sync<WAVE>();
     }
     double dab[NAB], jab[NAB];
 #pragma unroll
@@ -387,7 +404,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         // short task (few kets) still fills NA times as many lanes, and the
         // lanes of a wave share k
         const int nq = send - s0;
-        for (int it = (int)threadIdx.x; it < NA * nq; it += E::WGS) {
+        for (int it = tid; it < NA * nq; it += NT) {
             const int k = it / nq, s = s0 + it % nq;
             const int4 kb = a.kbf[s];
             const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
@@ -399,7 +416,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             if (k == 0) ++n64;
         }
     }
-    for (int s = s0 + (int)threadIdx.x; s < send && !E::PASSES; s += E::WGS) {
+    for (int s = s0 + tid; s < send && !E::PASSES; s += NT) {
         const int4 kb = a.kbf[s];   // ket's first basis functions and shells
         const int fc = kb.x, fd = kb.y;
         const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
@@ -443,8 +460,8 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         }
     }
     if constexpr (MODE == 0) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < (NA + NB) * RS; i += E::WGS) {
+        task_sync<WAVE>();
+        for (int i = tid; i < (NA + NB) * RS; i += NT) {
             const double v = FI[i];
             if (v != 0.0) {
                 const int row = i < NA * RS ? bra.bfa + i / RS : bra.bfb + (i - NA * RS) / RS;
@@ -498,6 +515,31 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
     }
 }
 
+// Persistent launch with one task per wave: each wave of a resident
+// workgroup takes its own queue entries (same queues and order as
+// k_class_persist) and digests into its own LDS bra rows, so short tasks
+// (small molecules of a batch) occupy 64 lanes instead of a workgroup.  The
+// Boys rows are shared by the workgroup's waves.
+template <class E, int MODE, int FP32>
+__global__ __launch_bounds__(E::WGS) void k_class_wave(const ClassArgs a) {
+    extern __shared__ __align__(16) double lds[];
+    double* t64 = lds;
+    float* t32 = reinterpret_cast<float*>(lds);
+    load_boys_lds<E, FP32>(a, t64, t32);
+    const int x0 = blockIdx.x & 7;
+    for (int q = 0; q < 8;) {
+        const int x = (x0 + q) & 7;
+        int k = 0;
+        if ((threadIdx.x & 63) == 0) k = (int)atomicAdd(a.work + x, 1ull);
+        k = __shfl(k, 0, 64);
+        if (k >= a.qlen) {
+            ++q;
+            continue;
+        }
+        class_task<E, MODE, FP32, true>(a, 8 * k + x, t64, t32);
+    }
+}
+
 // Schwarz bound of every pair of one pair class: Q = sqrt(max (mn|mn)) with
 // the component normalisation s_m s_n applied (always FP64).
 // 1/sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!) of Cartesian component c of shell l.
@@ -540,8 +582,17 @@ template <class E>
 struct ClassKernelsOne {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
-    // variant = 4 persistent + 2 mode + fp32
+    // variant = 4 persistent + 2 mode + fp32; bit 4: one task per wave (persistent)
     static const void* get(int variant) {
+        if (variant & 16) {
+            if constexpr (kOnlyFp64Global) {
+                return (variant & 2) ? (const void*)k_class_wave<E, 1, 0> : (const void*)k_class_wave<E, 0, 0>;
+            } else {
+                static const void* w[4] = {(const void*)k_class_wave<E, 0, 0>, (const void*)k_class_wave<E, 0, 1>,
+                                           (const void*)k_class_wave<E, 1, 0>, (const void*)k_class_wave<E, 1, 1>};
+                return w[variant & 3];
+            }
+        }
         if constexpr (kOnlyFp64Global) {
             static const void* t[4] = {(const void*)k_class<E, 0, 0>, (const void*)k_class<E, 1, 0>,
                                        (const void*)k_class_persist<E, 0, 0>, (const void*)k_class_persist<E, 1, 0>};
@@ -557,14 +608,14 @@ struct ClassKernelsOne {
 };
 
 // variant bit 3: the class's alternative workgroup size (EA; the same kernels
-// when EA has E's size).
+// when EA has E's size); bit 4: one task per wave.
 template <class E, class EA>
 struct ClassKernels {
     static const void* get(int variant) {
         if constexpr (EA::WGS != E::WGS) {
-            if (variant & 8) return ClassKernelsOne<EA>::get(variant & 7);
+            if (variant & 8) return ClassKernelsOne<EA>::get(variant & 23);
         }
-        return ClassKernelsOne<E>::get(variant & 7);
+        return ClassKernelsOne<E>::get(variant & 23);
     }
 };
 

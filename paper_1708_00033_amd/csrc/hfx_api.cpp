@@ -322,9 +322,15 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.ntask = (int)tasks.size();
     if (P.ntask == 0) return HFX_OK;
     P.persist = c->tune_persist[P.cid] > 0;
+    // one task per wave: each wave of the workgroup needs its own bra rows
+    P.wave = 0;
+    if (c->tune_persist[P.cid] == 2) {
+        P.wave = WGS / 64;
+        if (P.lds(false) > 160 * 1024 - 256) P.wave = 0;   // does not fit: one task per workgroup
+    }
     for (int mx = 0; mx < (P.fp64_only ? 1 : 2); ++mx) {
         const size_t lds = P.lds(mx != 0);
-        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.mode, mx, lds);
+        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, lds);
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
@@ -381,7 +387,7 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     if (task_quartets != 0 && (task_quartets < 256 || task_quartets % 256 != 0 || task_quartets > (1 << 24)))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be 0 or a multiple of 256 in [256, 2^24]");
     if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
-    if (persistent < 0 || persistent > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0 or 1");
+    if (persistent < 0 || persistent > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0, 1 or 2");
     if (digest < -1 || digest > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0 or 1");
     for (int k = 0; k < 21; ++k)
         if (cid == -1 || cid == k) {
@@ -937,7 +943,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[6] = p.launches;
     info[7] = p.mode;
     info[8] = hfx_class_wgs(p.cid, p.alt);
-    info[9] = p.persist ? 1 : 0;
+    info[9] = p.persist ? (p.wave ? 2 : 1) : 0;
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
     if (ms) *ms = p.ms;
     return HFX_OK;
@@ -1007,13 +1013,14 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         constexpr int kMaxGroups = 1 << 20;
         auto launch = [&](ClassArgs& x, int fp32) -> hfx_status {
             if (P.persist) {
-                HIPCK(hfx_launch_class(cid, P.alt, P.mode, fp32, P.nblocks[fp32], P.lds(fp32 != 0), st, &x));
+                HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, fp32, P.nblocks[fp32], P.lds(fp32 != 0), st,
+                                       &x));
                 return HFX_OK;
             }
             for (int off = 0; off < P.ntask; off += kMaxGroups) {
                 x.task_off = off;
-                HIPCK(hfx_launch_class(cid, P.alt, P.mode, fp32, std::min(kMaxGroups, P.ntask - off), P.lds(fp32 != 0),
-                                       st, &x));
+                HIPCK(hfx_launch_class(cid, P.alt, 0, P.mode, fp32, std::min(kMaxGroups, P.ntask - off),
+                                       P.lds(fp32 != 0), st, &x));
             }
             return HFX_OK;
         };

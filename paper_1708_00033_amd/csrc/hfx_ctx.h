@@ -46,8 +46,10 @@ struct SubPlan {
     double ms = 0.0;
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
-    size_t lds(bool mx) const { return (mode == 0 ? lds_bytes : 0) + lds_tab[mx ? 1 : 0]; }
+    // LDS of a workgroup: bra rows (one set per wave with one task per wave) and Boys rows
+    size_t lds(bool mx) const { return (mode == 0 ? lds_bytes * (wave ? wave : 1) : 0) + lds_tab[mx ? 1 : 0]; }
     bool persist = false;     // persistent launch through per-XCD work counters
+    int wave = 0;             // > 0: one task per wave (persistent), this many waves per workgroup
     int alt = 0;              // 1: the class's alternative workgroup size
     int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / FP32 kernel
 };
@@ -174,9 +176,9 @@ hipError_t hfx_pad_blocks(const double* src, const long long* moff, const int* d
                           double* dst, hipStream_t st);
 hipError_t hfx_pad_rest(const int* dim, int nmol, int NP, double pad, double* dst, hipStream_t st);
 // eri_dispatch.hip
-hipError_t hfx_launch_class(int cid, int alt, int mode, int mixed, int nblocks, size_t lds_bytes,
+hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int nblocks, size_t lds_bytes,
                             hipStream_t stream, const ClassArgs* args);
-int hfx_class_resident_blocks(int cid, int alt, int mode, int mixed, size_t lds_bytes);
+int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes);
 int hfx_class_wgs(int cid, int alt);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);

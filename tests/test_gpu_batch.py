@@ -33,9 +33,11 @@ def test_batch_build_equals_individual_builds():
     for m, D in zip(mols, Ds):
         F, _ = hfx.Context().load(m).build_fock(D)
         refs.append(F)
-    for digest, persistent in ((0, 0), (1, 0), (0, 1)):
+    for digest, persistent in ((0, 0), (1, 0), (0, 1), (0, 2), (1, 2)):
         bctx = hfx.Context(digest=digest).load_batch(mols)
         bctx.set_class_tuning(-1, 2048, 1, persistent)
+        if persistent == 2 and digest == 0:   # one task per wave, LDS rows per wave, for some classes
+            assert any(p["persistent"] == 2 for p in bctx.plans())
         nbf, nocc, off, tot = bctx.layout
         assert list(nbf) == [m.nbf for m in mols]
         assert tot == sum(m.nbf ** 2 for m in mols)
@@ -64,7 +66,7 @@ def test_batch_against_oracle_and_mixed():
         assert np.abs(blk - (T + V + 2 * J - K)).max() < 1e-6
 
 
-@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("persistent", [0, 1, 2])
 def test_graph_replay_matches_eager(persistent):
     """Replays of a captured build (persistent launches reset their work
     counters with a fill kernel inside the graph) equal the eager build."""

@@ -118,7 +118,7 @@ def test_mixed_precision_dimer(dimer):
     assert abs(r["energy"] - r64["energy"]) < 1e-6
 
 
-@pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1)])
+@pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1), (2, -1)])
 def test_mixed_precision_16_waters(persistent, digest):
     """A mixed build runs an FP64 kernel before each bra's split and an FP32
     kernel from it on; a 16-water cluster puts a large share in FP32.  Both
@@ -329,7 +329,7 @@ def test_launch_chunks_cover_every_task():
 
 
 def test_scheduling_knobs_do_not_change_results():
-    """Task size and XCD striping move work between workgroups only."""
+    """Task size, XCD striping and the launch form move work between workgroups (or waves) only."""
     import torch
     m = W.water_cluster(16, 77)
     ctx = _hfx().Context().load(m)
@@ -340,7 +340,8 @@ def test_scheduling_knobs_do_not_change_results():
     ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, ref.data_ptr(), s)
     out = torch.empty_like(D)
     for tq, st, pe, dg in [(8192, 1, 0, -1), (1024, 1, 0, -1), (32768, 0, 0, -1), (2048, 1, 1, -1),
-                           (256, 0, 1, -1), (32768, 1, 1, -1), (8192, 0, 0, 1), (2048, 1, 1, 1)]:
+                           (256, 0, 1, -1), (32768, 1, 1, -1), (8192, 0, 0, 1), (2048, 1, 1, 1),
+                           (2048, 1, 2, -1), (32768, 0, 2, -1), (8192, 1, 2, 1)]:
         ctx.set_class_tuning(-1, tq, st, pe, dg)
         ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
         torch.cuda.synchronize()
