@@ -373,16 +373,20 @@ def main():
     flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    kname = (f"{'k_class_persist' if dom['persistent'] else 'k_class'}<Eval{dom['cls']}, {dom['mode']}, 0> "
-             f"grid {dom['blocks'] * dom['wgs']}")
+    form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave"}[dom["persistent"]]
+    import gen_eri   # on the path after class_flop_model(); "A": the class's alternative workgroup size
+    alt = "A" if dom["wgs"] != gen_eri.wg_size(dom["cls"]) else ""
+    kname = f"{form}<Eval{dom['cls']}{alt}, {dom['mode']}, 0> grid {dom['blocks'] * dom['wgs']}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
     prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if os.path.exists(prof):
         with open(prof) as fh:
             pj = json.load(fh)
-        if pj.get("source_hash") == source_hash() and pj.get("kernel") == kname:
-            traffic = pj.get("hbm_bytes_per_launch")
+        # per profiled launch form of the dominant class: {kernel: {"hbm_bytes_per_launch": ...}}
+        kernels = pj.get("kernels", {pj.get("kernel"): pj})
+        if pj.get("source_hash") == source_hash() and kname in kernels:
+            traffic = kernels[kname].get("hbm_bytes_per_launch")
     res = {
         "metric": "screened ERI quartets/s + Fock-build time, FP64 vs mixed @1e-6 Eh, 1 GPU",
         "value": value,
