@@ -192,8 +192,10 @@ def batched_bench(args, log):
 
 def large_bench(args, log):
     """512 waters (9728 basis functions), Schwarz tau 1e-11: one GPU's share
-    (bra pairs r with r mod G = 0) of a G-GPU build, FP64 and mixed, from a
-    rank-2560 projector density; with --large-scf also full SCF."""
+    (bra pairs r with r mod G = 0) of a G-GPU build, FP64, mixed with every
+    class's FP32 kernel, and mixed with the FP32 kernel only for the classes
+    it ran faster, from a rank-2560 projector density; with --large-scf also
+    full SCF."""
     import numpy as np
     import torch
     import workloads as W
@@ -217,8 +219,15 @@ def large_bench(args, log):
            "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
            "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load, "shards": G,
            "digest_modes": sorted(set(p["mode"] for p in ctx.plans()))}
+    Gtn = torch.empty_like(D)
+    class_ms = {}
     for prec, Go, tag in (() if args.large_no_builds else
-                          ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"))):
+                          ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"),
+                           (hfx.HFX_PREC_MIXED, Gtn, "mixed_tuned"))):
+        if tag == "mixed_tuned":
+            # per class, the FP32 kernel only where the all-FP32 build ran the class faster
+            for k in range(21):
+                ctx.set_class_precision(k, int(class_ms["mixed"][k] < class_ms["fp64"][k]))
         ctx.configure(precision=prec)
         ctx.kernel_timing(True)
         torch.cuda.synchronize()
@@ -228,6 +237,7 @@ def large_bench(args, log):
         dt = time.perf_counter() - t
         ms, n = ctx.kernel_times()
         ctx.kernel_timing(False)
+        class_ms[tag] = ms
         q = int(st.quartets_fp64 + st.quartets_fp32)
         if G == 1 and q != quartets:
             raise RuntimeError(f"evaluated {q} quartets, planned {quartets}")
@@ -239,6 +249,12 @@ def large_bench(args, log):
         out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
         out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(0.5 * torch.sum(D * (Gmx - G64)).item())
         out["mixed"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed"]["share_build_s"]
+        out["mixed_tuned"]["max_abs_dG_vs_fp64"] = (Gtn - G64).abs().max().item()
+        out["mixed_tuned"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed_tuned"]["share_build_s"]
+        out["mixed_tuned"]["fp32_classes"] = [hfx.CLASS_NAMES[k] for k in range(21)
+                                              if class_ms["mixed"][k] < class_ms["fp64"][k]]
+        for k in range(21):
+            ctx.set_class_precision(k, 1)
     scf_runs = {"none": (), "fp64": ("fp64",), "mixed": ("mixed",), "both": ("fp64", "mixed")}[args.large_scf]
     for tag in scf_runs:
         ctx.configure(precision=hfx.HFX_PREC_FP64 if tag == "fp64" else hfx.HFX_PREC_MIXED, log_level=1)
