@@ -398,6 +398,8 @@ class Context:
 
     def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1, persistent: int = 0,
                          digest: int = -1):
+        """hfx_set_class_tuning: persistent 0 = one workgroup per task, 1 = resident grid with per-XCD
+        queues, 2 = resident grid with one task per wave."""
         self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe, persistent, digest))
 
     def set_class_precision(self, cls: int, fp32: int):
