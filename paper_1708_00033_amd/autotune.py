@@ -2,8 +2,9 @@
 
 For every quartet class the library exposes four scheduling knobs
 (``hfx_set_class_tuning``): quartets per workgroup task, XCD striping of
-long ket prefixes, the launch form (one workgroup per task, or a persistent
-resident grid fed by per-XCD atomic work counters) and the digestion (bra
+long ket prefixes, the launch form (one workgroup per task, a persistent
+resident grid fed by per-XCD atomic work counters, or such a grid with one
+task per wave for short tasks) and the digestion (bra
 rows staged in LDS, or global atomics).  Results do not depend on them.  The tuner times each
 candidate setting for all classes at once with the library's per-launch HIP
 events, keeps each class's fastest setting, applies it and returns the table
