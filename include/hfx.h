@@ -109,7 +109,18 @@ typedef struct {
 hfx_status hfx_default_options(hfx_options *opt);
 hfx_status hfx_default_scf_options(hfx_scf_options *opt);
 
-/* Create a context on opt->device.  *out owns all device memory it allocates. */
+/* Resources of the quartet-class kernels, read from the code objects'
+ * metadata (no launch): out[21*3] = per class {largest per-lane scratch
+ * (private segment) in bytes over its kernel variants, largest register
+ * count, the scratch budget per lane}.  hfx_create refuses (HFX_ERR_DEVICE)
+ * when a class kernel needs more scratch than the budget: the runtime
+ * reserves scratch for every wave slot, and a kernel far above the budget
+ * can make its queue fail with out-of-resources at launch. */
+hfx_status hfx_kernel_resources(int device, long long *out);
+
+/* Create a context on opt->device.  *out owns all device memory it allocates.
+ * HFX_ERR_DEVICE: no such device, or a class kernel exceeds the scratch
+ * budget (hfx_kernel_resources). */
 hfx_status hfx_create(const hfx_options *opt, hfx_ctx **out);
 
 /* Load geometry and basis (section 4.1 shells).  Z[natom] nuclear charges,
@@ -161,8 +172,10 @@ hfx_status hfx_build_2e_dev(hfx_ctx *ctx, const double *dD, double cj, double ck
 
 /* Capture one Fock build dF = F(dD) on a non-null stream into a HIP graph
  * (an eager build runs first), and replay it.  The graph keeps dD, dF and
- * the context's buffers; re-capture after hfx_load, hfx_configure or
- * hfx_set_class_tuning. */
+ * the context's buffers.  hfx_load, hfx_set_class_tuning, and any change of
+ * precision, fp32_tau, digestion or task size (hfx_configure,
+ * hfx_set_class_precision) discard the graph: hfx_graph_launch then returns
+ * HFX_ERR_STATE until the next capture. */
 hfx_status hfx_graph_capture(hfx_ctx *ctx, const double *dD, double *dF, void *stream);
 hfx_status hfx_graph_launch(hfx_ctx *ctx, void *stream);
 

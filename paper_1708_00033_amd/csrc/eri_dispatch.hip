@@ -53,6 +53,25 @@ extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, i
 }
 
 
+// Largest per-lane private segment (scratch) in bytes and largest register
+// count over every kernel variant of class cid (launch form, digestion,
+// precision, workgroup size), read from the code object's metadata without a
+// launch.
+extern "C" hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs) {
+    long long sc = 0;
+    int rg = 0;
+    for (int v = 0; v < 32; ++v) {
+        hipFuncAttributes fa;
+        const hipError_t e = hipFuncGetAttributes(&fa, kClassLookup[cid](v));
+        if (e != hipSuccess) return e;
+        sc = fa.localSizeBytes > (size_t)sc ? (long long)fa.localSizeBytes : sc;
+        rg = fa.numRegs > rg ? fa.numRegs : rg;
+    }
+    *scratch_bytes = sc;
+    *regs = rg;
+    return hipSuccess;
+}
+
 extern "C" hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim,
                                          const double* boys, double* Q, hipStream_t stream) {
     if (npairs <= 0) return hipSuccess;

@@ -54,6 +54,17 @@ static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}}
 
 static hfx_status replan(hfx_ctx* c);
 
+// A captured build replays the launch arguments (plans, task buffers,
+// precision split) of the moment it was captured: drop it whenever those
+// change, so that hfx_graph_launch reports HFX_ERR_STATE instead of replaying
+// freed buffers or a stale precision choice.
+static void drop_graph(hfx_ctx* c) {
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+}
+
 // ---- options -----------------------------------------------------------------------
 
 extern "C" hfx_status hfx_default_options(hfx_options* o) {
@@ -100,10 +111,7 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
 static void release_system(hfx_ctx* c) {
     hfx_guess_release(c);
     dfree(c->d_work);
-    if (c->graph_exec) {
-        (void)hipGraphExecDestroy(c->graph_exec);
-        c->graph_exec = nullptr;
-    }
+    drop_graph(c);
     dfree(c->d_prim);
     for (int k = 0; k < 6; ++k) {
         dfree(c->d_pairs[k]);
@@ -146,6 +154,44 @@ static void release_system(hfx_ctx* c) {
     c->loaded = false;
 }
 
+// Per-lane scratch (private segment) that a class kernel may need.  The
+// runtime reserves scratch for every wave slot the kernel can occupy; a
+// (dd|dd) kernel variant with 25,200 bytes per lane made a queue fail with
+// HSA_STATUS_ERROR_OUT_OF_RESOURCES, while every current variant needs under
+// 8 KiB.  Checked once per process from the code objects' metadata.
+constexpr long long kScratchBudget = 16384;
+
+struct KernelResources {
+    hipError_t err = hipSuccess;
+    long long scratch[21] = {0};
+    int regs[21] = {0};
+};
+
+static const KernelResources& kernel_resources() {
+    static const KernelResources r = [] {
+        KernelResources k;
+        for (int cid = 0; cid < 21 && k.err == hipSuccess; ++cid)
+            k.err = hfx_class_kernel_resources(cid, &k.scratch[cid], &k.regs[cid]);
+        return k;
+    }();
+    return r;
+}
+
+extern "C" hfx_status hfx_kernel_resources(int device, long long* out) {
+    if (!out) return HFX_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HFX_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return HFX_ERR_DEVICE;
+    const KernelResources& r = kernel_resources();
+    if (r.err != hipSuccess) return HFX_ERR_DEVICE;
+    for (int k = 0; k < 21; ++k) {
+        out[3 * k] = r.scratch[k];
+        out[3 * k + 1] = r.regs[k];
+        out[3 * k + 2] = kScratchBudget;
+    }
+    return HFX_OK;
+}
+
 extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
     if (!out) return HFX_ERR_INVALID_ARG;
     hfx_ctx* c = new (std::nothrow) hfx_ctx();
@@ -159,6 +205,12 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         return HFX_ERR_DEVICE;
     }
     if (hipSetDevice(c->opt.device) != hipSuccess) { delete c; return HFX_ERR_DEVICE; }
+    {
+        const KernelResources& r = kernel_resources();
+        bool ok = r.err == hipSuccess;
+        for (int k = 0; k < 21 && ok; ++k) ok = r.scratch[k] <= kScratchBudget;
+        if (!ok) { delete c; return HFX_ERR_DEVICE; }
+    }
     std::vector<double> tab((size_t)BOYS_NL * BOYS_NT * BOYS_ROW);
     hfx_boys_table(tab.data());
     std::vector<float> tab32(tab.begin(), tab.end());
@@ -203,6 +255,7 @@ extern "C" hfx_status hfx_configure(hfx_ctx* c, const hfx_options* o) {
     if (o->device != c->opt.device || o->schwarz_tau != c->opt.schwarz_tau)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "device and schwarz_tau cannot change after hfx_create");
     const bool new_plan = o->task_quartets != c->opt.task_quartets || o->digest != c->opt.digest;
+    if (new_plan || o->precision != c->opt.precision || o->fp32_tau != c->opt.fp32_tau) drop_graph(c);
     c->opt = *o;
     if (new_plan && c->loaded) {
         HIPCK(hipSetDevice(c->opt.device));
@@ -350,6 +403,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
 // (Re)build every launch plan from the stored Q-sorted lists with the
 // current per-class tuning.
 static hfx_status replan(hfx_ctx* c) {
+    drop_graph(c);
     dfree(c->d_work);
     for (auto& p : c->plans) {
         dfree(p.d_split);
@@ -406,7 +460,10 @@ extern "C" hfx_status hfx_set_class_precision(hfx_ctx* c, int cid, int fp32) {
     if (cid < -1 || cid >= 21) return hfx_fail(c, HFX_ERR_INVALID_ARG, "class index out of range");
     if (fp32 < 0 || fp32 > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "fp32 must be 0 or 1");
     for (int k = 0; k < 21; ++k)
-        if (cid == -1 || cid == k) c->tune_fp32[k] = fp32;
+        if (cid == -1 || cid == k) {
+            if (c->tune_fp32[k] != fp32) drop_graph(c);
+            c->tune_fp32[k] = fp32;
+        }
     return HFX_OK;
 }
 
@@ -1106,10 +1163,7 @@ extern "C" hfx_status hfx_graph_capture(hfx_ctx* c, const double* dD, double* dF
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_graph_capture: nothing loaded");
     HIPCK(hipSetDevice(c->opt.device));
     hipStream_t st = (hipStream_t)stream;
-    if (c->graph_exec) {
-        (void)hipGraphExecDestroy(c->graph_exec);
-        c->graph_exec = nullptr;
-    }
+    drop_graph(c);
     const bool timing = c->timing;
     c->timing = false;
     hfx_status s = hfx_build_internal(c, dD, 2.0, 1.0, c->d_H, dF, st, nullptr, 0, 1);

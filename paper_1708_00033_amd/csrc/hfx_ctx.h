@@ -180,6 +180,7 @@ hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int
                             hipStream_t stream, const ClassArgs* args);
 int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes);
 int hfx_class_wgs(int cid, int alt);
+hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);
 }

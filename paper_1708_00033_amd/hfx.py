@@ -13,8 +13,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# HFX_LIB: another build of the same library (e.g. a tuning experiment)
-LIB_PATH = os.environ.get("HFX_LIB") or os.path.join(_HERE, "libhfx.so")
+LIB_PATH = os.path.join(_HERE, "libhfx.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1708_00033_amd.build` "
@@ -128,6 +127,7 @@ _sigs = {
     "hfx_guess_adam": ([C.c_void_p, C.c_double, C.c_void_p], C.c_int),
     "hfx_guess_apply": ([_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)], C.c_int),
     "hfx_guess_last_error": ([C.c_void_p], C.c_char_p),
+    "hfx_kernel_resources": ([C.c_int, C.POINTER(C.c_longlong)], C.c_int),
     "hfx_last_error": ([_ctx_p], C.c_char_p),
     "hfx_destroy": ([_ctx_p], None),
 }
@@ -138,6 +138,16 @@ for _name, (_args, _res) in _sigs.items():
     globals()[_name] = _f
 
 EXPORTED = sorted(_sigs)
+
+
+def kernel_resources(device: int = 0) -> np.ndarray:
+    """Per class (21 x 3): largest per-lane scratch bytes, largest register
+    count over the class's kernel variants, and the scratch budget."""
+    a = np.zeros(21 * 3, dtype=np.int64)
+    st = hfx_kernel_resources(device, a.ctypes.data_as(C.POINTER(C.c_longlong)))
+    if st != HFX_OK:
+        raise HfxError(st, "hfx_kernel_resources failed")
+    return a.reshape(21, 3)
 
 
 class HfxError(RuntimeError):

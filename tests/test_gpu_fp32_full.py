@@ -1,0 +1,271 @@
+"""GPU parity of the FP32 class kernels integral by integral, of the
+full-size 64-water build in the benchmark's launch configuration, and of the
+context's state rules (kernel resources, captured graphs)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "cluster64_oracle_jk.json")
+
+# FP32 evaluation of one integral: the Boys function (5 Taylor terms) and the
+# recurrences run in FP32 (unit roundoff 6e-8); the Obara-Saika / Head-Gordon-
+# Pople steps of an L <= 8 class lose at most a few hundred ulps to
+# cancellation, so a widened FP32 integral is within 2e-5 of its value relative
+# to the largest integral of its column.  The tolerance below is that bound.
+FP32_RTOL = 2e-5
+
+
+def _hfx():
+    from paper_1708_00033_amd import hfx
+    return hfx
+
+
+@pytest.fixture(scope="module")
+def four_waters():
+    import oracle
+    m = W.water_cluster(4, 41)
+    return m, oracle.Basis(m)
+
+
+def test_kernel_resources_within_budget():
+    """Every class kernel's scratch per lane is read from the code objects
+    (no launch) and stays inside the budget that hfx_create enforces."""
+    r = _hfx().kernel_resources(0)
+    print("per class: scratch bytes/lane, registers:", [tuple(x[:2]) for x in r])
+    assert (r[:, 0] <= r[:, 2]).all()
+    assert (r[:, 1] > 0).all()
+
+
+def _unit_density(n, lam, sig):
+    D = np.zeros((n, n))
+    D[lam, sig] = D[sig, lam] = 1.0
+    return D
+
+
+def _all_fp32_context(mol, **kw):
+    """A mixed context with the FP32 threshold so high that every quartet of
+    the classes built in FP32 goes to the FP32 kernel."""
+    hfx = _hfx()
+    ctx = hfx.Context(precision=hfx.HFX_PREC_MIXED, fp32_tau=1e300, **kw).load(mol)
+    ctx.set_class_precision(-1, 1)
+    return ctx
+
+
+def _fp64_only_quartets(ctx):
+    """Quartets of the classes that have no FP32 kernel ((dd|dp), (dd|dd))."""
+    counts = ctx.class_counts()
+    return int(counts[19, 0] + counts[20, 0])
+
+
+def test_fp32_kernels_integral_by_integral(four_waters):
+    """With D = e_ls + e_sl, J_mn = 2 (mn|ls) and K_mn = (ml|ns) + (ms|nl):
+    single integrals of every class, evaluated by the FP32 kernels, against
+    the oracle's FP64 values."""
+    import torch
+    m, B = four_waters
+    hfx = _hfx()
+    ctx = _all_fp32_context(m)
+    n = m.nbf
+    bf, ls = B.shell_bf, B.shell_l
+    s = torch.cuda.current_stream().cuda_stream
+    # (lambda, sigma) in s, p and d shells of different waters
+    picks = [(bf[0], bf[10]), (bf[3] + 1, bf[1]), (bf[5] + 2, bf[13] + 1), (bf[25] + 4, bf[35] + 5),
+             (bf[7], bf[7]), (bf[15], bf[34])]
+    assert {int(ls[k]) for k in (3, 5, 13, 25, 35, 15, 34)} == {1, 2}
+    for lam, sig in picks:
+        D = _unit_density(n, lam, sig)
+        dD = torch.tensor(D, device="cuda")
+        out = {}
+        for name, cj, ck in (("J", 1.0, 0.0), ("K", 0.0, -1.0)):
+            G = torch.empty_like(dD)
+            st = ctx.build_2e_dev(dD.data_ptr(), cj, ck, G.data_ptr(), s, stats=True)
+            torch.cuda.synchronize()
+            assert st.quartets_fp32 > 0
+            assert st.quartets_fp64 == _fp64_only_quartets(ctx)
+            out[name] = G.cpu().numpy()
+        J, K, _ = B.jk(D, 1e-10)
+        for name, ref in (("J", J), ("K", K)):
+            err = np.abs(out[name] - ref)
+            scale = np.abs(ref).max()
+            assert (err <= FP32_RTOL * scale).all(), (lam, sig, name, err.max(), scale)
+            # and far from the FP64 kernels' agreement: the FP32 path really ran
+        assert np.abs(out["J"] - J).max() > 1e-12 * np.abs(J).max()
+
+
+def test_fp32_kernels_random_density(four_waters):
+    """All eligible quartets in FP32, a random density: F within FP32_RTOL of
+    the oracle's, relative to max |F - H|."""
+    m, B = four_waters
+    ctx = _all_fp32_context(m)
+    D = W.random_symmetric(m.nbf, 17, 0.2)
+    F, st = ctx.build_fock(D)
+    S, T, V, _ = B.one_electron()
+    J, K, ost = B.jk(D, 1e-10)
+    G = 2 * J - K
+    assert st.quartets_fp32 + st.quartets_fp64 == ost[0]
+    assert st.quartets_fp64 == _fp64_only_quartets(ctx)
+    assert np.abs(F - (T + V + G)).max() <= FP32_RTOL * np.abs(G).max()
+
+
+@pytest.mark.parametrize("persistent", [0, 2])
+def test_fp32_kernels_batched(persistent):
+    """A batch of two clusters, every eligible quartet in FP32, static and
+    per-wave launch forms: each molecule's F against the oracle."""
+    import oracle
+    mols = [W.water_cluster(3, 51), W.water_cluster(2, 52)]
+    hfx = _hfx()
+    ctx = hfx.Context(precision=hfx.HFX_PREC_MIXED, fp32_tau=1e300).load_batch(mols)
+    ctx.set_class_precision(-1, 1)
+    ctx.set_class_tuning(-1, 2048, 1, persistent, -1)
+    nbf, _, off, tot = ctx.layout
+    Ds = [W.random_symmetric(int(n), 60 + i, 0.2) for i, n in enumerate(nbf)]
+    F, st = ctx.build_fock(np.concatenate([d.ravel() for d in Ds]))
+    assert st.quartets_fp32 > 0
+    for i, mol in enumerate(mols):
+        B = oracle.Basis(mol)
+        S, T, V, _ = B.one_electron()
+        J, K, _ = B.jk(Ds[i], 1e-10)
+        n = int(nbf[i])
+        Fi = F[int(off[i]):int(off[i]) + n * n].reshape(n, n)
+        assert np.abs(Fi - (T + V + 2 * J - K)).max() <= FP32_RTOL * np.abs(2 * J - K).max(), i
+
+
+def test_fp32_kernels_windowed_112_waters():
+    """Above 2048 basis functions (column-windowed LDS digestion), all
+    eligible quartets in FP32: J and K against the FP64 build and sampled
+    blocks against the oracle."""
+    import torch
+    import oracle
+    m = W.water_cluster(112, 5)
+    D = W.random_orthonormal_density(m.nbf, m.nocc, 23)
+    dD = torch.tensor(D, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for tag, ctx in (("fp64", _hfx().Context().load(m)), ("fp32", _all_fp32_context(m))):
+        J, K = torch.empty_like(dD), torch.empty_like(dD)
+        ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s)
+        st = ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s, stats=True)
+        torch.cuda.synchronize()
+        res[tag] = (J.cpu().numpy(), K.cpu().numpy(), st)
+    (J64, K64, _), (J32, K32, st32) = res["fp64"], res["fp32"]
+    assert st32.quartets_fp32 > 0.9 * (st32.quartets_fp32 + st32.quartets_fp64)
+    assert np.abs(J32 - J64).max() <= FP32_RTOL * np.abs(J64).max()
+    assert np.abs(K32 - K64).max() <= FP32_RTOL * np.abs(K64).max()
+    B = oracle.Basis(m)
+    bf = B.shell_bf
+    for a, b in [(5, 5), (700, 1115)]:
+        Jb, Kb = B.jk_block(a, b, D, 1e-10)
+        na, nb = Jb.shape
+        assert np.abs(J32[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Jb).max() <= FP32_RTOL * np.abs(J64).max()
+        assert np.abs(K32[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Kb).max() <= FP32_RTOL * np.abs(K64).max()
+
+
+def test_graph_dropped_when_plans_or_precision_change(four_waters):
+    """A captured build replays the launch arguments of its capture: any
+    re-plan or precision change discards it (HFX_ERR_STATE on launch, nothing
+    replayed) until the next capture."""
+    import torch
+    m, _ = four_waters
+    hfx = _hfx()
+    ctx = hfx.Context().load(m)
+    D = torch.tensor(W.random_symmetric(m.nbf, 3, 0.2), device="cuda")
+    F = torch.empty_like(D)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+
+    def expect_dropped():
+        with pytest.raises(hfx.HfxError) as e:
+            ctx.graph_launch(sp)
+        assert e.value.status == hfx.HFX_ERR_STATE
+
+    changes = [lambda: ctx.set_class_tuning(-1, 512, 0, 1),
+               lambda: ctx.set_class_precision(3, 0),
+               lambda: ctx.configure(precision=hfx.HFX_PREC_MIXED),
+               lambda: ctx.configure(fp32_tau=1e-6),
+               lambda: ctx.configure(task_quartets=1024),
+               lambda: ctx.load(m)]
+    for change in changes:
+        ctx.graph_capture(D.data_ptr(), F.data_ptr(), sp)
+        ctx.graph_launch(sp)
+        stream.synchronize()
+        change()
+        expect_dropped()
+    ctx.graph_capture(D.data_ptr(), F.data_ptr(), sp)
+    F.zero_()
+    ctx.graph_launch(sp)
+    stream.synchronize()
+    ref = torch.empty_like(D)
+    ctx.build_fock_dev(D.data_ptr(), ref.data_ptr(), sp)
+    stream.synchronize()
+    assert (F - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+
+
+@pytest.fixture(scope="module")
+def cluster64_golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def _check_against_golden(g, J, K, D, e_tol, blk_tol, row_tol):
+    e2 = 2 * np.sum(D * J) - np.sum(D * K)
+    e2_ref = 2 * g["tr_DJ"] - g["tr_DK"]
+    assert abs(e2 - e2_ref) < e_tol, (e2, e2_ref)
+    assert np.abs(J.sum(1) - np.array(g["row_sums_J"])).max() < row_tol
+    assert np.abs(K.sum(1) - np.array(g["row_sums_K"])).max() < row_tol
+    bf = np.cumsum([0] + [W.NCART[s.l] for s in W.cluster64_config().shells])
+    for blk in g["blocks"]:
+        a, b = blk["a"], blk["b"]
+        Jb, Kb = np.array(blk["J"]), np.array(blk["K"])
+        na, nb = Jb.shape
+        assert np.abs(J[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Jb).max() < blk_tol, blk["pair_class"]
+        assert np.abs(K[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Kb).max() < blk_tol, blk["pair_class"]
+
+
+def test_cluster64_full_size_in_benchmark_configuration(cluster64_golden):
+    """The 64-water build (1216 basis functions, 3.0e9 quartets) in the
+    benchmark's launch configuration -- the per-class autotuner's choice of
+    task size, striping, launch form (persistent / per-wave) and digestion,
+    as the benchmark runs it -- against the oracle's full build at a seeded
+    projector density: the two-electron energy tr(D (2J - K)) within 1e-8 Eh,
+    every row sum of J and K, and one shell block per pair class; the mixed
+    build (every class's FP32 kernel on) within 1e-6 Eh."""
+    import torch
+    from paper_1708_00033_amd import autotune
+    g = cluster64_golden
+    m = W.cluster64_config()
+    hfx = _hfx()
+    D = W.random_orthonormal_density(m.nbf, m.nocc, 21)
+    dD = torch.tensor(D, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    ctx = hfx.Context().load(m)
+    F = torch.empty_like(dD)
+    table = autotune.autotune(ctx, dD.data_ptr(), F.data_ptr(), s, reps=1)
+    forms = {v["persistent"] for v in table.values()}
+    print("autotuned launch forms:", autotune.summary(table))
+    J, K = torch.empty_like(dD), torch.empty_like(dD)
+    st = ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s, stats=True)
+    ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert st.quartets_fp64 == g["quartets"] and st.integrals == g["integrals"]
+    _check_against_golden(g, J.cpu().numpy(), K.cpu().numpy(), D, 1e-8, 1e-10, 1e-9)
+    # the persistent form for every class (the benchmark's preferred setting)
+    ctx.set_class_tuning(-1, *autotune.PREFERRED[:2], 1)
+    ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s)
+    ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s)
+    torch.cuda.synchronize()
+    _check_against_golden(g, J.cpu().numpy(), K.cpu().numpy(), D, 1e-8, 1e-10, 1e-9)
+    # mixed: every class's FP32 kernel for its eligible quartets
+    autotune.apply(ctx, table)
+    ctx.configure(precision=hfx.HFX_PREC_MIXED)
+    st = ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s, stats=True)
+    ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert st.quartets_fp32 > 0 and st.quartets_fp32 + st.quartets_fp64 == g["quartets"]
+    _check_against_golden(g, J.cpu().numpy(), K.cpu().numpy(), D, 1e-6, 1e-6, 1e-6)
+    assert forms

@@ -386,3 +386,158 @@ def test_fractional_occupation_rule():
     occ = scf.fractional_occupation(eps, 4.0)
     assert np.allclose(occ, [1, 1, 2 / 3, 2 / 3, 2 / 3, 0])
     assert np.allclose(scf.fractional_occupation(np.array([-0.5, 0.1]), 0.5), [0.5, 0])
+
+
+# ---- d shells on either side, Schwarz bounds ------------------------------------------
+
+def _norm_comp(a, comp):
+    """Unit-normalised Cartesian primitive factor (2a/pi)^{3/4} (4a)^{l/2} /
+    sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!)."""
+    def dfo(n):
+        return float(np.prod(np.arange(2 * n - 1, 0, -2))) if n > 0 else 1.0
+    l = sum(comp)
+    return (2 * a / np.pi) ** 0.75 * (4 * a) ** (l / 2) / np.sqrt(dfo(comp[0]) * dfo(comp[1]) * dfo(comp[2]))
+
+
+def _comps(l):
+    return [(x, y, l - x - y) for x in range(l, -1, -1) for y in range(l - x, -1, -1)]
+
+
+def _raise_by_derivative(l, comp_value, comp_value_at, a, h=1e-3):
+    """Every raw component of angular momentum l from the raw components of
+    l - 1 (and l - 2) on the same centre: for a raw Gaussian
+    G_e = prod (x_i - A_i)^{e_i} exp(-a |r - A|^2),
+      d/dA_i G_e = 2a G_{e + 1_i} - e_i G_{e - 1_i},
+    so G_{e + 1_i} = (d/dA_i G_e + e_i G_{e - 1_i}) / (2a).
+    comp_value(e) -> raw integral with the shell at its own centre;
+    comp_value_at(e, i, t) -> the same with the centre moved by t along i.
+    Returns {component: raw value}."""
+    out = {}
+    for e in _comps(l):
+        i = next(k for k in range(3) if e[k] > 0)
+        low = list(e)
+        low[i] -= 1
+        low = tuple(low)
+        d = _richardson(lambda t: comp_value_at(low, i, t), h)
+        extra = 0.0
+        if low[i] > 0:
+            lower2 = list(low)
+            lower2[i] -= 1
+            extra = low[i] * comp_value(tuple(lower2))
+        out[e] = (d + extra) / (2 * a)
+    return out
+
+
+def test_eri_d_on_ket_by_centre_derivatives(oracle_lib):
+    """(ss|ps) and (ss|ds) with the p/d shell on the ket side: centre
+    derivatives of the lower-l integrals at centre C (shell index 2)."""
+    import oracle
+    rng = np.random.default_rng(17)
+    ex = rng.uniform(0.3, 1.4, size=4)
+    cen = rng.uniform(-1.0, 1.0, size=(4, 3))
+    c_exp = ex[2]
+
+    def raw(e, i=None, t=0.0):
+        l = sum(e)
+        c = cen.copy()
+        if i is not None:
+            c[2, i] += t
+        blk = oracle.Basis(_prim_mol([0, 0, l, 0], ex, c)).eri_shell(0, 1, 2, 3)[0, 0, :, 0]
+        k = _comps(l).index(e)
+        return blk[k] / _norm_comp(c_exp, e)
+
+    for l in (1, 2):
+        got = oracle.Basis(_prim_mol([0, 0, l, 0], ex, cen)).eri_shell(0, 1, 2, 3)[0, 0, :, 0]
+        ref = _raise_by_derivative(l, lambda e: raw(e), lambda e, i, t: raw(e, i, t), c_exp)
+        for k, e in enumerate(_comps(l)):
+            want = _norm_comp(c_exp, e) * ref[e]
+            assert abs(got[k] - want) < 3e-8 * max(abs(want), 1e-3), (l, e, got[k], want)
+
+
+@pytest.mark.parametrize("lket", [0, 1, 2])
+def test_nuclear_attraction_d_by_centre_derivative(oracle_lib, lket):
+    """d-shell nuclear attraction <d|V_C|X> (X = s, p, d) from centre
+    derivatives of <p|V_C|X> and <s|V_C|X>."""
+    import oracle
+    ex = [0.85, 0.55]
+    cen = np.array([[0.1, -0.2, 0.3], [0.7, 0.4, -0.5]])
+    nuc = np.array([[-0.3, 0.6, 0.2]])
+    nb = W.NCART[lket]
+
+    def V(la, A):
+        c = cen.copy()
+        c[0] = A
+        shells = [W.Shell(0, la, np.array([ex[0]]), np.array([1.0])),
+                  W.Shell(1, lket, np.array([ex[1]]), np.array([1.0]))]
+        m = W.Molecule(np.array([0, 0, 5], dtype=np.int32), np.concatenate([c, nuc]), shells)
+        v = oracle.Basis(m).one_electron()[2]
+        na = W.NCART[la]
+        return v[:na, na:na + nb]
+
+    for j in range(nb):
+        def raw(e, i=None, t=0.0, j=j):
+            A = cen[0].copy()
+            if i is not None:
+                A[i] += t
+            l = sum(e)
+            return V(l, A)[_comps(l).index(e), j] / _norm_comp(ex[0], e)
+
+        got = V(2, cen[0])[:, j]
+        ref = _raise_by_derivative(2, lambda e: raw(e), lambda e, i, t: raw(e, i, t), ex[0])
+        for k, e in enumerate(_comps(2)):
+            want = _norm_comp(ex[0], e) * ref[e]
+            assert abs(got[k] - want) < 3e-8 * max(abs(want), 1e-3), (lket, j, e, got[k], want)
+
+
+@pytest.fixture(scope="module")
+def water_spd():
+    """One water with the s/p/d basis (19 functions, d shell on oxygen)."""
+    import oracle
+    m = W.water_cluster(1, 5)
+    return m, oracle.Basis(m)
+
+
+def test_eri_8fold_symmetry_and_schwarz_spd(water_spd):
+    """Every permutation symmetry and the Cauchy-Schwarz inequality with d
+    shells on the bra and on the ket side."""
+    _, B = water_spd
+    eri = B.eri_full()
+    assert eri.shape[0] == 19
+    scale = np.abs(eri).max()
+    for p in [(1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]:
+        assert np.abs(eri - eri.transpose(p)).max() <= 1e-14 * scale, p
+    diag = np.einsum("ijij->ij", eri)
+    assert (diag >= -1e-15).all()
+    bound = np.sqrt(np.abs(diag)[:, :, None, None] * np.abs(diag)[None, None, :, :])
+    assert (np.abs(eri) <= bound * (1 + 1e-12) + 1e-16).all()
+
+
+@pytest.mark.parametrize("which", ["dimer", "water_spd"])
+def test_schwarz_bounds_equal_eri_diagonal(which, dimer, water_spd):
+    """Q_ab = sqrt(max over mu in a, nu in b of (mu nu|mu nu)) read off the
+    full ERI tensor (an independent route: every function quartet, no shell
+    blocks)."""
+    _, B = dimer if which == "dimer" else water_spd
+    eri = B.eri_full()
+    Q = B.schwarz()
+    bf = list(B.shell_bf) + [B.nbf]
+    diag = np.einsum("ijij->ij", eri)
+    for a in range(B.nshell):
+        for b in range(B.nshell):
+            blk = diag[bf[a]:bf[a + 1], bf[b]:bf[b + 1]]
+            assert abs(Q[a, b] - np.sqrt(blk.max())) <= 1e-14 * max(1.0, Q[a, b]), (a, b)
+    assert np.abs(Q - Q.T).max() == 0.0
+
+
+def test_jk_8fold_equals_brute_force_spd(water_spd):
+    """The 8-fold loop with d shells: equal to the ordered brute force and to
+    the N^4 tensor contraction."""
+    m, B = water_spd
+    D = W.random_symmetric(m.nbf, 31)
+    J8, K8, _ = B.jk(D, 0.0)
+    Jb, Kb = B.jk_brute(D, 0.0)
+    assert np.abs(J8 - Jb).max() <= 1e-13 * np.abs(Jb).max()
+    assert np.abs(K8 - Kb).max() <= 1e-13 * np.abs(Kb).max()
+    eri = B.eri_full()
+    assert np.allclose(J8, np.einsum("mnls,ls->mn", eri, D), atol=1e-12, rtol=0)
+    assert np.allclose(K8, np.einsum("mlns,ls->mn", eri, D), atol=1e-12, rtol=0)
