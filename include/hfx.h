@@ -189,6 +189,26 @@ hfx_status hfx_graph_launch(hfx_ctx *ctx, void *stream);
 hfx_status hfx_build_2e_shard_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, int shard,
                                   int nshards, double *dG, void *stream, hfx_fock_stats *stats);
 
+/* Two-electron build that allocates nothing, for callers that cannot call
+ * hipMalloc (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): dG = cj J - ck K exactly as hfx_build_2e_dev
+ * (same kernels, same results), but the per-build scratch -- the accumulator
+ * and the component-scaled density (sum of nbf_m^2 FP64 each), the max|D|
+ * word, the quartet counters and the launch queue counters -- lives in a
+ * fixed 32 MiB device array of the library, one per GPU, held until the
+ * process ends, instead of context memory (the context's screened plans and
+ * ket lists, made at hfx_load, are read as usual).
+ * Limit: 16 x (sum of nbf_m^2) bytes plus 68 KiB within 32 MiB (one molecule:
+ * nbf <= 1446) and at most 512 launch plans; a larger system gives
+ * HFX_ERR_INVALID_ARG and launches nothing.  Every call on a GPU, whatever
+ * its context, shares that GPU's array, which keeps the last call's contents;
+ * each call clears what it accumulates.  Calls that overlap in time on one
+ * GPU (concurrent streams or threads) race and give wrong results; calls
+ * ordered on one stream, or synchronised, are safe.  stats as in
+ * hfx_build_2e_dev (synchronises). */
+hfx_status hfx_build_2e_noalloc_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, double *dG,
+                                    void *stream, hfx_fock_stats *stats);
+
 /* Closed-shell SCF to convergence (section 3, eq. 1): guess, Fock build,
  * Pulay DIIS, eigensolve of X^T F X, aufbau density.  D_out, C_out
  * (nbf x nmo, nmo = nbf - dropped), eps_out (nmo) are optional host arrays.

@@ -224,6 +224,10 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         hfx_destroy(c);
         return HFX_ERR_DEVICE;
     }
+    if (hfx_noalloc_init(c->opt.device) != hipSuccess) {   // device address of the no-alloc scratch
+        hfx_destroy(c);
+        return HFX_ERR_DEVICE;
+    }
     if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
         hfx_destroy(c);
         return HFX_ERR_DEVICE;
@@ -1010,31 +1014,44 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
 
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
                               hipStream_t st, hfx_fock_stats* stats, int shard, int nshards) {
+    BuildBufs b;
+    b.W = c->d_W;
+    b.Dp = c->d_Dp;
+    b.dmax = c->d_dmax;
+    b.counters = c->d_counters;
+    b.bad = c->d_bad;
+    b.work = c->d_work;
+    return hfx_build_with(c, b, dD, cj, ck, dH, dOut, st, stats, shard, nshards);
+}
+
+hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, double cj, double ck,
+                          const double* dH, double* dOut, hipStream_t st, hfx_fock_stats* stats, int shard,
+                          int nshards) {
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "build: nothing loaded");
     const size_t nn = c->nelem;
     const bool mixed = c->opt.precision == HFX_PREC_MIXED;
     auto t0 = std::chrono::steady_clock::now();
     if (c->timing) collect_timing(c);
-    HIPCK(hfx_fill_u64(c->d_dmax, 1, st));
-    HIPCK(hfx_fill_u64(c->d_counters, 43, st));   // 42 quartet counters + the non-finite flag
-    HIPCK(hfx_prepare_density(dD, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, c->d_Dp,
-                              c->d_dmax, st));
-    HIPCK(hfx_fill(c->d_W, nn, 0.0, st));
+    HIPCK(hfx_fill_u64(bufs.dmax, 1, st));
+    HIPCK(hfx_fill_u64(bufs.counters, 43, st));   // 42 quartet counters + the non-finite flag
+    HIPCK(hfx_prepare_density(dD, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, bufs.Dp,
+                              bufs.dmax, st));
+    HIPCK(hfx_fill(bufs.W, nn, 0.0, st));
     for (auto& KL : c->ketlists) {
         HIPCK(hfx_fill(KL.d_wket, (size_t)KL.ncd * KL.n, 0.0, st));
-        HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), c->d_Dp, c->d_moff,
+        HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), bufs.Dp, c->d_moff,
                              KL.d_dket, st));
     }
     bool any_persist = false;
     for (const auto& P : c->plans) any_persist |= P.persist;
-    if (any_persist) HIPCK(hfx_fill_u64(c->d_work, 16 * (int)c->plans.size(), st));
+    if (any_persist) HIPCK(hfx_fill_u64(bufs.work, 16 * (int)c->plans.size(), st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
         const int cid = P.cid;
         const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid];
         if (mx)
-            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_tasks, P.ntask, c->opt.fp32_tau, c->d_dmax, P.d_split,
+            HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_tasks, P.ntask, c->opt.fp32_tau, bufs.dmax, P.d_split,
                             st));
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
@@ -1052,15 +1069,15 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         a.tasks = P.d_tasks;
         a.boys64 = c->d_boys64;
         a.boys32 = c->d_boys32;
-        a.D = c->d_Dp;
-        a.W = c->d_W;
+        a.D = bufs.Dp;
+        a.W = bufs.W;
         a.wket = KL.d_wket;
-        a.counters = c->d_counters + 2 * cid;
+        a.counters = bufs.counters + 2 * cid;
         a.cj = cj;
         a.ck = ck;
         a.shard = shard;
         a.nshards = nshards;
-        a.work = P.persist ? c->d_work + 16 * pi : nullptr;
+        a.work = P.persist ? bufs.work + 16 * pi : nullptr;
         a.qlen = P.ntask / 8;
         a.part = mx ? 1 : 0;
         a.task_off = 0;
@@ -1087,7 +1104,7 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         if (mx) {   // the same tasks' kets from their split on, in FP32
             ClassArgs b = a;
             b.part = 2;
-            b.work = P.persist ? c->d_work + 16 * pi + 8 : nullptr;
+            b.work = P.persist ? bufs.work + 16 * pi + 8 : nullptr;
             ls = launch(b, 1);
             if (ls != HFX_OK) return ls;
         }
@@ -1097,17 +1114,17 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
         }
     }
     for (auto& KL : c->ketlists)
-        HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, c->d_moff, c->d_W,
+        HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, c->d_moff, bufs.W,
                               st));
-    HIPCK(hfx_assemble(dH, c->d_W, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, dOut, c->d_bad,
+    HIPCK(hfx_assemble(dH, bufs.W, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, dOut, bufs.bad,
                        st));
     c->last_stream = st;
     if (stats) {
         HIPCK(hipStreamSynchronize(st));
         unsigned long long cnt[42];
         int bad = 0;
-        HIPCK(hipMemcpy(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
-        HIPCK(hipMemcpy(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(cnt, bufs.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(&bad, bufs.bad, sizeof(int), hipMemcpyDeviceToHost));
         stats->quartets_fp64 = stats->quartets_fp32 = stats->integrals = stats->prim_quartets = 0;
         for (int k = 0; k < 21; ++k) {
             stats->quartets_fp64 += (long long)cnt[2 * k];

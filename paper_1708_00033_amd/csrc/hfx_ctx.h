@@ -139,14 +139,33 @@ struct hfx_ctx {
     hipStream_t last_stream = nullptr;
 };
 
+// Per-build scratch of one Fock build: the accumulator W and the
+// component-scaled density D' (ragged, nelem doubles each), the max|D| word,
+// 42 quartet counters followed by the non-finite flag, and 16 queue counters
+// per launch plan.  Context memory by default (hfx_ctx_bufs); the no-alloc
+// entry point passes a static device array instead.
+struct BuildBufs {
+    double* W = nullptr;
+    double* Dp = nullptr;
+    unsigned long long* dmax = nullptr;
+    unsigned long long* counters = nullptr;
+    int* bad = nullptr;
+    unsigned long long* work = nullptr;
+};
+
 // implemented in guess.hip
 void hfx_guess_release(hfx_ctx* c);
+
+// implemented in noalloc.hip
+hipError_t hfx_noalloc_init(int device);
 
 // implemented in hfx_api.cpp
 hfx_status hfx_fail(hfx_ctx* c, hfx_status s, const std::string& msg);
 hfx_status hfx_hip_check(hfx_ctx* c, hipError_t e, const char* what);
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
                               hipStream_t st, hfx_fock_stats* stats, int shard, int nshards);
+hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& b, const double* dD, double cj, double ck, const double* dH,
+                          double* dOut, hipStream_t st, hfx_fock_stats* stats, int shard, int nshards);
 
 // implemented in misc_kernels.hip
 extern "C" {

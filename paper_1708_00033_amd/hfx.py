@@ -99,6 +99,8 @@ _sigs = {
                           C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_build_2e_shard_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p,
                                 C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_build_2e_noalloc_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                  C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
     "hfx_batch_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
@@ -310,6 +312,14 @@ class Context:
         st = hfx_fock_stats() if stats else None
         self._check(hfx_build_2e_shard_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, shard, nshards, C.c_void_p(dG_ptr),
                                            C.c_void_p(stream), C.byref(st) if stats else None))
+        return st
+
+    def build_2e_noalloc_dev(self, dD_ptr: int, cj: float, ck: float, dG_ptr: int, stream: int = 0,
+                             stats: bool = False):
+        """hfx_build_2e_noalloc_dev: per-build scratch in the library's fixed device array."""
+        st = hfx_fock_stats() if stats else None
+        self._check(hfx_build_2e_noalloc_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, C.c_void_p(dG_ptr),
+                                             C.c_void_p(stream), C.byref(st) if stats else None))
         return st
 
     def scf(self, D0: Optional[np.ndarray] = None, want_c: bool = False, model: "GuessNet" = None, **kw):
