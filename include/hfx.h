@@ -238,7 +238,12 @@ hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
  * eight per-XCD queues through atomic counters, the dynamic load balancing
  * of algorithms 1-3's ddi_dlbnext; 2: persistent with one task per wave,
  * each wave with its own LDS bra rows, for short tasks; falls back to 1 when
- * the workgroup's rows do not fit in LDS) and the digestion (-1: the context's
+ * the workgroup's rows do not fit in LDS; 3: persistent and register-tiled:
+ * a ket's primitives (1, 3 or 9 per pair) are read into registers once and
+ * serve a block of two Q-adjacent bras (one when their LDS rows do not
+ * fit), FP64 only -- a mixed build evaluates such a class in FP64; classes
+ * or ket lists without register-tiled kernels fall back to 1; 4: as 3 with
+ * one bra per task) and the digestion (-1: the context's
  * option; HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL; LDS staging needs
  * (n_a + n_b) x nbf x 8 bytes <= 160 KiB and falls back to global
  * otherwise).  Re-plans a loaded system; results are unchanged up to the
@@ -265,11 +270,12 @@ hfx_status hfx_kernel_timing(hfx_ctx *ctx, int enable);
 hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 
 /* Launches of a build: one per (quartet class, ket primitive count).
- * info[11] = {class index, ket primitives per pair, workgroup tasks, unique
+ * info[12] = {class index, ket primitives per pair, workgroup tasks, unique
  * quartets, primitive quartets, integrals, timed launches, digestion mode,
- * work-items per workgroup, launch form (0/1/2 as in hfx_set_class_tuning), workgroups of the FP64
- * kernel}; *ms = summed event time of the timed launches (a mixed build
- * times its FP64 and FP32 kernels together). */
+ * work-items per workgroup, launch form (0..4 as in hfx_set_class_tuning),
+ * workgroups of the FP64 kernel, bras per task}; *ms = summed event time of
+ * the timed launches (a mixed build times its FP64 and FP32 kernels
+ * together). */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 

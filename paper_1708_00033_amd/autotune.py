@@ -21,7 +21,8 @@ from . import hfx
 
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
     (2048, 0, 0, -1), (2048, 1, 0, -1), (8192, 0, 0, -1), (8192, 1, 0, -1), (32768, 0, 0, -1), (32768, 1, 0, -1),
-    (2048, 1, 1, -1), (8192, 1, 1, -1), (8192, 0, 0, 1), (32768, 0, 0, 1), (8192, 1, 2, -1), (32768, 0, 2, -1))
+    (2048, 1, 1, -1), (8192, 1, 1, -1), (8192, 0, 0, 1), (32768, 0, 0, 1), (8192, 1, 2, -1), (32768, 0, 2, -1),
+    (32768, 0, 3, -1), (32768, 0, 4, -1), (8192, 1, 4, -1))
 
 
 PREFERRED: Tuple[int, int, int, int] = (32768, 0, 0, -1)

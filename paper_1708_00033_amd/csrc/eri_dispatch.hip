@@ -4,13 +4,57 @@
 
 #define HFX_DECL(cid)                                        \
     extern "C" const void* hfx_class_kernel_##cid(int);      \
+    extern "C" const void* hfx_class_kernel_kr_##cid(int);   \
     extern "C" const void* hfx_schwarz_kernel_##cid(void);
 HFX_FOR_EACH_CID(HFX_DECL)
 
 #define HFX_KPTR(cid) hfx_class_kernel_##cid,
+#define HFX_RPTR(cid) hfx_class_kernel_kr_##cid,
 #define HFX_SPTR(cid) hfx_schwarz_kernel_##cid,
 static const void* (*const kClassLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_KPTR)};
+static const void* (*const kClassLookupKr[21])(int) = {HFX_FOR_EACH_CID(HFX_RPTR)};
 static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPTR)};
+
+// Register-tiled kernels: variant index of (digestion mode, ket primitive
+// count, bras per block), or -1 when the class has none for that count.
+static int kr_variant(int cid, int mode, int kp, int nbl) {
+    const int kpi = kp == 1 ? 0 : (kp == 3 ? 1 : (kp == 9 ? 2 : -1));
+    if (kpi < 0 || nbl < 1 || nbl > 2) return -1;
+    const int v = mode + 2 * kpi + 6 * (nbl - 1);
+    return kClassLookupKr[cid](v) ? v : -1;
+}
+
+extern "C" int hfx_class_has_kr(int cid, int kp) { return kr_variant(cid, 0, kp, 1) >= 0; }
+
+extern "C" hipError_t hfx_launch_class_kr(int cid, int mode, int kp, int nbl, int nblocks, size_t lds_bytes,
+                                          hipStream_t stream, const ClassArgs* args) {
+    if (nblocks <= 0) return hipSuccess;
+    const int v = kr_variant(cid, mode, kp, nbl);
+    if (v < 0 || !args->work) return hipErrorInvalidValue;
+    const void* fn = kClassLookupKr[cid](v);
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    void* kargs[] = {(void*)args};
+    return hipLaunchKernel(fn, dim3(nblocks), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+}
+
+extern "C" int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, size_t lds_bytes) {
+    const int v = kr_variant(cid, mode, kp, nbl);
+    if (v < 0) return 0;
+    const void* fn = kClassLookupKr[cid](v);
+    if (lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
+        return 0;
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEriClassInfo[cid].wgs, lds_bytes) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * ncu;
+}
 
 #define HFX_WG 256
 
@@ -60,9 +104,11 @@ extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, i
 extern "C" hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs) {
     long long sc = 0;
     int rg = 0;
-    for (int v = 0; v < 32; ++v) {
+    for (int v = 0; v < 32 + 12; ++v) {
+        const void* fn = v < 32 ? kClassLookup[cid](v) : kClassLookupKr[cid](v - 32);
+        if (!fn) continue;
         hipFuncAttributes fa;
-        const hipError_t e = hipFuncGetAttributes(&fa, kClassLookup[cid](v));
+        const hipError_t e = hipFuncGetAttributes(&fa, fn);
         if (e != hipSuccess) return e;
         sc = fa.localSizeBytes > (size_t)sc ? (long long)fa.localSizeBytes : sc;
         rg = fa.numRegs > rg ? fa.numRegs : rg;

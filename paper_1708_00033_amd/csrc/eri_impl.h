@@ -154,6 +154,105 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
     }
 }
 
+// The updates of digest() for the register-tiled kernels: D_cd comes in
+// registers (read once per ket) and the ket block's J contribution is summed
+// into jcd over the bras of a block (one atomic per ket and component after
+// the block) instead of one atomic per quartet.
+template <int NA, int NB, int NC, int ND, int MODE>
+__device__ __forceinline__ void digest_kr(const double* I, double g, double ck, const PairInfo& bra, int fc, int fd,
+                                          const double* dcd, const double* dab, double* jab, double* jcd,
+                                          double* FI, double* FJ, const double* __restrict__ D,
+                                          double* __restrict__ W, int N, int RS, int cb, int db) {
+    const int fa = bra.bfa, fb = bra.bfb;
+    const double ckg = -ck * g;
+#pragma unroll
+    for (int mn = 0; mn < NA * NB; ++mn) {
+        double v = 0.0;
+#pragma unroll
+        for (int ls = 0; ls < NC * ND; ++ls) v += I[mn * NC * ND + ls] * dcd[ls];
+        jab[mn] += g * v;
+    }
+#pragma unroll
+    for (int ls = 0; ls < NC * ND; ++ls) {
+        double v = 0.0;
+#pragma unroll
+        for (int mn = 0; mn < NA * NB; ++mn) v += I[mn * NC * ND + ls] * dab[mn];
+        jcd[ls] += g * v;
+    }
+    {   // K: W_ac -= ck g sum I D_bd
+        double dbd[NB * ND];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) dbd[n * ND + s] = D[(size_t)(fb + n) * N + fd + s];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) {
+                double v = 0.0;
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dbd[n * ND + s];
+                row_add<MODE>(FI + m * RS, W, fa + m, fc + l, N, fc + l - cb, ckg * v);
+            }
+    }
+    {   // K: W_bd -= ck g sum I D_ac
+        double dac[NA * NC];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) dac[m * NC + l] = D[(size_t)(fa + m) * N + fc + l];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < NA; ++m)
+#pragma unroll
+                    for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dac[m * NC + l];
+                row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v);
+            }
+    }
+    {   // K: W_ad -= ck g sum I D_bc
+        double dbc[NB * NC];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) dbc[n * NC + l] = D[(size_t)(fb + n) * N + fc + l];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) {
+                double v = 0.0;
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dbc[n * NC + l];
+                row_add<MODE>(FI + m * RS, W, fa + m, fd + s, N, fd + s - db, ckg * v);
+            }
+    }
+    {   // K: W_bc -= ck g sum I D_ad
+        double dad[NA * ND];
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int s = 0; s < ND; ++s) dad[m * ND + s] = D[(size_t)(fa + m) * N + fd + s];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int l = 0; l < NC; ++l) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < NA; ++m)
+#pragma unroll
+                    for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dad[m * ND + s];
+                row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v);
+            }
+    }
+}
+
 // Same updates with rolled loops, for classes whose integral block is too
 // large to keep in registers (the block then lives in scratch).
 template <int NA, int NB, int NC, int ND, int MODE>
@@ -473,6 +572,174 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     }
 }
 
+// Register-tiled task: a block of nb <= NBL consecutive bras of the class's
+// Q-sorted list (one molecule) against one range of kets whose primitive
+// count KP is a compile-time constant.  Each lane takes kets of the range; a
+// ket's primitives, D'_cd and record are read once into registers and
+// serve every bra of the block, whose screened prefixes differ: bra r takes
+// ket s iff Q_r Q_s >= tau (and, for bra and ket of one pair class, the ket's
+// class position <= r), the same test that sizes the plan's prefixes.  The
+// ket block's J sum over the block goes out in one atomic per component; each
+// bra has its own LDS rows F_I, F_J (MODE 0).  FP64 only.
+template <class E, int MODE, int KP, int NBL>
+__device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, const double* t64) {
+    constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND, NI = NAB * NCD;
+    constexpr int NT = E::WGS;
+    const int tid = (int)threadIdx.x;
+    extern __shared__ __align__(16) double lds[];
+    const int4 task = a.tasks[ti];
+    if (task.x < 0) return;
+    const int r0 = task.x & 0x0fffffff;
+    const int nb = (task.x >> 28) + 1;
+    const int s0 = task.y, send = task.z;
+    PairInfo bra[NBL];
+    bool on[NBL];
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+        on[i] = i < nb && (a.nshards <= 1 || (r0 + i) % a.nshards == a.shard);
+        bra[i] = a.bra[r0 + (i < nb ? i : 0)];
+    }
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) any |= on[i];
+    if (!any) return;   // uniform: another shard's block
+    // the block's molecule (shared by its bras): blocks of D', W, leading dimension
+    const int N = bra[0].ld;
+    const double* __restrict__ Dm = a.D + a.moff[bra[0].mol];
+    double* __restrict__ Wm = a.W + a.moff[bra[0].mol];
+    int RS = N, cb = 0, db = 0, half = N;
+    if (a.win) {
+        RS = a.rs;
+        half = RS / 2;
+        const int wc = task.w & 0xffff, wd = task.w >> 16;
+        cb = wc * a.win;
+        db = wd == wc ? cb : wd * a.win - half;
+    }
+    constexpr int ROWS = (NA + NB);
+    double* F0 = lds + LdsLayout<E, 0>::ROWS;   // bra i's rows at F0 + i ROWS a.rs
+    if constexpr (MODE == 0) {
+        for (int i = tid; i < nb * ROWS * a.rs; i += NT) F0[i] = 0.0;
+        __syncthreads();
+    }
+    double dab[NBL][NAB], jab[NBL][NAB], sbra[NBL];
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+        sbra[i] = bra[i].a != bra[i].b ? 2.0 : 1.0;
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                dab[i][m * NB + n] = Dm[(size_t)(bra[i].bfa + m) * N + bra[i].bfb + n];
+                jab[i][m * NB + n] = 0.0;
+            }
+    }
+    const int nl = a.nket_list;
+    unsigned n64 = 0;
+    for (int s = s0 + tid; s < send; s += NT) {
+        const int4 kb = a.kbf[s];
+        const int fc = kb.x, fd = kb.y;
+        double kv[KP][9];
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+#pragma unroll
+            for (int f = 0; f < 9; ++f) kv[k][f] = a.kprim[(size_t)(f * KP + k) * nl + s];
+        double dcd[NCD], jcd[NCD];
+#pragma unroll
+        for (int ls = 0; ls < NCD; ++ls) {
+            dcd[ls] = a.dket[(size_t)ls * nl + s];
+            jcd[ls] = 0.0;
+        }
+        const double qs = a.ketq[s];
+        const int ks = a.same ? a.kpos[s] : 0;
+        const double* kab = a.ket[s].AB;   // read only by classes with a p or d ket
+        const double gk = kb.z != kb.w ? 2.0 : 1.0;
+        bool hit = false;
+#pragma unroll
+        for (int i = 0; i < NBL; ++i) {
+            if (!on[i]) continue;
+            if (!(qs * bra[i].Q >= a.tau) || ks > r0 + i) continue;
+            const double g = sbra[i] * gk * ((kb.z == bra[i].a && kb.w == bra[i].b) ? 1.0 : 2.0);
+            double I[NI];
+            E::template run_kr<double, BOYS_LROW64, KP>(a.prim + bra[i].prim_off, bra[i].nprim, kv, bra[i].AB, kab,
+                                                        t64, I);
+            ++n64;
+            hit = true;
+            double* FI = F0 + i * ROWS * a.rs;
+            digest_kr<NA, NB, NC, ND, MODE>(I, g, a.ck, bra[i], fc, fd, dcd, dab[i], jab[i], jcd, FI, FI + NA * RS,
+                                            Dm, Wm, N, RS, cb, db);
+        }
+        if (hit) {
+            const double cj2 = 2.0 * a.cj;
+#pragma unroll
+            for (int l = 0; l < NC; ++l)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if constexpr (MODE == 0)
+                        atomicAdd(a.wket + (size_t)(l * ND + d) * nl + s, cj2 * jcd[l * ND + d]);
+                    else
+                        atomicAdd(Wm + (size_t)(fc + l) * N + fd + d, cj2 * jcd[l * ND + d]);
+                }
+        }
+    }
+    const int lane = tid & 63;
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+        if (!on[i]) continue;
+#pragma unroll
+        for (int mn = 0; mn < NAB; ++mn) {
+            const double v = wave_sum(jab[i][mn]);
+            if (lane == 0) atomicAdd(Wm + (size_t)(bra[i].bfa + mn / NB) * N + bra[i].bfb + mn % NB, 2.0 * a.cj * v);
+        }
+    }
+    {
+        const unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
+        if (lane == 0 && a.counters && c64) atomicAdd(a.counters + 0, c64);
+    }
+    if constexpr (MODE == 0) {
+        __syncthreads();
+        for (int i = tid; i < nb * ROWS * a.rs; i += NT) {
+            const double v = F0[i];
+            if (v != 0.0) {
+                const int bi = i / (ROWS * a.rs), j = i - bi * ROWS * a.rs;
+                int bfa = bra[0].bfa, bfb = bra[0].bfb;
+#pragma unroll
+                for (int k = 1; k < NBL; ++k)
+                    if (bi == k) {
+                        bfa = bra[k].bfa;
+                        bfb = bra[k].bfb;
+                    }
+                const int row = j < NA * RS ? bfa + j / RS : bfb + (j - NA * RS) / RS;
+                const int lc = j < NA * RS ? j % RS : (j - NA * RS) % RS;
+                const int col = lc + (lc < half ? cb : db);
+                if (col < N) atomicAdd(Wm + (size_t)row * N + col, v);
+            }
+        }
+    }
+}
+
+// Persistent register-tiled launch (same queues as k_class_persist).
+template <class E, int MODE, int KP, int NBL>
+__global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
+    extern __shared__ __align__(16) double lds[];
+    __shared__ int next_entry;
+    double* t64 = lds;
+    load_boys_lds<E, 0>(a, t64, nullptr);
+    const int x0 = blockIdx.x & 7;
+    for (int q = 0; q < 8;) {
+        const int x = (x0 + q) & 7;
+        if (threadIdx.x == 0) next_entry = (int)atomicAdd(a.work + x, 1ull);
+        __syncthreads();
+        const int k = next_entry;
+        __syncthreads();
+        if (k >= a.qlen) {
+            ++q;
+            continue;
+        }
+        class_task_kr<E, MODE, KP, NBL>(a, 8 * k + x, t64);
+    }
+}
+
 // Static launch: workgroup i runs task task_off + i (a plan's tasks may span
 // several launches: a grid is limited to 2^32 work-items).
 template <class E, int MODE, int FP32>
@@ -619,6 +886,27 @@ struct ClassKernels {
     }
 };
 
+// Register-tiled kernels of one class: variant = mode + 2 kpi + 6 (NBL - 1),
+// ket primitive count 1, 3 or 9 (kpi 0, 1, 2), blocks of 1 or 2 bras.
+template <class E>
+struct ClassKernelsKr {
+    static const void* get(int v) {
+        static const void* t[12] = {
+            (const void*)k_class_kr<E, 0, 1, 1>, (const void*)k_class_kr<E, 1, 1, 1>,
+            (const void*)k_class_kr<E, 0, 3, 1>, (const void*)k_class_kr<E, 1, 3, 1>,
+            (const void*)k_class_kr<E, 0, 9, 1>, (const void*)k_class_kr<E, 1, 9, 1>,
+            (const void*)k_class_kr<E, 0, 1, 2>, (const void*)k_class_kr<E, 1, 1, 2>,
+            (const void*)k_class_kr<E, 0, 3, 2>, (const void*)k_class_kr<E, 1, 3, 2>,
+            (const void*)k_class_kr<E, 0, 9, 2>, (const void*)k_class_kr<E, 1, 9, 2>};
+        return (v >= 0 && v < 12) ? t[v] : nullptr;
+    }
+};
+
+#define HFX_CLASS_KR(cid) \
+    extern "C" const void* hfx_class_kernel_kr_##cid(int v) { return ClassKernelsKr<Eval##cid>::get(v); }
+#define HFX_CLASS_NO_KR(cid) \
+    extern "C" const void* hfx_class_kernel_kr_##cid(int) { return nullptr; }
+
 // Per-class translation unit: evaluator wrapper, the kernel variants, the
 // Schwarz kernel and C lookups.
 #define HFX_CLASS_TU(cid, fname, la_, lb_, lc_, ld_, wgs_, wgs_alt_)                                               \
@@ -631,6 +919,13 @@ struct ClassKernels {
                                                    const double* cd, const R* tab, R* out) {           \
             fname<R, BS>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),          \
                          R(cd[1]), R(cd[2]), tab, out);                                                \
+        }                                                                                              \
+        template <typename R, int BS, int KP>                                                          \
+        __device__ __forceinline__ static void run_kr(const PrimPair* bp, int nbp,                     \
+                                                      const R (&kv)[KP][9], const double* ab,          \
+                                                      const double* cd, const R* tab, R* out) {        \
+            fname##_kr<R, BS, KP>(bp, nbp, kv, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]), R(cd[1]),       \
+                                  R(cd[2]), tab, out);                                                 \
         }                                                                                              \
     };                                                                                                 \
     struct Eval##cid##A : Eval##cid {                                                                   \

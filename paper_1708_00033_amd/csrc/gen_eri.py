@@ -279,12 +279,47 @@ class ClassGen:
         lines.extend(outs)
         lines.append("}")
         self.hrr_flops = hfl[0]
+        if a_sel is None:
+            # Register-tiled form: the ket's KP primitives (a compile-time count)
+            # are already in registers, kv[k] = {q, 1/2q, Q, Q - C, K}; the bra
+            # primitive loop is outermost (one set of scalar loads per bra
+            # primitive) and the KP ket primitives inside it are unrolled, so
+            # their independent Boys / recurrence chains interleave.
+            kr = [f"template <typename R, int BS, int KP>\n__device__ __forceinline__ void {fname}_kr(",
+                  "    const PrimPair* __restrict__ bp, int nbp, const R (&kv)[KP][9], const R AB0, const R AB1,",
+                  "    const R AB2, const R CD0, const R CD1, const R CD2, const R* __restrict__ boys_tab,",
+                  "    R* __restrict__ out) {"]
+            for a in acc_name.values():
+                kr.append(f"  R {a} = R(0);")
+            kr += ["#pragma unroll 1",
+                   "  for (int ib = 0; ib < nbp; ++ib) {",
+                   "    const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + ib);",
+                   "    const R p = R(B[0]), i2p = R(B[1]), Kb = R(B[8]);",
+                   "    const R PA0 = R(B[5]), PA1 = R(B[6]), PA2 = R(B[7]);",
+                   "    const R P0 = R(B[2]), P1 = R(B[3]), P2 = R(B[4]);",
+                   "#pragma unroll",
+                   "    for (int ik = 0; ik < KP; ++ik) {",
+                   "      const R q = kv[ik][0], i2q = kv[ik][1], Kk = kv[ik][8];",
+                   "      const R Q0 = kv[ik][2], Q1 = kv[ik][3], Q2 = kv[ik][4];",
+                   "      const R QC0 = kv[ik][5], QC1 = kv[ik][6], QC2 = kv[ik][7];",
+                   "      const R PQ0 = P0 - Q0, PQ1 = P1 - Q1, PQ2 = P2 - Q2;"]
+            kr += ["      " + x for x in blk[4:]]
+            kr += ["    }", "  }", "  (void)AB0; (void)AB1; (void)AB2; (void)CD0; (void)CD1; (void)CD2;"]
+            kr.extend(hcode)
+            kr.extend(outs)
+            kr.append("}")
+            lines.append("")
+            lines.extend(kr)
         return "\n".join(lines)
 
 
 # Classes whose whole integral block is too large for registers are also
 # emitted as passes, one per Cartesian component of shell a.
 PASS_CLASSES = {19, 20}
+# Classes that also get the register-tiled kernels (ket primitives in
+# registers, blocks of bras): low total angular momentum, where the per-ket
+# loads and atomics weigh most against the arithmetic.
+KR_CLASSES = {0, 1, 2, 3, 4, 6, 7}
 
 
 def main(out_dir):
@@ -319,7 +354,8 @@ def main(out_dir):
         macro = "HFX_CLASS_TU_PASSES" if cid in PASS_CLASSES else "HFX_CLASS_TU"
         tu = [f"// Generated by gen_eri.py: kernels of class {cid} ({PAIR_NAMES[B]}|{PAIR_NAMES[K]}).",
               f'#include "eri_class_{cid:02d}.h"', '#include "../eri_impl.h"', "",
-              f"{macro}({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {wg_size(cid)}, {wg_alt(cid)})", ""]
+              f"{macro}({cid}, {fname}, {la}, {lb}, {lc}, {ld}, {wg_size(cid)}, {wg_alt(cid)})",
+              f"HFX_CLASS_KR({cid})" if cid in KR_CLASSES else f"HFX_CLASS_NO_KR({cid})", ""]
         with open(os.path.join(out_dir, f"eri_class_{cid:02d}.hip"), "w") as fh:
             fh.write("\n".join(tu))
         table.append((cid, B, K, la, lb, lc, ld, g.flops, g.hrr_flops, fname))

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -123,6 +124,7 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_soa);
         dfree(L.d_wket);
         dfree(L.d_kbf);
+        dfree(L.d_kpos);
         dfree(L.d_dket);
     }
     c->ketlists.clear();
@@ -346,11 +348,57 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     // workgroups fit in LDS, else its default (a large group keeps the waves
     // per CU up when LDS admits one workgroup per CU)
     P.alt = hfx_class_wgs(P.cid, 1) != hfx_class_wgs(P.cid, 0) && 2 * P.lds(false) <= 160 * 1024 - 512;
+    // register-tiled persistent form (launch form 3): blocks of two
+    // Q-adjacent bras of one molecule when their rows fit in LDS, else one
+    const int form = c->tune_persist[P.cid];
+    if ((form == 3 || form == 4) && hfx_class_has_kr(P.cid, KL.kp) && nbra < (1 << 28)) {
+        P.kr = true;
+        P.alt = 0;
+        P.nbl = form == 3 ? 2 : 1;
+        if (P.mode == 0 && P.lds(false) > 160 * 1024 - 256) P.nbl = 1;
+    }
+    // one task per block of bras: the block's ket range in a group is the
+    // longest of its bras' screened prefixes; the kernel keeps, per bra, only
+    // the kets of its own prefix (the same test as above, per lane)
+    struct BRun { int r0, nb, g, n; };
+    std::vector<BRun> bruns;
+    if (P.nbl > 1) {
+        std::vector<int> first(nbra), size(nbra);
+        for (int r = 0; r < nbra;) {
+            int e = r;
+            while (e < nbra && bras[e].mol == bras[r].mol) ++e;
+            for (int b = r; b < e; b += P.nbl)
+                for (int k = b; k < std::min(e, b + P.nbl); ++k) {
+                    first[k] = b;
+                    size[k] = std::min(P.nbl, e - b);
+                }
+            r = e;
+        }
+        std::map<int, int> cur;   // group -> longest prefix of the current block
+        int cur_first = -1, cur_nb = 0;
+        auto flush = [&]() {
+            for (const auto& x : cur) bruns.push_back(BRun{cur_first, cur_nb, x.first, x.second});
+            cur.clear();
+        };
+        for (const Run& ru : runs) {
+            if (first[ru.r] != cur_first) {
+                flush();
+                cur_first = first[ru.r];
+                cur_nb = size[ru.r];
+            }
+            int& x = cur[ru.g];
+            x = std::max(x, ru.n);
+        }
+        flush();
+    } else {
+        bruns.reserve(runs.size());
+        for (const Run& ru : runs) bruns.push_back(BRun{ru.r, 1, ru.g, ru.n});
+    }
     const int NX = 8, WGS = hfx_class_wgs(P.cid, P.alt);
     std::vector<std::vector<int4>> queue(NX);
     std::vector<long long> load(NX, 0);
-    for (const Run& ru : runs) {
-        const int r = ru.r, n = ru.n, kb = gs[ru.g], w = wcode[ru.g];
+    for (const BRun& ru : bruns) {
+        const int r = ru.r0 | ((ru.nb - 1) << 28), n = ru.n, kb = gs[ru.g], w = wcode[ru.g];
         if (stripe && n >= 2 * NX * WGS) {
             int nch = (n + TQ - 1) / TQ;
             nch = ((nch + NX - 1) / NX) * NX;
@@ -385,7 +433,13 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
         P.wave = WGS / 64;
         if (P.lds(false) > 160 * 1024 - 256) P.wave = 0;   // does not fit: one task per workgroup
     }
-    for (int mx = 0; mx < (P.fp64_only ? 1 : 2); ++mx) {
+    if (P.kr) {
+        int nb = hfx_class_resident_blocks_kr(P.cid, P.mode, KL.kp, P.nbl, P.lds(false));
+        if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a register-tiled class kernel failed");
+        nb = std::min(nb, P.ntask);
+        P.nblocks[0] = P.nblocks[1] = ((nb + 7) / 8) * 8;
+    }
+    for (int mx = 0; mx < (P.kr ? 0 : (P.fp64_only ? 1 : 2)); ++mx) {
         const size_t lds = P.lds(mx != 0);
         int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, lds);
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
@@ -445,7 +499,8 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     if (task_quartets != 0 && (task_quartets < 256 || task_quartets % 256 != 0 || task_quartets > (1 << 24)))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be 0 or a multiple of 256 in [256, 2^24]");
     if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
-    if (persistent < 0 || persistent > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0, 1 or 2");
+    if (persistent < 0 || persistent > 4)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0, 1, 2, 3 or 4");
     if (digest < -1 || digest > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0 or 1");
     for (int k = 0; k < 21; ++k)
         if (cid == -1 || cid == k) {
@@ -809,6 +864,12 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
             HIPCK(dalloc(&KL.d_dket, (size_t)KL.ncd * n));
             HIPCK(dalloc(&KL.d_kbf, n));
             HIPCK(hipMemcpy(KL.d_kbf, kbf.data(), n * sizeof(int4), hipMemcpyHostToDevice));
+            {
+                std::vector<int> kp_int(n);
+                for (size_t i = 0; i < n; ++i) kp_int[i] = (int)sp[i];
+                HIPCK(dalloc(&KL.d_kpos, n));
+                HIPCK(hipMemcpy(KL.d_kpos, kp_int.data(), n * sizeof(int), hipMemcpyHostToDevice));
+            }
             HIPCK(hipMemcpy(KL.d_pairs, sub.data(), n * sizeof(PairInfo), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_q, q.data(), n * sizeof(double), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_soa, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1004,8 +1065,9 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[6] = p.launches;
     info[7] = p.mode;
     info[8] = hfx_class_wgs(p.cid, p.alt);
-    info[9] = p.persist ? (p.wave ? 2 : 1) : 0;
+    info[9] = p.kr ? c->tune_persist[p.cid] : (p.persist ? (p.wave ? 2 : 1) : 0);
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
+    info[11] = p.nbl;
     if (ms) *ms = p.ms;
     return HFX_OK;
 }
@@ -1049,7 +1111,7 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
         const int cid = P.cid;
-        const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid];
+        const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid] && !P.kr;
         if (mx)
             HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_tasks, P.ntask, c->opt.fp32_tau, bufs.dmax, P.d_split,
                             st));
@@ -1078,6 +1140,10 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         a.shard = shard;
         a.nshards = nshards;
         a.work = P.persist ? bufs.work + 16 * pi : nullptr;
+        a.ketq = KL.d_q;
+        a.kpos = KL.d_kpos;
+        a.tau = c->opt.schwarz_tau;
+        a.same = P.B == P.K;
         a.qlen = P.ntask / 8;
         a.part = mx ? 1 : 0;
         a.task_off = 0;
@@ -1086,6 +1152,10 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         // keeps workgroup i on XCD i mod 8 in step with the task queues)
         constexpr int kMaxGroups = 1 << 20;
         auto launch = [&](ClassArgs& x, int fp32) -> hfx_status {
+            if (P.kr) {
+                HIPCK(hfx_launch_class_kr(cid, P.mode, KL.kp, P.nbl, P.nblocks[0], P.lds(false), st, &x));
+                return HFX_OK;
+            }
             if (P.persist) {
                 HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, fp32, P.nblocks[fp32], P.lds(fp32 != 0), st,
                                        &x));

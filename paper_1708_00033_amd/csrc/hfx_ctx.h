@@ -26,6 +26,7 @@ struct KetList {
     double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
     double* d_dket = nullptr;   // D'_cd of every ket, gathered per build, same layout
     int4* d_kbf = nullptr;      // per ket: (bfa, bfb, a, b)
+    int* d_kpos = nullptr;      // per ket: position in its pair class's Q-sorted list
     int ncd = 1;
 };
 
@@ -47,9 +48,13 @@ struct SubPlan {
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
     // LDS of a workgroup: bra rows (one set per wave with one task per wave) and Boys rows
-    size_t lds(bool mx) const { return (mode == 0 ? lds_bytes * (wave ? wave : 1) : 0) + lds_tab[mx ? 1 : 0]; }
+    size_t lds(bool mx) const {
+        return (mode == 0 ? lds_bytes * (wave ? wave : nbl) : 0) + lds_tab[mx ? 1 : 0];
+    }
     bool persist = false;     // persistent launch through per-XCD work counters
     int wave = 0;             // > 0: one task per wave (persistent), this many waves per workgroup
+    bool kr = false;          // register-tiled persistent kernel (ket primitives in registers), FP64
+    int nbl = 1;              // bras per task (register-tiled blocks of Q-adjacent bras)
     int alt = 0;              // 1: the class's alternative workgroup size
     int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / FP32 kernel
 };
@@ -200,6 +205,10 @@ hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int
 int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes);
 int hfx_class_wgs(int cid, int alt);
 hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs);
+int hfx_class_has_kr(int cid, int kp);
+hipError_t hfx_launch_class_kr(int cid, int mode, int kp, int nbl, int nblocks, size_t lds_bytes, hipStream_t stream,
+                               const ClassArgs* args);
+int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, size_t lds_bytes);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);
 }

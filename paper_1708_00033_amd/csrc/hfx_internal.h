@@ -46,7 +46,12 @@ struct ClassArgs {
     int nket_list, knprim;
     const int* __restrict__ split;      // per task: kets below this list position use FP64 (mixed builds)
     const int4* __restrict__ tasks;     // (bra index, first ket, end ket, window code wc | wd << 16); bra -1:
-                                        // empty.  Task 8k + x is entry k of XCD x's queue
+                                        // empty.  Task 8k + x is entry k of XCD x's queue.  Register-tiled
+                                        // plans: bra index | (bras in the block - 1) << 28
+    const double* __restrict__ ketq;    // register-tiled plans: Q of every ket (list order)
+    const int* __restrict__ kpos;       // and its position in its pair class's Q-sorted list
+    double tau;                         // Schwarz threshold
+    int same;                           // bra and ket of the same pair class (ket position <= bra index)
     int win, rs;                        // column window (0: whole rows) and LDS bra-row length (doubles)
     int task_off;                       // static launch: workgroup i runs task task_off + i
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the

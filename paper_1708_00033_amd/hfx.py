@@ -419,7 +419,7 @@ class Context:
     def set_class_tuning(self, cls: int, task_quartets: int = 0, xcd_stripe: int = -1, persistent: int = 0,
                          digest: int = -1):
         """hfx_set_class_tuning: persistent 0 = one workgroup per task, 1 = resident grid with per-XCD
-        queues, 2 = resident grid with one task per wave."""
+        queues, 2 = resident grid with one task per wave, 3 = resident grid, register-tiled (FP64)."""
         self._check(hfx_set_class_tuning(self.ptr, cls, task_quartets, xcd_stripe, persistent, digest))
 
     def set_class_precision(self, cls: int, fp32: int):
@@ -447,12 +447,13 @@ class Context:
         self._check(hfx_plan_count(self.ptr, C.byref(n)))
         out = []
         for i in range(n.value):
-            info = (C.c_longlong * 11)()
+            info = (C.c_longlong * 12)()
             ms = C.c_double()
             self._check(hfx_plan_info(self.ptr, i, info, C.byref(ms)))
             out.append(dict(cls=int(info[0]), ket_nprim=int(info[1]), tasks=int(info[2]), quartets=int(info[3]),
                             prim=int(info[4]), integrals=int(info[5]), launches=int(info[6]), mode=int(info[7]),
-                            wgs=int(info[8]), persistent=int(info[9]), blocks=int(info[10]), ms=ms.value))
+                            wgs=int(info[8]), persistent=int(info[9]), blocks=int(info[10]),
+                            bras_per_task=int(info[11]), ms=ms.value))
         return out
 
     def kernel_times(self):

@@ -341,7 +341,8 @@ def test_scheduling_knobs_do_not_change_results():
     out = torch.empty_like(D)
     for tq, st, pe, dg in [(8192, 1, 0, -1), (1024, 1, 0, -1), (32768, 0, 0, -1), (2048, 1, 1, -1),
                            (256, 0, 1, -1), (32768, 1, 1, -1), (8192, 0, 0, 1), (2048, 1, 1, 1),
-                           (2048, 1, 2, -1), (32768, 0, 2, -1), (8192, 1, 2, 1)]:
+                           (2048, 1, 2, -1), (32768, 0, 2, -1), (8192, 1, 2, 1),
+                           (32768, 0, 3, -1), (2048, 1, 3, -1), (256, 0, 3, -1), (8192, 1, 3, 1)]:
         ctx.set_class_tuning(-1, tq, st, pe, dg)
         ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
         torch.cuda.synchronize()
@@ -354,3 +355,64 @@ def test_scheduling_knobs_do_not_change_results():
     ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
     torch.cuda.synchronize()
     assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+
+
+@pytest.mark.parametrize("digest", [0, 1])
+def test_register_tiled_form_all_classes(four_waters, digest):
+    """Launch form 3 (ket primitives in registers, blocks of two bras with
+    per-lane screening) on every class that has it: F, the quartet count and
+    the per-class counts equal the oracle's; classes without it fall back."""
+    m, B = four_waters
+    ctx = _hfx().Context(digest=digest).load(m)
+    ctx.set_class_tuning(-1, 512, 1, 3, -1)
+    plans = ctx.plans()
+    assert any(p["persistent"] == 3 and p["bras_per_task"] == 2 for p in plans)
+    D = W.random_symmetric(m.nbf, 71, 0.2)
+    F, st = ctx.build_fock(D)
+    ref, _, _ = _fock_ref(B, D)
+    assert np.abs(F - ref).max() < 1e-10 * max(1.0, np.abs(ref).max())
+    _, _, ost = B.jk(D, 1e-10)
+    assert st.quartets_fp64 == ost[0] and st.quartets_fp32 == 0
+    # mixed: the register-tiled classes run FP64, the rest keep their split
+    ctx.configure(precision=_hfx().HFX_PREC_MIXED)
+    Fm, stm = ctx.build_fock(D)
+    assert stm.quartets_fp64 + stm.quartets_fp32 == ost[0]
+    assert np.abs(Fm - ref).max() < 1e-6
+
+
+def test_register_tiled_form_batch_windows_and_shards():
+    """Blocks of bras never cross molecules of a batch; with column windows
+    (above 2048 basis functions) and with shards (bras of one block in
+    different shards) the results equal the default form's."""
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    mols = [W.water_cluster(3, 81), W.water_cluster(1, 82), W.water_cluster(6, 83), W.water_cluster(2, 84)]
+    ctx = _hfx().Context().load_batch(mols)
+    nbf, nocc, off, tot = ctx.layout
+    D = torch.tensor(np.concatenate([W.random_orthonormal_density(int(n), int(o), 40 + i).ravel()
+                                     for i, (n, o) in enumerate(zip(nbf, nocc))]), device="cuda")
+    ref, out = torch.empty_like(D), torch.empty_like(D)
+    st0 = ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, ref.data_ptr(), s, stats=True)
+    ctx.set_class_tuning(-1, 1024, 1, 3, -1)
+    st1 = ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s, stats=True)
+    torch.cuda.synchronize()
+    assert st1.quartets_fp64 == st0.quartets_fp64
+    assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+    for nshards in (2, 3):
+        tot_ = torch.zeros_like(D)
+        part = torch.empty_like(D)
+        for g in range(nshards):
+            ctx.build_2e_shard_dev(D.data_ptr(), 2.0, 1.0, g, nshards, part.data_ptr(), s)
+            tot_ += part
+        torch.cuda.synchronize()
+        assert (tot_ - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+    m = W.water_cluster(112, 5)
+    Dw = torch.tensor(W.random_orthonormal_density(m.nbf, m.nocc, 23), device="cuda")
+    cw = _hfx().Context().load(m)
+    rw, ow = torch.empty_like(Dw), torch.empty_like(Dw)
+    cw.build_2e_dev(Dw.data_ptr(), 2.0, 1.0, rw.data_ptr(), s)
+    cw.set_class_tuning(-1, 8192, 1, 3, -1)
+    assert any(p["persistent"] == 3 for p in cw.plans())
+    cw.build_2e_dev(Dw.data_ptr(), 2.0, 1.0, ow.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert (ow - rw).abs().max().item() <= 1e-13 * rw.abs().max().item()
