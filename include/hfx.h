@@ -64,7 +64,15 @@ typedef struct {
 } hfx_shell;
 
 enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 };
-enum { HFX_DIGEST_LDS = 0, HFX_DIGEST_GLOBAL = 1 };
+/* Digestion of the integrals into the Fock matrix (eq. 2):
+ *   LDS      the bra's rows of the Fock matrix staged in LDS for a task and
+ *            flushed once (algorithm 3's private F_I / F_J buffers);
+ *   GLOBAL   every update a device-wide atomic into one shared matrix;
+ *   PRIVATE  every update an atomic into the copy of the matrix private to
+ *            the XCD the wave runs on (algorithm 2's private Fock matrices,
+ *            one per XCD: 8 copies of sum nbf_m^2 FP64 in HBM), summed by a
+ *            reduction kernel after the class launches. */
+enum { HFX_DIGEST_LDS = 0, HFX_DIGEST_GLOBAL = 1, HFX_DIGEST_PRIVATE = 2 };
 enum { HFX_GUESS_SAD = 0, HFX_GUESS_CORE = 1, HFX_GUESS_LEARNED = 2 };
 
 /* Learned initial-guess network (see the section "Learned initial guess"). */
@@ -77,7 +85,7 @@ typedef struct {
     double fp32_tau;       /* MIXED: FP32 iff Q_ab Q_cd max|D| < fp32_tau (default
                               1e-7); the classes with a d-d bra and a d-d or d-p
                               ket stay FP64 */
-    int digest;            /* HFX_DIGEST_LDS (bra rows staged in LDS) or HFX_DIGEST_GLOBAL */
+    int digest;            /* HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE */
     int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
 } hfx_options;
@@ -170,6 +178,21 @@ hfx_status hfx_build_fock_dev(hfx_ctx *ctx, const double *dD, double *dF, void *
 hfx_status hfx_build_2e_dev(hfx_ctx *ctx, const double *dD, double cj, double ck, double *dG,
                             void *stream, hfx_fock_stats *stats);
 
+/* Several densities in one pass over the screened integrals (the loop
+ * structure shared by UHF, GVB, DFT and CPHF, section 7): each integral is
+ * evaluated once and digested for every density.  dD: ndens densities
+ * (1 <= ndens <= 64), each nbf x nbf FP64 (ragged layout for a batch),
+ * consecutive on the device; dJ, dK (either may be NULL): the J(D_d) and
+ * K(D_d) of each density in the same layout, so that for example an
+ * unrestricted build forms F_a = H + J_a + J_b - K_a and F_b = H + J_a + J_b
+ * - K_b from the alpha and beta densities.  FP64 throughout (the context's
+ * precision is ignored); digestion by device-wide atomics.  Work buffers of
+ * 3 x ndens matrices (and the ket lists' D_cd per density) are allocated on
+ * the first call with a larger ndens and kept by the context.  stats as in
+ * hfx_build_2e_dev (quartets counted once per quartet). */
+hfx_status hfx_build_jk_multi_dev(hfx_ctx *ctx, int ndens, const double *dD, double *dJ, double *dK, void *stream,
+                                  hfx_fock_stats *stats);
+
 /* Capture one Fock build dF = F(dD) on a non-null stream into a HIP graph
  * (an eager build runs first), and replay it.  The graph keeps dD, dF and
  * the context's buffers.  hfx_load, hfx_set_class_tuning, and any change of
@@ -244,7 +267,7 @@ hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
  * fit), FP64 only -- a mixed build evaluates such a class in FP64; classes
  * or ket lists without register-tiled kernels fall back to 1; 4: as 3 with
  * one bra per task) and the digestion (-1: the context's
- * option; HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL; LDS staging needs
+ * option; HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE; LDS staging needs
  * (n_a + n_b) x nbf x 8 bytes <= 160 KiB and falls back to global
  * otherwise).  Re-plans a loaded system; results are unchanged up to the
  * order of floating-point sums.  Set by the autotuner
@@ -271,7 +294,8 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 
 /* Launches of a build: one per (quartet class, ket primitive count).
  * info[12] = {class index, ket primitives per pair, workgroup tasks, unique
- * quartets, primitive quartets, integrals, timed launches, digestion mode,
+ * quartets, primitive quartets, integrals, timed launches, digestion used
+ * (HFX_DIGEST_*),
  * work-items per workgroup, launch form (0..4 as in hfx_set_class_tuning),
  * workgroups of the FP64 kernel, bras per task}; *ms = summed event time of
  * the timed launches (a mixed build times its FP64 and FP32 kernels

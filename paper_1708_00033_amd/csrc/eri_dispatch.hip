@@ -5,12 +5,15 @@
 #define HFX_DECL(cid)                                        \
     extern "C" const void* hfx_class_kernel_##cid(int);      \
     extern "C" const void* hfx_class_kernel_kr_##cid(int);   \
+    extern "C" const void* hfx_class_kernel_multi_##cid(void); \
     extern "C" const void* hfx_schwarz_kernel_##cid(void);
 HFX_FOR_EACH_CID(HFX_DECL)
 
 #define HFX_KPTR(cid) hfx_class_kernel_##cid,
 #define HFX_RPTR(cid) hfx_class_kernel_kr_##cid,
 #define HFX_SPTR(cid) hfx_schwarz_kernel_##cid,
+#define HFX_MPTR(cid) hfx_class_kernel_multi_##cid,
+static const void* (*const kMultiLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_MPTR)};
 static const void* (*const kClassLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_KPTR)};
 static const void* (*const kClassLookupKr[21])(int) = {HFX_FOR_EACH_CID(HFX_RPTR)};
 static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPTR)};
@@ -97,6 +100,21 @@ extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, i
 }
 
 
+// Multi-density kernel of class cid (persistent; args->work set): nblocks
+// workgroups, LDS = the class's FP64 Boys rows.
+extern "C" hipError_t hfx_launch_class_multi(int cid, int nblocks, size_t lds_bytes, hipStream_t stream,
+                                             const ClassArgs* args) {
+    if (nblocks <= 0) return hipSuccess;
+    if (!args->work) return hipErrorInvalidValue;
+    const void* fn = kMultiLookup[cid]();
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    void* kargs[] = {(void*)args};
+    return hipLaunchKernel(fn, dim3(nblocks), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+}
+
 // Largest per-lane private segment (scratch) in bytes and largest register
 // count over every kernel variant of class cid (launch form, digestion,
 // precision, workgroup size), read from the code object's metadata without a
@@ -104,8 +122,8 @@ extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, i
 extern "C" hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs) {
     long long sc = 0;
     int rg = 0;
-    for (int v = 0; v < 32 + 12; ++v) {
-        const void* fn = v < 32 ? kClassLookup[cid](v) : kClassLookupKr[cid](v - 32);
+    for (int v = 0; v < 32 + 12 + 1; ++v) {
+        const void* fn = v < 32 ? kClassLookup[cid](v) : (v < 44 ? kClassLookupKr[cid](v - 32) : kMultiLookup[cid]());
         if (!fn) continue;
         hipFuncAttributes fa;
         const hipError_t e = hipFuncGetAttributes(&fa, fn);

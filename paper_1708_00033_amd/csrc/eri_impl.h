@@ -19,7 +19,9 @@
 // is summed in registers, W_ac/W_ad/W_bc/W_bd go to LDS with ds_add_f64, and
 // only the ket block W_cd goes straight to HBM with global atomics.  At the
 // end of the task the LDS rows are flushed with one atomic per touched
-// element.  MODE 1 (shared global): every update is a global atomic.
+// element.  MODE 1 (global): every update is a global atomic, into one
+// shared W or (private digestion, ClassArgs::wrep) into the copy of W of the
+// XCD the wave runs on; the copies are summed after the class launches.
 #pragma once
 #include "hfx_internal.h"
 
@@ -40,11 +42,14 @@ __device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, in
     }
 }
 
+// dket: the gathered D'_cd of the ket list ([component][ket position]); W
+// receives the J updates and WK the K updates of MODE 1 (one matrix for a
+// Fock build, separate J and K accumulators for a multi-density build).
 template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                        int fc, int fd, int spos, const double* dab, double* jab, double* FI,
-                                       double* FJ, const double* __restrict__ D, double* __restrict__ W, int N,
-                                       int RS, int cb, int db) {
+                                       double* FJ, const double* __restrict__ D, double* W, int N,
+                                       int RS, int cb, int db, const double* __restrict__ dket, double* WK) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
@@ -52,7 +57,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
         // D_cd gathered in ket-list order before the build (coalesced across lanes)
         double dcd[NC * ND];
 #pragma unroll
-        for (int ls = 0; ls < NC * ND; ++ls) dcd[ls] = a.dket[(size_t)ls * a.nket_list + spos];
+        for (int ls = 0; ls < NC * ND; ++ls) dcd[ls] = dket[(size_t)ls * a.nket_list + spos];
 #pragma unroll
         for (int mn = 0; mn < NA * NB; ++mn) {
             double v = 0.0;
@@ -92,7 +97,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int n = 0; n < NB; ++n)
 #pragma unroll
                     for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dbd[n * ND + s];
-                row_add<MODE>(FI + m * RS, W, fa + m, fc + l, N, fc + l - cb, ckg * v);
+                row_add<MODE>(FI + m * RS, WK, fa + m, fc + l, N, fc + l - cb, ckg * v);
             }
     }
     // K: W_bd -= ck g sum_{mu lambda} I D_ac
@@ -111,7 +116,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int m = 0; m < NA; ++m)
 #pragma unroll
                     for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dac[m * NC + l];
-                row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v);
+                row_add<MODE>(FJ + n * RS, WK, fb + n, fd + s, N, fd + s - db, ckg * v);
             }
     }
     // K: W_ad -= ck g sum_{nu lambda} I D_bc
@@ -130,7 +135,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int n = 0; n < NB; ++n)
 #pragma unroll
                     for (int l = 0; l < NC; ++l) v += I[((m * NB + n) * NC + l) * ND + s] * dbc[n * NC + l];
-                row_add<MODE>(FI + m * RS, W, fa + m, fd + s, N, fd + s - db, ckg * v);
+                row_add<MODE>(FI + m * RS, WK, fa + m, fd + s, N, fd + s - db, ckg * v);
             }
     }
     // K: W_bc -= ck g sum_{mu sigma} I D_ad
@@ -149,7 +154,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
                 for (int m = 0; m < NA; ++m)
 #pragma unroll
                     for (int s = 0; s < ND; ++s) v += I[((m * NB + n) * NC + l) * ND + s] * dad[m * ND + s];
-                row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v);
+                row_add<MODE>(FJ + n * RS, WK, fb + n, fc + l, N, fc + l - cb, ckg * v);
             }
     }
 }
@@ -259,14 +264,15 @@ template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_rolled(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                               int fc, int fd, int spos, const double* dab, double* jab,
                                               double* FI, double* FJ, const double* __restrict__ D,
-                                              double* __restrict__ W, int N, int RS, int cb, int db) {
+                                              double* W, int N, int RS, int cb, int db,
+                                              const double* __restrict__ dket, double* WK) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
 #pragma unroll 1
     for (int mn = 0; mn < NA * NB; ++mn) {
         double v = 0.0;
 #pragma unroll 1
-        for (int ls = 0; ls < NC * ND; ++ls) v += I[mn * NC * ND + ls] * a.dket[(size_t)ls * a.nket_list + spos];
+        for (int ls = 0; ls < NC * ND; ++ls) v += I[mn * NC * ND + ls] * dket[(size_t)ls * a.nket_list + spos];
         jab[mn] += g * v;
     }
 #pragma unroll 1
@@ -286,7 +292,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int s = 0; s < ND; ++s)
                     v1 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
-            row_add<MODE>(FI + m * RS, W, fa + m, fc + l, N, fc + l - cb, ckg * v1);
+            row_add<MODE>(FI + m * RS, WK, fa + m, fc + l, N, fc + l - cb, ckg * v1);
         }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n)
@@ -298,7 +304,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int l = 0; l < NC; ++l)
                     v2 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fc + l];
-            row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v2);
+            row_add<MODE>(FJ + n * RS, WK, fb + n, fd + s, N, fd + s - db, ckg * v2);
         }
 #pragma unroll 1
     for (int m = 0; m < NA; ++m)
@@ -310,7 +316,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int l = 0; l < NC; ++l)
                     v3 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
-            row_add<MODE>(FI + m * RS, W, fa + m, fd + s, N, fd + s - db, ckg * v3);
+            row_add<MODE>(FI + m * RS, WK, fa + m, fd + s, N, fd + s - db, ckg * v3);
         }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n)
@@ -322,7 +328,7 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
 #pragma unroll 1
                 for (int s = 0; s < ND; ++s)
                     v4 += I[((m * NB + n) * NC + l) * ND + s] * D[(size_t)(fa + m) * N + fd + s];
-            row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v4);
+            row_add<MODE>(FJ + n * RS, WK, fb + n, fc + l, N, fc + l - cb, ckg * v4);
         }
 }
 
@@ -334,7 +340,8 @@ template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest_pass(int k, const double* I, double g, const ClassArgs& a,
                                             const PairInfo& bra, int fc, int fd, int spos, const double* dab,
                                             double* jab, double* FI, double* FJ, const double* __restrict__ D,
-                                            double* __restrict__ W, int N, int RS, int cb, int db) {
+                                            double* W, int N, int RS, int cb, int db,
+                                            const double* __restrict__ dket, double* WK) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     constexpr int NCD = NC * ND;
@@ -342,7 +349,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
     for (int n = 0; n < NB; ++n) {   // J, bra block (mu = k)
         double v = 0.0;
 #pragma unroll 1
-        for (int ls = 0; ls < NCD; ++ls) v += I[n * NCD + ls] * a.dket[(size_t)ls * a.nket_list + spos];
+        for (int ls = 0; ls < NCD; ++ls) v += I[n * NCD + ls] * dket[(size_t)ls * a.nket_list + spos];
         jab[k * NB + n] += g * v;
     }
 #pragma unroll 1
@@ -362,7 +369,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
         for (int n = 0; n < NB; ++n)
 #pragma unroll 1
             for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fd + s];
-        row_add<MODE>(FI + k * RS, W, fa + k, fc + l, N, fc + l - cb, ckg * v);
+        row_add<MODE>(FI + k * RS, WK, fa + k, fc + l, N, fc + l - cb, ckg * v);
     }
 #pragma unroll 1
     for (int s = 0; s < ND; ++s) {   // K: (k, d_s) -= sum_{n l} I D_bc
@@ -371,7 +378,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
         for (int n = 0; n < NB; ++n)
 #pragma unroll 1
             for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fb + n) * N + fc + l];
-        row_add<MODE>(FI + k * RS, W, fa + k, fd + s, N, fd + s - db, ckg * v);
+        row_add<MODE>(FI + k * RS, WK, fa + k, fd + s, N, fd + s - db, ckg * v);
     }
 #pragma unroll 1
     for (int n = 0; n < NB; ++n) {
@@ -380,14 +387,14 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
             double v = 0.0;
 #pragma unroll 1
             for (int l = 0; l < NC; ++l) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fc + l];
-            row_add<MODE>(FJ + n * RS, W, fb + n, fd + s, N, fd + s - db, ckg * v);
+            row_add<MODE>(FJ + n * RS, WK, fb + n, fd + s, N, fd + s - db, ckg * v);
         }
 #pragma unroll 1
         for (int l = 0; l < NC; ++l) {   // K: (b_n, c_l) -= sum_s I D_ad
             double v = 0.0;
 #pragma unroll 1
             for (int s = 0; s < ND; ++s) v += I[(n * NC + l) * ND + s] * D[(size_t)(fa + k) * N + fd + s];
-            row_add<MODE>(FJ + n * RS, W, fb + n, fc + l, N, fc + l - cb, ckg * v);
+            row_add<MODE>(FJ + n * RS, WK, fb + n, fc + l, N, fc + l - cb, ckg * v);
         }
     }
 }
@@ -467,7 +474,9 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     // the bra's molecule: its blocks of D' and W, leading dimension ld
     const int N = bra.ld;
     const double* __restrict__ Dm = a.D + a.moff[bra.mol];
-    double* __restrict__ Wm = a.W + a.moff[bra.mol];
+    // private digestion: this XCD's own copy of W (algorithm 2's private
+    // Fock matrix, one per XCD instead of one per thread)
+    double* __restrict__ Wm = a.W + a.moff[bra.mol] + (a.wrep ? (size_t)hfx_xcc_id() * a.wrep : 0);
     // LDS bra rows of length RS: whole rows, or (column windows) the task's
     // window of shell c at [0, RS/2) and of shell d at [RS/2, RS) (one region
     // when both windows coincide); column col sits at col - cb (c) / col - db (d)
@@ -511,7 +520,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
                                                       a.knprim, bra.AB, a.ket[s].AB, t64, Ik);
             digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
-                                              db);
+                                              db, a.dket, Wm);
             if (k == 0) ++n64;
         }
     }
@@ -534,9 +543,11 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             ++n32;
         }
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
+                                                a.dket, Wm);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db);
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db, a.dket,
+                                         Wm);
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
     // outside the task's windows)
@@ -607,7 +618,7 @@ __device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, 
     // the block's molecule (shared by its bras): blocks of D', W, leading dimension
     const int N = bra[0].ld;
     const double* __restrict__ Dm = a.D + a.moff[bra[0].mol];
-    double* __restrict__ Wm = a.W + a.moff[bra[0].mol];
+    double* __restrict__ Wm = a.W + a.moff[bra[0].mol] + (a.wrep ? (size_t)hfx_xcc_id() * a.wrep : 0);
     int RS = N, cb = 0, db = 0, half = N;
     if (a.win) {
         RS = a.rs;
@@ -737,6 +748,108 @@ __global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
             continue;
         }
         class_task_kr<E, MODE, KP, NBL>(a, 8 * k + x, t64);
+    }
+}
+
+// Several densities in one pass over the integrals (FP64, global atomics):
+// every quartet of the task is evaluated once and digested for each density
+// d < a.ndens (D'_d, its gathered D'_cd and its J and K accumulators at
+// offsets d dstride / d kstride), the J updates into a.W and the K updates
+// into a.WK.  The bra block's J sums are reduced over each wave per ket
+// iteration (all lanes of a wave iterate together).  Tasks may be blocks of
+// bras (register-tiled plans): each bra keeps the kets of its own screened
+// prefix, the test the planner used.
+template <class E>
+__device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int ti, const double* t64) {
+    constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
+    constexpr int NAB = NA * NB, NI = NAB * NC * ND;
+    constexpr int NT = E::WGS;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int4 task = a.tasks[ti];
+    if (task.x < 0) return;
+    const int r0 = task.x & 0x0fffffff, nb = (task.x >> 28) + 1;
+    const int s0 = task.y, nq = task.z - task.y;
+    const int nwork = E::PASSES ? NA * nq : nq;
+    unsigned n64 = 0;
+    for (int i = 0; i < nb; ++i) {
+        const int r = r0 + i;
+        if (a.nshards > 1 && r % a.nshards != a.shard) continue;   // uniform
+        const PairInfo bra = a.bra[r];
+        const int N = bra.ld;
+        const size_t moff = (size_t)a.moff[bra.mol];
+        const double sbra = bra.a != bra.b ? 2.0 : 1.0;
+        for (int base = 0; base < nwork; base += NT) {
+            const int it = base + tid;
+            bool valid = it < nwork;
+            const int k = E::PASSES ? (valid ? it / nq : 0) : 0;
+            const int s = s0 + (valid ? (E::PASSES ? it % nq : it) : 0);
+            if (valid) valid = a.ketq[s] * bra.Q >= a.tau && !(a.same && a.kpos[s] > r);
+            const int4 kb = a.kbf[s];
+            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+            double I[E::PASSES ? NB * NC * ND : NI];
+            if (valid) {
+                if constexpr (E::PASSES)
+                    E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s,
+                                                              a.nket_list * a.knprim, a.nket_list, a.knprim, bra.AB,
+                                                              a.ket[s].AB, t64, I);
+                else
+                    E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s,
+                                                         a.nket_list * a.knprim, a.nket_list, a.knprim, bra.AB,
+                                                         a.ket[s].AB, t64, I);
+                if (k == 0) ++n64;
+            }
+            for (int d = 0; d < a.ndens; ++d) {
+                const double* __restrict__ Dd = a.D + (size_t)d * a.dstride + moff;
+                double* WJ = a.W + (size_t)d * a.dstride + moff;
+                double* WKd = a.WK + (size_t)d * a.dstride + moff;
+                const double* dket = a.dket + (size_t)d * a.kstride;
+                double dab[NAB], jt[NAB];
+#pragma unroll
+                for (int mn = 0; mn < NAB; ++mn) {
+                    dab[mn] = Dd[(size_t)(bra.bfa + mn / NB) * N + bra.bfb + mn % NB];
+                    jt[mn] = 0.0;
+                }
+                if (valid) {
+                    if constexpr (E::PASSES)
+                        digest_pass<NA, NB, NC, ND, 1>(k, I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd,
+                                                       WJ, N, 0, 0, 0, dket, WKd);
+                    else if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
+                        digest_rolled<NA, NB, NC, ND, 1>(I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd,
+                                                         WJ, N, 0, 0, 0, dket, WKd);
+                    else
+                        digest<NA, NB, NC, ND, 1>(I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd, WJ, N,
+                                                  0, 0, 0, dket, WKd);
+                }
+#pragma unroll
+                for (int mn = 0; mn < NAB; ++mn) {
+                    const double v = wave_sum(jt[mn]);
+                    if (lane == 0 && v != 0.0)
+                        atomicAdd(WJ + (size_t)(bra.bfa + mn / NB) * N + bra.bfb + mn % NB, 2.0 * a.cj * v);
+                }
+            }
+        }
+    }
+    const unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
+    if (lane == 0 && a.counters && c64) atomicAdd(a.counters + 0, c64);
+}
+
+template <class E>
+__global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
+    extern __shared__ __align__(16) double lds[];
+    __shared__ int next_entry;
+    load_boys_lds<E, 0>(a, lds, nullptr);
+    const int x0 = blockIdx.x & 7;
+    for (int q = 0; q < 8;) {
+        const int x = (x0 + q) & 7;
+        if (threadIdx.x == 0) next_entry = (int)atomicAdd(a.work + x, 1ull);
+        __syncthreads();
+        const int k = next_entry;
+        __syncthreads();
+        if (k >= a.qlen) {
+            ++q;
+            continue;
+        }
+        class_task_multi<E>(a, 8 * k + x, lds);
     }
 }
 
@@ -934,6 +1047,7 @@ struct ClassKernelsKr {
     extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
         return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
     }                                                                                                  \
+    extern "C" const void* hfx_class_kernel_multi_##cid(void) { return (const void*)k_class_multi<Eval##cid>; } \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }
 
 // Per-class translation unit of a large class: the full evaluator (Schwarz
@@ -964,4 +1078,5 @@ struct ClassKernelsKr {
     extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
         return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
     }                                                                                                  \
+    extern "C" const void* hfx_class_kernel_multi_##cid(void) { return (const void*)k_class_multi<Eval##cid>; } \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }

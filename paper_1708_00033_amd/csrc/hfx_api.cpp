@@ -55,6 +55,8 @@ static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}}
 
 static hfx_status replan(hfx_ctx* c);
 
+constexpr int kXcds = 8;   // XCDs of an MI355X: private digestion keeps one copy of W per XCD
+
 // A captured build replays the launch arguments (plans, task buffers,
 // precision split) of the moment it was captured: drop it whenever those
 // change, so that hfx_graph_launch reports HFX_ERR_STATE instead of replaying
@@ -100,8 +102,8 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "precision must be HFX_PREC_FP64 or HFX_PREC_MIXED");
     if (!(o->fp32_tau >= 0.0) || !std::isfinite(o->fp32_tau))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "fp32_tau must be finite and >= 0");
-    if (o->digest != HFX_DIGEST_LDS && o->digest != HFX_DIGEST_GLOBAL)
-        return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be HFX_DIGEST_LDS or HFX_DIGEST_GLOBAL");
+    if (o->digest != HFX_DIGEST_LDS && o->digest != HFX_DIGEST_GLOBAL && o->digest != HFX_DIGEST_PRIVATE)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE");
     if (o->task_quartets < 256 || o->task_quartets % 256 != 0 || o->task_quartets > (1 << 24))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be a multiple of 256 in [256, 2^24]");
     return HFX_OK;
@@ -126,6 +128,8 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_kbf);
         dfree(L.d_kpos);
         dfree(L.d_dket);
+        dfree(L.d_dket_multi);
+        L.dket_multi_cap = 0;
     }
     c->ketlists.clear();
     c->host_bra.clear();
@@ -150,6 +154,9 @@ static void release_system(hfx_ctx* c) {
     dfree(c->d_S);
     dfree(c->d_H);
     dfree(c->d_W);
+    dfree(c->d_Wrep);
+    dfree(c->d_multi);
+    c->multi_cap = 0;
     dfree(c->d_Dp);
     dfree(c->d_tmpD);
     dfree(c->d_tmpF);
@@ -344,6 +351,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
     P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;
+    P.priv = digest == HFX_DIGEST_PRIVATE;   // global-atomic kernels into the per-XCD copies
     // workgroup size: the class's alternative (smaller) size when two such
     // workgroups fit in LDS, else its default (a large group keeps the waves
     // per CU up when LDS admits one workgroup per CU)
@@ -484,6 +492,10 @@ static hfx_status replan(hfx_ctx* c) {
     std::stable_sort(c->plans.begin(), c->plans.end(),
                      [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
     HIPCK(dalloc(&c->d_work, 16 * std::max<size_t>(c->plans.size(), 1)));   // FP64 and FP32 launches
+    bool any_priv = false;
+    for (const auto& p : c->plans) any_priv |= p.priv;
+    if (any_priv && !c->d_Wrep) HIPCK(dalloc(&c->d_Wrep, kXcds * c->nelem));
+    if (!any_priv) dfree(c->d_Wrep);
     if (c->timing)
         for (auto& p : c->plans) {
             HIPCK(hipEventCreate(&p.ev0));
@@ -501,7 +513,7 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
     if (persistent < 0 || persistent > 4)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0, 1, 2, 3 or 4");
-    if (digest < -1 || digest > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0 or 1");
+    if (digest < -1 || digest > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0, 1 or 2");
     for (int k = 0; k < 21; ++k)
         if (cid == -1 || cid == k) {
             c->tune_tq[k] = task_quartets;
@@ -1063,7 +1075,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[4] = p.prim;
     info[5] = p.integrals;
     info[6] = p.launches;
-    info[7] = p.mode;
+    info[7] = p.priv ? 2 : p.mode;
     info[8] = hfx_class_wgs(p.cid, p.alt);
     info[9] = p.kr ? c->tune_persist[p.cid] : (p.persist ? (p.wave ? 2 : 1) : 0);
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
@@ -1104,9 +1116,16 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), bufs.Dp, c->d_moff,
                              KL.d_dket, st));
     }
-    bool any_persist = false;
-    for (const auto& P : c->plans) any_persist |= P.persist;
+    bool any_persist = false, any_priv = false;
+    for (const auto& P : c->plans) {
+        any_persist |= P.persist;
+        any_priv |= P.priv;
+    }
     if (any_persist) HIPCK(hfx_fill_u64(bufs.work, 16 * (int)c->plans.size(), st));
+    if (any_priv) {
+        if (!c->d_Wrep) return hfx_fail(c, HFX_ERR_STATE, "build: private digestion without its copies of W");
+        HIPCK(hfx_fill(c->d_Wrep, kXcds * nn, 0.0, st));
+    }
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
@@ -1132,7 +1151,8 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         a.boys64 = c->d_boys64;
         a.boys32 = c->d_boys32;
         a.D = bufs.Dp;
-        a.W = bufs.W;
+        a.W = P.priv ? c->d_Wrep : bufs.W;
+        a.wrep = P.priv ? (long long)nn : 0;
         a.wket = KL.d_wket;
         a.counters = bufs.counters + 2 * cid;
         a.cj = cj;
@@ -1183,6 +1203,7 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
             P.pending = true;
         }
     }
+    if (any_priv) HIPCK(hfx_reduce_replicas(c->d_Wrep, kXcds, nn, bufs.W, st));
     for (auto& KL : c->ketlists)
         HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, c->d_moff, bufs.W,
                               st));
@@ -1236,6 +1257,111 @@ extern "C" hfx_status hfx_build_2e_shard_dev(hfx_ctx* c, const double* dD, doubl
     if (!std::isfinite(cj) || !std::isfinite(ck)) return hfx_fail(c, HFX_ERR_INVALID_ARG, "non-finite cj/ck");
     HIPCK(hipSetDevice(c->opt.device));
     return hfx_build_internal(c, dD, cj, ck, nullptr, dG, (hipStream_t)stream, stats, shard, nshards);
+}
+
+// ---- several densities in one pass ------------------------------------------------
+// Every screened quartet is evaluated once and digested for each density
+// (section 7 of the paper names UHF, GVB, DFT and CPHF as sharing this loop
+// structure: an alpha and a beta density, or one density per perturbation).
+
+extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double* dD, double* dJ, double* dK,
+                                             void* stream, hfx_fock_stats* stats) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (ndens < 1 || ndens > 64 || !dD || (!dJ && !dK))
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_build_jk_multi_dev: ndens in [1, 64], dD and dJ or dK needed");
+    if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_build_jk_multi_dev: nothing loaded");
+    HIPCK(hipSetDevice(c->opt.device));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nn = c->nelem;
+    auto t0 = std::chrono::steady_clock::now();
+    if (c->multi_cap < ndens) {
+        dfree(c->d_multi);
+        c->multi_cap = 0;
+        HIPCK(dalloc(&c->d_multi, 3 * (size_t)ndens * nn));
+        c->multi_cap = ndens;
+    }
+    for (auto& KL : c->ketlists)
+        if (KL.dket_multi_cap < ndens) {
+            dfree(KL.d_dket_multi);
+            KL.dket_multi_cap = 0;
+            HIPCK(dalloc(&KL.d_dket_multi, (size_t)ndens * KL.ncd * KL.n));
+            KL.dket_multi_cap = ndens;
+        }
+    double* Dp = c->d_multi;
+    double* WJ = Dp + (size_t)ndens * nn;
+    double* WK = WJ + (size_t)ndens * nn;
+    HIPCK(hfx_fill_u64(c->d_dmax, 1, st));
+    HIPCK(hfx_fill_u64(c->d_counters, 43, st));
+    for (int d = 0; d < ndens; ++d)
+        HIPCK(hfx_prepare_density(dD + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,
+                                  c->max_ld, Dp + (size_t)d * nn, c->d_dmax, st));
+    HIPCK(hfx_fill(WJ, 2 * (size_t)ndens * nn, 0.0, st));
+    for (auto& KL : c->ketlists)
+        for (int d = 0; d < ndens; ++d)
+            HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]),
+                                 Dp + (size_t)d * nn, c->d_moff, KL.d_dket_multi + (size_t)d * KL.ncd * KL.n, st));
+    HIPCK(hfx_fill_u64(c->d_work, 16 * (int)c->plans.size(), st));
+    for (size_t pi = 0; pi < c->plans.size(); ++pi) {
+        const SubPlan& P = c->plans[pi];
+        const KetList& KL = c->ketlists[P.list];
+        ClassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.bra = c->d_pairs[P.B];
+        a.ket = KL.d_pairs;
+        a.kbf = KL.d_kbf;
+        a.prim = c->d_prim;
+        a.kprim = KL.d_soa;
+        a.nket_list = KL.n;
+        a.knprim = KL.kp;
+        a.tasks = P.d_tasks;
+        a.moff = c->d_moff;
+        a.boys64 = c->d_boys64;
+        a.boys32 = c->d_boys32;
+        a.D = Dp;
+        a.W = WJ;
+        a.WK = WK;
+        a.dket = KL.d_dket_multi;
+        a.counters = c->d_counters + 2 * P.cid;
+        a.cj = 1.0;    // J updates into W: (W + W^T)/8 = J
+        a.ck = -1.0;   // K updates into WK: (WK + WK^T)/8 = K
+        a.nshards = 1;
+        a.work = c->d_work + 16 * pi;
+        a.qlen = P.ntask / 8;
+        a.ketq = KL.d_q;
+        a.kpos = KL.d_kpos;
+        a.tau = c->opt.schwarz_tau;
+        a.same = P.B == P.K;
+        a.ndens = ndens;
+        a.dstride = (long long)nn;
+        a.kstride = (long long)KL.ncd * KL.n;
+        const int nblocks = ((std::min(P.ntask, 2048) + 7) / 8) * 8;   // resident or queued: queues drain either way
+        HIPCK(hfx_launch_class_multi(P.cid, nblocks, P.lds_tab[0], st, &a));
+    }
+    for (int d = 0; d < ndens; ++d) {
+        if (dJ)
+            HIPCK(hfx_assemble(nullptr, WJ + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,
+                               c->max_ld, dJ + (size_t)d * nn, c->d_bad, st));
+        if (dK)
+            HIPCK(hfx_assemble(nullptr, WK + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,
+                               c->max_ld, dK + (size_t)d * nn, c->d_bad, st));
+    }
+    c->last_stream = st;
+    if (stats) {
+        HIPCK(hipStreamSynchronize(st));
+        unsigned long long cnt[42];
+        int bad = 0;
+        HIPCK(hipMemcpy(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost));
+        stats->quartets_fp64 = stats->quartets_fp32 = stats->integrals = stats->prim_quartets = 0;
+        for (int k = 0; k < 21; ++k) {
+            stats->quartets_fp64 += (long long)cnt[2 * k];
+            stats->integrals += c->totals[k].integrals;
+            stats->prim_quartets += c->totals[k].prim;
+        }
+        stats->t_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (bad) return hfx_fail(c, HFX_ERR_NUMERICAL, "non-finite value in J or K");
+    }
+    return HFX_OK;
 }
 
 // ---- HIP graph of one build -------------------------------------------------------

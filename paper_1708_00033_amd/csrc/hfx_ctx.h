@@ -25,6 +25,8 @@ struct KetList {
     double* d_soa = nullptr;
     double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
     double* d_dket = nullptr;   // D'_cd of every ket, gathered per build, same layout
+    double* d_dket_multi = nullptr;   // the same for each density of a multi-density build
+    int dket_multi_cap = 0;           // densities it holds
     int4* d_kbf = nullptr;      // per ket: (bfa, bfb, a, b)
     int* d_kpos = nullptr;      // per ket: position in its pair class's Q-sorted list
     int ncd = 1;
@@ -54,6 +56,7 @@ struct SubPlan {
     bool persist = false;     // persistent launch through per-XCD work counters
     int wave = 0;             // > 0: one task per wave (persistent), this many waves per workgroup
     bool kr = false;          // register-tiled persistent kernel (ket primitives in registers), FP64
+    bool priv = false;        // private digestion: global atomics into the per-XCD copies of W
     int nbl = 1;              // bras per task (register-tiled blocks of Q-adjacent bras)
     int alt = 0;              // 1: the class's alternative workgroup size
     int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / FP32 kernel
@@ -128,6 +131,10 @@ struct hfx_ctx {
     double* d_S = nullptr;
     double* d_H = nullptr;
     double* d_W = nullptr;
+    double* d_Wrep = nullptr;   // private digestion: 8 per-XCD copies of W (allocated by plans that use it)
+    // multi-density builds: D' and the J and K accumulators of each density
+    double* d_multi = nullptr;
+    int multi_cap = 0;
     double* d_Dp = nullptr;
     double* d_tmpD = nullptr;   // host-variant staging
     double* d_tmpF = nullptr;
@@ -177,6 +184,7 @@ extern "C" {
 hipError_t hfx_prepare_density(const double* D, const double* cs, int nmol, const long long* moff, const int* mdim,
                                const int* mboff, int max_ld, double* Dp, unsigned long long* dmax_bits, hipStream_t st);
 hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st);
+hipError_t hfx_reduce_replicas(const double* rep, int nrep, size_t n, double* W, hipStream_t st);
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t hfx_split(const PairInfo* bra, const double* ketq, const int4* tasks, int ntask, double fp32_tau,
                      const unsigned long long* dmax_bits, int* split, hipStream_t st);
@@ -209,6 +217,7 @@ int hfx_class_has_kr(int cid, int kp);
 hipError_t hfx_launch_class_kr(int cid, int mode, int kp, int nbl, int nblocks, size_t lds_bytes, hipStream_t stream,
                                const ClassArgs* args);
 int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, size_t lds_bytes);
+hipError_t hfx_launch_class_multi(int cid, int nblocks, size_t lds_bytes, hipStream_t stream, const ClassArgs* args);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);
 }

@@ -52,6 +52,14 @@ struct ClassArgs {
     const int* __restrict__ kpos;       // and its position in its pair class's Q-sorted list
     double tau;                         // Schwarz threshold
     int same;                           // bra and ket of the same pair class (ket position <= bra index)
+    long long wrep;                     // private digestion: elements between the per-XCD replicas of W
+                                        // (W is replica 0); 0: one shared W
+    // multi-density builds (k_class_multi): ndens densities D' (and their J
+    // accumulators W, K accumulators WK) dstride elements apart, their
+    // gathered D'_cd kstride elements apart
+    int ndens;
+    long long dstride, kstride;
+    double* WK;
     int win, rs;                        // column window (0: whole rows) and LDS bra-row length (doubles)
     int task_off;                       // static launch: workgroup i runs task task_off + i
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
@@ -69,6 +77,15 @@ struct ClassArgs {
     int shard, nshards;                 // only bras with r % nshards == shard (1 shard: all)
     double cj, ck;                      // W_ab += cj*2 g D_cd ; W_ac -= ck g D_bd
 };
+
+// Index (0..7) of the accelerator complex die (XCD) the wave runs on, read
+// from the hardware register.  It only selects which private copy of the
+// accumulator a wave adds into: device-wide atomics keep any choice correct.
+__device__ __forceinline__ int hfx_xcc_id() {
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return (int)(x & 7u);
+}
 
 // Constant address space: loads through such a pointer at a wave-uniform
 // address become scalar (SMEM) loads.

@@ -93,6 +93,16 @@ __global__ void k_assemble(const double* __restrict__ H, const double* __restric
     }
 }
 
+// W += sum of the nrep private copies of W (replica x at x * n): the
+// reduction of algorithm 2's private Fock matrices, here one per XCD.
+__global__ void k_reduce_replicas(const double* __restrict__ rep, int nrep, size_t n, double* __restrict__ W) {
+    for (size_t i = (size_t)blockIdx.x * MISC_WG + threadIdx.x; i < n; i += (size_t)gridDim.x * MISC_WG) {
+        double v = 0.0;
+        for (int x = 0; x < nrep; ++x) v += rep[(size_t)x * n + i];
+        W[i] += v;
+    }
+}
+
 // dket[comp][s] = D'_cd of ket pair s of one list (component comp of its
 // block), so that the class kernels read it coalesced by ket position.
 __global__ void k_gather_ket(const PairInfo* __restrict__ kets, int n, int nc, int nd, const double* __restrict__ D,
@@ -408,6 +418,11 @@ hipError_t hfx_prepare_density(const double* D, const double* cs, int nmol, cons
 hipError_t hfx_fill(double* p, size_t n, double v, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(MISC_WG), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t hfx_reduce_replicas(const double* rep, int nrep, size_t n, double* W, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_replicas, dim3(grid_for(n)), dim3(MISC_WG), 0, st, rep, nrep, n, W);
     return hipGetLastError();
 }
 hipError_t hfx_fill_u64(unsigned long long* p, int n, hipStream_t st) {

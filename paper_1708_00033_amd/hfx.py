@@ -40,7 +40,7 @@ HFX_ERR_STATE = 6
 STATUS_NAMES = {0: "HFX_OK", 1: "HFX_ERR_INVALID_ARG", 2: "HFX_ERR_OOM", 3: "HFX_ERR_DEVICE",
                 4: "HFX_ERR_NOT_CONVERGED", 5: "HFX_ERR_NUMERICAL", 6: "HFX_ERR_STATE"}
 HFX_PREC_FP64, HFX_PREC_MIXED = 0, 1
-HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL = 0, 1
+HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL, HFX_DIGEST_PRIVATE = 0, 1, 2
 HFX_GUESS_SAD, HFX_GUESS_CORE, HFX_GUESS_LEARNED = 0, 1, 2
 GUESS_NFEAT = 164
 GUESS_HEAD_OUT = (225, 30, 4)
@@ -101,6 +101,8 @@ _sigs = {
                                 C.c_void_p, C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_build_2e_noalloc_dev": ([_ctx_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                                   C.POINTER(hfx_fock_stats)], C.c_int),
+    "hfx_build_jk_multi_dev": ([_ctx_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.POINTER(hfx_fock_stats)], C.c_int),
     "hfx_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp, _dp, _dp], C.c_int),
     "hfx_batch_scf": ([_ctx_p, C.POINTER(hfx_scf_options), C.POINTER(hfx_scf_result), _dp], C.c_int),
     "hfx_configure": ([_ctx_p, C.POINTER(hfx_options)], C.c_int),
@@ -312,6 +314,16 @@ class Context:
         st = hfx_fock_stats() if stats else None
         self._check(hfx_build_2e_shard_dev(self.ptr, C.c_void_p(dD_ptr), cj, ck, shard, nshards, C.c_void_p(dG_ptr),
                                            C.c_void_p(stream), C.byref(st) if stats else None))
+        return st
+
+    def build_jk_multi_dev(self, ndens: int, dD_ptr: int, dJ_ptr: int, dK_ptr: int, stream: int = 0,
+                           stats: bool = False):
+        """hfx_build_jk_multi_dev: J and K of ndens consecutive densities from one pass over the integrals
+        (dJ_ptr / dK_ptr may be 0)."""
+        st = hfx_fock_stats() if stats else None
+        self._check(hfx_build_jk_multi_dev(self.ptr, int(ndens), C.c_void_p(dD_ptr), C.c_void_p(dJ_ptr or None),
+                                           C.c_void_p(dK_ptr or None), C.c_void_p(stream),
+                                           C.byref(st) if stats else None))
         return st
 
     def build_2e_noalloc_dev(self, dD_ptr: int, cj: float, ck: float, dG_ptr: int, stream: int = 0,

@@ -342,7 +342,8 @@ def test_scheduling_knobs_do_not_change_results():
     for tq, st, pe, dg in [(8192, 1, 0, -1), (1024, 1, 0, -1), (32768, 0, 0, -1), (2048, 1, 1, -1),
                            (256, 0, 1, -1), (32768, 1, 1, -1), (8192, 0, 0, 1), (2048, 1, 1, 1),
                            (2048, 1, 2, -1), (32768, 0, 2, -1), (8192, 1, 2, 1),
-                           (32768, 0, 3, -1), (2048, 1, 3, -1), (256, 0, 3, -1), (8192, 1, 3, 1)]:
+                           (32768, 0, 3, -1), (2048, 1, 3, -1), (256, 0, 3, -1), (8192, 1, 3, 1),
+                           (8192, 1, 0, 2), (2048, 1, 1, 2), (32768, 0, 2, 2), (2048, 0, 3, 2)]:
         ctx.set_class_tuning(-1, tq, st, pe, dg)
         ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
         torch.cuda.synchronize()
@@ -416,3 +417,124 @@ def test_register_tiled_form_batch_windows_and_shards():
     cw.build_2e_dev(Dw.data_ptr(), 2.0, 1.0, ow.data_ptr(), s)
     torch.cuda.synchronize()
     assert (ow - rw).abs().max().item() <= 1e-13 * rw.abs().max().item()
+
+
+@pytest.mark.parametrize("persistent", [0, 1, 2])
+def test_private_digestion_all_classes(four_waters, persistent):
+    """Per-XCD private copies of the Fock matrix (algorithm 2's private Fock
+    matrices, one per XCD) reduced after the class launches: F equals the
+    oracle's for every class and launch form, and J, K separately."""
+    import torch
+    m, B = four_waters
+    hfx = _hfx()
+    ctx = hfx.Context(digest=hfx.HFX_DIGEST_PRIVATE).load(m)
+    ctx.set_class_tuning(-1, 1024, 1, persistent, -1)
+    assert {p["mode"] for p in ctx.plans()} == {2}
+    D = W.random_symmetric(m.nbf, 73, 0.2)
+    F, st = ctx.build_fock(D)
+    ref, J, K = _fock_ref(B, D)
+    assert np.abs(F - ref).max() < 1e-10 * max(1.0, np.abs(ref).max())
+    dD = torch.tensor(D, device="cuda")
+    G = torch.empty_like(dD)
+    s = torch.cuda.current_stream().cuda_stream
+    ctx.build_2e_dev(dD.data_ptr(), 0.0, -1.0, G.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert np.abs(G.cpu().numpy() - K).max() < 1e-10
+
+
+def test_private_digestion_batch_and_mixed_with_other_digestions():
+    """Per class a different digestion (LDS, shared global, private) in one
+    build of a batch, FP64 and mixed: equal to the all-LDS build."""
+    import torch
+    hfx = _hfx()
+    s = torch.cuda.current_stream().cuda_stream
+    mols = [W.water_cluster(5, 85), W.water_cluster(2, 86)]
+    ctx = hfx.Context().load_batch(mols)
+    nbf, nocc, off, tot = ctx.layout
+    D = torch.tensor(np.concatenate([W.random_orthonormal_density(int(n), int(o), 50 + i).ravel()
+                                     for i, (n, o) in enumerate(zip(nbf, nocc))]), device="cuda")
+    ref, out = torch.empty_like(D), torch.empty_like(D)
+    ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, ref.data_ptr(), s)
+    for k in range(21):
+        ctx.set_class_tuning(k, 2048, 1, k % 3, [0, 1, 2][(k // 3) % 3])
+    assert {p["mode"] for p in ctx.plans()} == {0, 1, 2}
+    ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
+    ctx.configure(precision=hfx.HFX_PREC_MIXED)
+    st = ctx.build_2e_dev(D.data_ptr(), 2.0, 1.0, out.data_ptr(), s, stats=True)
+    torch.cuda.synchronize()
+    assert st.quartets_fp32 > 0
+    assert (out - ref).abs().max().item() < 1e-6
+
+
+def test_multi_density_jk_against_oracle(four_waters):
+    """Three densities in one pass over the integrals: J(D_d) and K(D_d) of
+    each equal the oracle's, the quartets are counted once, and an
+    unrestricted alpha/beta Fock pair formed from them equals the one formed
+    from single-density builds."""
+    import torch
+    m, B = four_waters
+    hfx = _hfx()
+    n = m.nbf
+    Ds = [W.random_symmetric(n, 90 + d, 0.2) for d in range(3)]
+    dD = torch.tensor(np.stack(Ds), device="cuda")
+    dJ, dK = torch.empty_like(dD), torch.empty_like(dD)
+    s = torch.cuda.current_stream().cuda_stream
+    for tuning in [None, (512, 1, 3, -1), (1024, 1, 1, 2)]:
+        ctx = hfx.Context().load(m)
+        if tuning:
+            ctx.set_class_tuning(-1, *tuning)
+        st = ctx.build_jk_multi_dev(3, dD.data_ptr(), dJ.data_ptr(), dK.data_ptr(), s, stats=True)
+        torch.cuda.synchronize()
+        _, _, ost = B.jk(Ds[0], 1e-10)
+        assert st.quartets_fp64 == ost[0]
+        J, K = dJ.cpu().numpy(), dK.cpu().numpy()
+        for d in range(3):
+            Jo, Ko, _ = B.jk(Ds[d], 1e-10)
+            assert np.abs(J[d] - Jo).max() < 1e-10, (tuning, d)
+            assert np.abs(K[d] - Ko).max() < 1e-10, (tuning, d)
+    # unrestricted pair from one pass vs from single-density builds
+    Fa = J[0] + J[1] - K[0]
+    G = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ctx.build_2e_dev(dD[0].data_ptr(), 1.0, 1.0, G.data_ptr(), s)   # J_a - K_a
+    Jb = torch.empty_like(G)
+    ctx.build_2e_dev(dD[1].data_ptr(), 1.0, 0.0, Jb.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert np.abs(Fa - (G + Jb).cpu().numpy()).max() < 1e-12 * np.abs(Fa).max()
+    # only K requested
+    dK2 = torch.empty_like(dD)
+    ctx.build_jk_multi_dev(3, dD.data_ptr(), 0, dK2.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert (dK2 - dK).abs().max().item() < 1e-12
+
+
+def test_multi_density_batch_and_limits():
+    """A batch (ragged layout per density) and argument checks."""
+    import torch
+    hfx = _hfx()
+    import oracle
+    mols = [W.water_cluster(2, 95), W.water_cluster(1, 96)]
+    ctx = hfx.Context().load_batch(mols)
+    nbf, nocc, off, tot = ctx.layout
+    Ds = [np.concatenate([W.random_symmetric(int(nb), 100 + 10 * d + i, 0.2).ravel() for i, nb in enumerate(nbf)])
+          for d in range(2)]
+    dD = torch.tensor(np.stack(Ds), device="cuda")
+    dJ, dK = torch.empty_like(dD), torch.empty_like(dD)
+    s = torch.cuda.current_stream().cuda_stream
+    ctx.build_jk_multi_dev(2, dD.data_ptr(), dJ.data_ptr(), dK.data_ptr(), s)
+    torch.cuda.synchronize()
+    J, K = dJ.cpu().numpy(), dK.cpu().numpy()
+    for i, mol in enumerate(mols):
+        Bm = oracle.Basis(mol)
+        nb = int(nbf[i])
+        sl = slice(int(off[i]), int(off[i]) + nb * nb)
+        for d in range(2):
+            Jo, Ko, _ = Bm.jk(Ds[d][sl].reshape(nb, nb), 1e-10)
+            assert np.abs(J[d][sl].reshape(nb, nb) - Jo).max() < 1e-10
+            assert np.abs(K[d][sl].reshape(nb, nb) - Ko).max() < 1e-10
+    for bad in (0, 65):
+        with pytest.raises(hfx.HfxError):
+            ctx.build_jk_multi_dev(bad, dD.data_ptr(), dJ.data_ptr(), dK.data_ptr(), s)
+    with pytest.raises(hfx.HfxError):
+        ctx.build_jk_multi_dev(2, dD.data_ptr(), 0, 0, s)
