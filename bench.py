@@ -62,10 +62,51 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(mol, D, target_s=15.0):
+def host_cpu():
+    """The host's processor as lscpu reports it, and the CPUs this process may use."""
+    import subprocess
+    kv = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            kv[k.strip()] = v.strip()
+    except Exception:
+        pass
+
+    def num(k):
+        try:
+            return int(kv.get(k, ""))
+        except ValueError:
+            return None
+    return {"model": kv.get("Model name"), "sockets": num("Socket(s)"), "cores_per_socket": num("Core(s) per socket"),
+            "threads_per_core": num("Thread(s) per core"), "cpus_online": num("CPU(s)"),
+            "cpus_usable": len(os.sched_getaffinity(0))}
+
+
+_ONE_THREAD_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+import numpy as np, oracle, workloads as W
+m = W.cluster64_config()
+D = np.load(%r)
+B = oracle.Basis(m)
+B.schwarz()
+t0 = time.time()
+_, _, st = B.jk(D, 1e-10, stride=%d, phase=0)
+dt = time.time() - t0
+print(json.dumps({"quartets": st[0], "seconds": dt, "threads": oracle.num_threads()}))
+"""
+
+
+def cpu_baseline(mol, D, target_s=15.0, one_thread_s=6.0):
     """The CPU oracle's 8-fold Fock build on a bounded sample of the same
     workload: every stride-th bra shell pair (all its kets), sized for about
-    target_s seconds; quartets/s of the sample."""
+    target_s seconds, with the OpenMP threads the process has; then a smaller
+    sample on one thread (a child process with OMP_NUM_THREADS=1)."""
+    import subprocess
+    import tempfile
+    import numpy as np
     import oracle
     B = oracle.Basis(mol)
     B.schwarz()
@@ -79,11 +120,27 @@ def cpu_baseline(mol, D, target_s=15.0):
         if dt2 >= 0.6 * target_s or stride == 1:
             break
         stride = max(1, int(stride * max(dt2, 0.05) / target_s))
-    stride2 = stride
-    return dict(value=st2[0] / dt2, unit="quartets/s", cores=nthreads, kind="oracle",
-                sample=f"bra shell pairs with index % {stride2} == 0 (all their kets): {st2[0]} screened quartets, "
-                       f"{st2[1]} integrals in {dt2:.1f} s, FP64 McMurchie-Davidson, OpenMP over bra pairs",
-                seconds=dt2)
+    rate = st2[0] / dt2
+    one = None
+    with tempfile.TemporaryDirectory() as td:
+        dpath = os.path.join(td, "D.npy")
+        np.save(dpath, D)
+        # one thread at the sample's per-thread rate: stride scaled to about one_thread_s seconds
+        s1 = max(stride, int(stride * nthreads * dt2 / one_thread_s))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        try:
+            out = subprocess.run([sys.executable, "-c", _ONE_THREAD_SAMPLE % (ROOT, dpath, s1)], env=env,
+                                 capture_output=True, text=True, timeout=300)
+            r1 = json.loads(out.stdout.strip().splitlines()[-1])
+            one = {"value": r1["quartets"] / r1["seconds"], "threads": r1["threads"], "quartets": r1["quartets"],
+                   "seconds": round(r1["seconds"], 2), "stride": s1}
+        except Exception as e:   # reported, not fatal: the multi-threaded sample is the baseline
+            one = {"error": str(e)[:200]}
+    return dict(value=rate, unit="quartets/s", cores=nthreads, kind="oracle",
+                sample=f"bra shell pairs with index % {stride} == 0 (all their kets): {st2[0]} screened quartets, "
+                       f"{st2[1]} integrals in {dt2:.1f} s, FP64 McMurchie-Davidson, OpenMP over bra pairs, "
+                       f"{nthreads} threads",
+                host=host_cpu(), one_thread=one, seconds=dt2)
 
 
 def batched_bench(args, log):
@@ -190,12 +247,48 @@ def batched_bench(args, log):
             "autotune": autotune.summary(tuning)}
 
 
+def graphene_bench(args, log):
+    """The paper's own workload shape (section 5.2, Table 4): AB-stacked
+    graphene bilayers with 15 basis functions per carbon in SP and d shells
+    (synthetic exponents), one FP64 Fock build each from a projector density,
+    default launch configuration."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1708_00033_amd import hfx
+    out = {"basis": "synthetic split-valence with d: 1s (6 primitives), 2sp (3), 3sp (1), d (1) per carbon",
+           "systems": {}}
+    sp = torch.cuda.current_stream().cuda_stream
+    for name in [x for x in args.graphene.split(",") if x]:
+        mol = W.graphene_bilayer(W.GRAPHENE_SIZES[name])
+        t0 = time.time()
+        ctx = hfx.Context(device=0).load(mol)
+        t_load = time.time() - t0
+        counts = ctx.class_counts()
+        q = int(counts[:, 0].sum())
+        D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 7), device="cuda:0")
+        F = torch.empty_like(D)
+        ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sp, stats=True)
+        dt = time.perf_counter() - t
+        if st.quartets_fp64 != q:
+            raise RuntimeError(f"graphene {name}: evaluated {st.quartets_fp64} quartets, planned {q}")
+        out["systems"][name] = {"atoms": mol.natom, "basis_functions": mol.nbf, "load_s": t_load,
+                                "quartets_per_build": q, "integrals_per_build": int(counts[:, 1].sum()),
+                                "primitive_quartets_per_build": int(counts[:, 2].sum()), "build_s": dt,
+                                "quartets_per_s": q / dt}
+        log(f"graphene {name}: {mol.nbf} BF, {q:.3e} quartets, build {dt:.2f} s")
+    return out
+
+
 def large_bench(args, log):
-    """512 waters (9728 basis functions), Schwarz tau 1e-11: one GPU's share
-    (bra pairs r with r mod G = 0) of a G-GPU build, FP64, mixed with every
-    class's FP32 kernel, and mixed with the FP32 kernel only for the classes
-    it ran faster, from a rank-2560 projector density; with --large-scf also
-    full SCF."""
+    """512 waters (9728 basis functions), Schwarz tau 1e-11: the full build
+    (or one GPU's share, bra pairs r with r mod G = 0, of a G-GPU build) in
+    FP64 and mixed with every class's FP32 kernel (with --large-tuned also
+    mixed with the FP32 kernel only for the classes it ran faster), from a
+    rank-2560 projector density; with --large-scf also full SCF."""
     import numpy as np
     import torch
     import workloads as W
@@ -214,16 +307,17 @@ def large_bench(args, log):
     Gmx = torch.empty_like(D)
     sp = torch.cuda.current_stream(dev).cuda_stream
     out = {"workload": f"512-water jittered lattice cluster, seed 3, 5120 shells, 9728 basis functions, "
-                       f"Schwarz tau 1e-11, projector density of rank 2560; one GPU's share (1/{G} of the bra "
-                       f"pairs) of a {G}-GPU build",
+                       f"Schwarz tau 1e-11, projector density of rank 2560"
+                       + ("" if G == 1 else f"; one GPU's share (1/{G} of the bra pairs) of a {G}-GPU build"),
            "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
            "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load, "shards": G,
            "digest_modes": sorted(set(p["mode"] for p in ctx.plans()))}
     Gtn = torch.empty_like(D)
     class_ms = {}
-    for prec, Go, tag in (() if args.large_no_builds else
-                          ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"),
-                           (hfx.HFX_PREC_MIXED, Gtn, "mixed_tuned"))):
+    legs = ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"))
+    if args.large_tuned:
+        legs += ((hfx.HFX_PREC_MIXED, Gtn, "mixed_tuned"),)
+    for prec, Go, tag in (() if args.large_no_builds else legs):
         if tag == "mixed_tuned":
             # per class, the FP32 kernel only where the all-FP32 build ran the class faster
             for k in range(21):
@@ -239,7 +333,8 @@ def large_bench(args, log):
         ctx.kernel_timing(False)
         class_ms[tag] = ms
         q = int(st.quartets_fp64 + st.quartets_fp32)
-        if G == 1 and q != quartets:
+        planned_share = int(sum(p["quartets"] for p in ctx.plans())) if G == 1 else None
+        if G == 1 and (q != quartets or q != planned_share):
             raise RuntimeError(f"evaluated {q} quartets, planned {quartets}")
         out[tag] = {"share_build_s": dt, "share_quartets": q, "quartets_per_s": q / dt,
                     "quartets_fp32": int(st.quartets_fp32),
@@ -249,10 +344,12 @@ def large_bench(args, log):
         out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
         out["mixed"]["dE_vs_fp64_at_fixed_D"] = float(0.5 * torch.sum(D * (Gmx - G64)).item())
         out["mixed"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed"]["share_build_s"]
-        out["mixed_tuned"]["max_abs_dG_vs_fp64"] = (Gtn - G64).abs().max().item()
-        out["mixed_tuned"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed_tuned"]["share_build_s"]
-        out["mixed_tuned"]["fp32_classes"] = [hfx.CLASS_NAMES[k] for k in range(21)
-                                              if class_ms["mixed"][k] < class_ms["fp64"][k]]
+        out["mixed"]["fraction_quartets_fp32"] = out["mixed"]["quartets_fp32"] / max(1, out["mixed"]["share_quartets"])
+        if args.large_tuned:
+            out["mixed_tuned"]["max_abs_dG_vs_fp64"] = (Gtn - G64).abs().max().item()
+            out["mixed_tuned"]["speedup_vs_fp64"] = out["fp64"]["share_build_s"] / out["mixed_tuned"]["share_build_s"]
+            out["mixed_tuned"]["fp32_classes"] = [hfx.CLASS_NAMES[k] for k in range(21)
+                                                  if class_ms["mixed"][k] < class_ms["fp64"][k]]
         for k in range(21):
             ctx.set_class_precision(k, 1)
     scf_runs = {"none": (), "fp64": ("fp64",), "mixed": ("mixed",), "both": ("fp64", "mixed")}[args.large_scf]
@@ -275,11 +372,17 @@ def main():
     ap.add_argument("--task", type=int, default=8192)
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
-    ap.add_argument("--large", action="store_true", help="also time FP64 and mixed builds of 512 waters")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512-water FP64 and mixed builds")
+    ap.add_argument("--large-tuned", action="store_true",
+                    help="512 waters: also a mixed build with the FP32 kernel only where it ran faster")
+    ap.add_argument("--no-graphene", action="store_true", help="skip the graphene bilayers")
+    ap.add_argument("--graphene", default="0.5nm,1nm,1.5nm",
+                    help="graphene bilayers to build (of 0.5nm, 1nm, 1.5nm, 2nm, 5nm)")
     ap.add_argument("--large-scf", default="none", choices=["none", "fp64", "mixed", "both"],
                     help="with --large: full SCF in these precisions")
     ap.add_argument("--large-no-builds", action="store_true", help="with --large: skip the build timings")
-    ap.add_argument("--large-shards", type=int, default=8, help="with --large: time one GPU's share of this many")
+    ap.add_argument("--large-shards", type=int, default=1,
+                    help="512 waters: time one GPU's share of a build over this many GPUs (1: the full build)")
     ap.add_argument("--only-large", action="store_true", help="run only the 512-water part")
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
     ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
@@ -376,6 +479,61 @@ def main():
         fp32_classes = [k for k, v in ptab.items() if v["fp32"]]
     dtmx, msmx, nmx, plansmx, stmx = timed(args.steps, Fmx, hfx.HFX_PREC_MIXED)
     quartets = int(counts[:, 0].sum())
+    # every planned quartet is evaluated (the timed builds run the same plans as these counted ones)
+    for tag, st_ in (("fp64", st64), ("mixed", stmx)):
+        if st_.quartets_fp64 + st_.quartets_fp32 != quartets:
+            raise RuntimeError(f"{tag} build evaluated {st_.quartets_fp64 + st_.quartets_fp32} quartets, "
+                               f"planned {quartets}")
+    ctx.configure(precision=hfx.HFX_PREC_FP64)
+
+    # the three digestions of eq. 2 on the same launch form, per class
+    digestion = {}
+    for dg, name in ((hfx.HFX_DIGEST_LDS, "lds_staged"), (hfx.HFX_DIGEST_GLOBAL, "global_atomic"),
+                     (hfx.HFX_DIGEST_PRIVATE, "private_per_xcd")):
+        ctx.set_class_tuning(-1, 32768, 0, 1, dg)
+        ctx.build_fock_dev(D.data_ptr(), F64.data_ptr(), sptr)
+        torch.cuda.synchronize()
+        ctx.kernel_timing(True)
+        t = time.perf_counter()
+        for _ in range(2):
+            ctx.build_fock_dev(D.data_ptr(), Fmx.data_ptr(), sptr)
+        torch.cuda.synchronize()
+        dtd = (time.perf_counter() - t) / 2
+        msd, nd = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        digestion[name] = {"build_ms": dtd * 1e3, "class_ms": [round(float(x) / 2, 3) for x in msd],
+                           "max_abs_dF_vs_autotuned": (Fmx - F64).abs().max().item()}
+    digestion["classes"] = list(hfx.CLASS_NAMES)
+    digestion["launch_form"] = "persistent, 32768 quartets per task, no striping (the same for all three)"
+    if tuning is not None:
+        autotune.apply(ctx, tuning)
+    else:
+        ctx.set_class_tuning(-1, 0, -1, 0, -1)
+    log("digestion comparison: " + ", ".join(f"{k} {v['build_ms']:.1f} ms" for k, v in digestion.items()
+                                           if isinstance(v, dict)))
+
+    # several densities in one pass over the integrals (alpha and beta of an unrestricted build)
+    Db = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 45), device=dev)
+    DD = torch.stack([D, Db])
+    JJ, KK = torch.empty_like(DD), torch.empty_like(DD)
+    ctx.build_jk_multi_dev(2, DD.data_ptr(), JJ.data_ptr(), KK.data_ptr(), sptr)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stm2 = ctx.build_jk_multi_dev(2, DD.data_ptr(), JJ.data_ptr(), KK.data_ptr(), sptr, stats=True)
+    t_multi = time.perf_counter() - t
+    Jsep, Ksep = torch.empty_like(D), torch.empty_like(D)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d in range(2):
+        ctx.build_2e_dev(DD[d].data_ptr(), 1.0, 0.0, Jsep.data_ptr(), sptr)
+        ctx.build_2e_dev(DD[d].data_ptr(), 0.0, -1.0, Ksep.data_ptr(), sptr)
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t
+    multi = {"densities": 2, "one_pass_ms": t_multi * 1e3, "separate_J_and_K_builds_ms": t_sep * 1e3,
+             "speedup": t_sep / t_multi, "quartets_evaluated_once": int(stm2.quartets_fp64) == quartets,
+             "max_abs_dK_beta_vs_separate": (KK[1] - Ksep).abs().max().item(),
+             "max_abs_dJ_beta_vs_separate": (JJ[1] - Jsep).abs().max().item()}
+    log(f"two densities in one pass: {t_multi * 1e3:.1f} ms vs {t_sep * 1e3:.1f} ms for separate J and K builds")
     value = quartets * args.steps / dt64
     value_mx = quartets * args.steps / dtmx
     Fd = (Fmx - F64).abs().max().item()
@@ -440,11 +598,15 @@ def main():
         "class_ms_mixed": {hfx.CLASS_NAMES[k]: round(msmx[k] / max(nmx[k], 1), 3) for k in np.argsort(-msmx)[:8]},
         "scf": {"energy": r["energy"], "iterations": r["iterations"]},
         "autotune": None if tuning is None else autotune.summary(tuning),
+        "digestion": digestion,
+        "multi_density": multi,
     }
     if not args.no_batch:
         log("batched builds: 256 clusters of 1-16 waters ...")
         res["batched"] = batched_bench(args, log)
-    if args.large:
+    if not args.no_graphene:
+        res["graphene"] = graphene_bench(args, log)
+    if not args.no_large:
         res["large"] = large_bench(args, log)
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -455,7 +617,7 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         cb = cpu_baseline(mol, Dh)
-        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "host", "one_thread")}
     print(json.dumps(res))
 
 

@@ -44,7 +44,7 @@ extern "C" {
 
 typedef enum {
     HFX_OK = 0,
-    HFX_ERR_INVALID_ARG = 1,   /* bad pointer, size, shell (l > 2, alpha <= 0), non-finite input */
+    HFX_ERR_INVALID_ARG = 1,   /* bad pointer, size, shell (l not in -1..2, alpha <= 0), non-finite input */
     HFX_ERR_OOM = 2,           /* device or host allocation failed */
     HFX_ERR_DEVICE = 3,        /* a HIP / rocBLAS / rocSOLVER call failed */
     HFX_ERR_NOT_CONVERGED = 4, /* SCF reached max_iter */
@@ -54,13 +54,21 @@ typedef enum {
 
 typedef struct hfx_ctx hfx_ctx;
 
-/* One shell: atom index, angular momentum l (0, 1 or 2), nprim primitives
- * with exponents exps[nprim] (> 0) and coefficients coefs[nprim] of
- * unit-normalised primitives (section 4.1: a shell groups the functions of
- * one atom sharing exponents and coefficients). */
+/* One shell: atom index, angular momentum l (0, 1 or 2, or HFX_SHELL_SP),
+ * nprim primitives with exponents exps[nprim] (> 0) and coefficients
+ * coefs[nprim] of unit-normalised primitives (section 4.1: a shell groups
+ * the functions of one atom sharing exponents and coefficients).
+ * HFX_SHELL_SP: an SP (L) shell of split-valence bases such as the paper's
+ * 6-31G(d) (section 5.2): an s and a p set sharing the exponents, with the s
+ * coefficients in coefs and the p coefficients in coefs_p (ignored for other
+ * l).  It is loaded as an s shell followed by a p shell, so its functions
+ * come in the order s, x, y, z and it counts as two shells wherever shells
+ * are counted (hfx_dims, hfx_schwarz). */
+#define HFX_SHELL_SP (-1)
 typedef struct {
     int atom, l, nprim;
     const double *exps, *coefs;
+    const double *coefs_p;
 } hfx_shell;
 
 enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 };

@@ -80,11 +80,41 @@ def num_threads() -> int:
     return lib().orc_num_threads()
 
 
+def _expand_sp(f):
+    """An SP (L) shell (l = -1) is an s shell and a p shell on the same atom
+    sharing its exponents, with the s and the p coefficients: written out as
+    those two shells, s first (so its functions come as s, x, y, z)."""
+    if not (f["sh_l"] == -1).any():
+        return f
+    atom, l, np_, off, exps, coefs = [], [], [], [], [], []
+    pos = 0
+    for sh in range(f["nshell"]):
+        o, n = int(f["sh_off"][sh]), int(f["sh_np"][sh])
+        ex = f["exps"][o:o + n]
+        parts = [(0, f["coefs"][o:o + n]), (1, f["coefs_p"][o:o + n])] if f["sh_l"][sh] == -1 else \
+            [(int(f["sh_l"][sh]), f["coefs"][o:o + n])]
+        for (ll, co) in parts:
+            atom.append(int(f["sh_atom"][sh]))
+            l.append(ll)
+            np_.append(n)
+            off.append(pos)
+            exps.append(ex)
+            coefs.append(co)
+            pos += n
+    g = dict(f)
+    g.update(nshell=len(l), sh_atom=np.array(atom, dtype=np.int32), sh_l=np.array(l, dtype=np.int32),
+             sh_np=np.array(np_, dtype=np.int32), sh_off=np.array(off, dtype=np.int32),
+             exps=np.ascontiguousarray(np.concatenate(exps)), coefs=np.ascontiguousarray(np.concatenate(coefs)))
+    return g
+
+
 class Basis:
-    """A molecule's basis as the oracle sees it (owns a C-side copy)."""
+    """A molecule's basis as the oracle sees it (owns a C-side copy).  SP
+    shells are written out as an s and a p shell, so shell indices count the
+    expanded shells."""
 
     def __init__(self, mol):
-        f = mol.flat()
+        f = _expand_sp(mol.flat())
         self._keep = f
         self.mol = mol
         self.ptr = lib().orc_basis_new(f["natom"], _i(f["Z"]), _d(f["xyz"]), f["nshell"],

@@ -111,7 +111,7 @@ def atomic_density(z: int, basis_shells, tau: float = 0.0, max_iter: int = 200) 
     element in its own basis (the SAD building block)."""
     import workloads as W
     mol = W.Molecule(np.array([z], dtype=np.int32), np.zeros((1, 3)),
-                     [W.Shell(0, s.l, s.exps, s.coefs) for s in basis_shells])
+                     [W.Shell(0, s.l, s.exps, s.coefs, getattr(s, "coefs_p", None)) for s in basis_shells])
     B = Basis(mol)
     S, T, V, _ = B.one_electron()
     H = T + V

@@ -538,11 +538,47 @@ extern "C" hfx_status hfx_set_class_precision(hfx_ctx* c, int cid, int fp32) {
     return HFX_OK;
 }
 
+static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int* Z, const double* xyz,
+                             const int* nshell_m, const hfx_shell* sh, const int* charge_m);
+
+// SP (L) shells are written out as an s shell and a p shell sharing the
+// exponents (s coefficients, then p coefficients), then loaded as usual.
 extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int* Z, const double* xyz,
                                      const int* nshell_m, const hfx_shell* sh, const int* charge_m) {
     if (!c) return HFX_ERR_INVALID_ARG;
     if (nmol <= 0 || !natom_m || !Z || !xyz || !nshell_m || !sh)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: empty system or null pointer");
+    long long ntot = 0;
+    for (int m = 0; m < nmol; ++m) {
+        if (nshell_m[m] <= 0) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: every molecule needs atoms and shells");
+        ntot += nshell_m[m];
+    }
+    bool any_sp = false;
+    for (long long s = 0; s < ntot; ++s) any_sp |= sh[s].l == HFX_SHELL_SP;
+    if (!any_sp) return load_batch(c, nmol, natom_m, Z, xyz, nshell_m, sh, charge_m);
+    std::vector<hfx_shell> ex;
+    std::vector<int> nsh(nmol, 0);
+    for (int m = 0, s = 0; m < nmol; ++m)
+        for (int k = 0; k < nshell_m[m]; ++k, ++s) {
+            hfx_shell q = sh[s];
+            if (q.l == HFX_SHELL_SP) {
+                if (!q.coefs_p) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: SP shell without p coefficients");
+                q.l = 0;
+                ex.push_back(q);
+                q.l = 1;
+                q.coefs = q.coefs_p;
+                ex.push_back(q);
+                nsh[m] += 2;
+            } else {
+                ex.push_back(q);
+                nsh[m] += 1;
+            }
+        }
+    return load_batch(c, nmol, natom_m, Z, xyz, nsh.data(), ex.data(), charge_m);
+}
+
+static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int* Z, const double* xyz,
+                             const int* nshell_m, const hfx_shell* sh, const int* charge_m) {
     // ---- validation ----
     long long natom = 0, nshell = 0;
     for (int m = 0; m < nmol; ++m) {
@@ -562,7 +598,8 @@ extern "C" hfx_status hfx_load_batch(hfx_ctx* c, int nmol, const int* natom_m, c
         for (int s = 0; s < nshell_m[m]; ++s) {
             const hfx_shell& q = sh[nshell + s];
             if (q.atom < 0 || q.atom >= natom_m[m]) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: shell atom index");
-            if (q.l < 0 || q.l > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: only s, p, d shells (l <= 2)");
+            if (q.l < 0 || q.l > 2)
+                return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: only s, p, d and SP shells (l in -1..2)");
             if (q.nprim < 1 || q.nprim > 16 || !q.exps || !q.coefs)
                 return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_load: nprim must be in [1, 16]");
             for (int k = 0; k < q.nprim; ++k)

@@ -417,6 +417,7 @@ static hfx_status sad_guess(hfx_ctx* c, std::vector<double>& Dsad) {
                 x.nprim = (int)c->raw_exps[s].size();
                 x.exps = c->raw_exps[s].data();
                 x.coefs = c->raw_coefs[s].data();
+                x.coefs_p = nullptr;
                 shells.push_back(x);
             }
             const double origin[3] = {0.0, 0.0, 0.0};

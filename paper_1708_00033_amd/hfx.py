@@ -49,9 +49,13 @@ CLASS_NAMES = [f"({b}|{k})" for bi, b in enumerate(["ss", "ps", "pp", "ds", "dp"
                for k in ["ss", "ps", "pp", "ds", "dp", "dd"][:bi + 1]]
 
 
+HFX_SHELL_SP = -1
+
+
 class hfx_shell(C.Structure):
     _fields_ = [("atom", C.c_int), ("l", C.c_int), ("nprim", C.c_int),
-                ("exps", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double))]
+                ("exps", C.POINTER(C.c_double)), ("coefs", C.POINTER(C.c_double)),
+                ("coefs_p", C.POINTER(C.c_double))]
 
 
 class hfx_options(C.Structure):
@@ -164,6 +168,19 @@ def _d(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
+def _fill_shell(dst: hfx_shell, sh, keep: list) -> None:
+    """One hfx_shell from a workloads.Shell (keeps the arrays alive in keep)."""
+    ex = np.ascontiguousarray(sh.exps, dtype=np.float64)
+    co = np.ascontiguousarray(sh.coefs, dtype=np.float64)
+    keep += [ex, co]
+    dst.atom, dst.l, dst.nprim = int(sh.atom), int(sh.l), len(ex)
+    dst.exps, dst.coefs = _d(ex), _d(co)
+    if int(sh.l) == HFX_SHELL_SP:
+        cp = np.ascontiguousarray(sh.coefs_p, dtype=np.float64)
+        keep.append(cp)
+        dst.coefs_p = _d(cp)
+
+
 def default_options(**kw) -> hfx_options:
     o = hfx_options()
     hfx_default_options(C.byref(o))
@@ -212,11 +229,7 @@ class Context:
         shells = (hfx_shell * f["nshell"])()
         self._keep = []
         for s, sh in enumerate(mol.shells):
-            ex = np.ascontiguousarray(sh.exps, dtype=np.float64)
-            co = np.ascontiguousarray(sh.coefs, dtype=np.float64)
-            self._keep += [ex, co]
-            shells[s].atom, shells[s].l, shells[s].nprim = int(sh.atom), int(sh.l), len(ex)
-            shells[s].exps, shells[s].coefs = _d(ex), _d(co)
+            _fill_shell(shells[s], sh, self._keep)
         Z = np.ascontiguousarray(f["Z"], dtype=np.int32)
         xyz = np.ascontiguousarray(f["xyz"], dtype=np.float64)
         self._check(hfx_load(self.ptr, f["natom"], Z.ctypes.data_as(C.POINTER(C.c_int)), _d(xyz), f["nshell"],
@@ -239,11 +252,7 @@ class Context:
         i = 0
         for m in mols:
             for sh in m.shells:
-                ex = np.ascontiguousarray(sh.exps, dtype=np.float64)
-                co = np.ascontiguousarray(sh.coefs, dtype=np.float64)
-                self._keep += [ex, co]
-                shells[i].atom, shells[i].l, shells[i].nprim = int(sh.atom), int(sh.l), len(ex)
-                shells[i].exps, shells[i].coefs = _d(ex), _d(co)
+                _fill_shell(shells[i], sh, self._keep)
                 i += 1
         ip = C.POINTER(C.c_int)
         self._check(hfx_load_batch(self.ptr, len(mols), nat.ctypes.data_as(ip), Z.ctypes.data_as(ip), _d(xyz),

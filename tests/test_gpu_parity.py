@@ -538,3 +538,49 @@ def test_multi_density_batch_and_limits():
             ctx.build_jk_multi_dev(bad, dD.data_ptr(), dJ.data_ptr(), dK.data_ptr(), s)
     with pytest.raises(hfx.HfxError):
         ctx.build_jk_multi_dev(2, dD.data_ptr(), 0, 0, s)
+
+
+def test_sp_shells_graphene_against_oracle():
+    """SP (L) shells through the C ABI (written out as s and p on load): an
+    8-carbon graphene bilayer's Fock matrix against the oracle's, the
+    0.5 nm bilayer of the paper's table (44 carbons, 660 functions) on
+    sampled shell blocks, and the 8-carbon SCF energy against the oracle's
+    converged energy (fixture written by tests/golden/make_graphene_golden.py)."""
+    import json
+    import os
+    import torch
+    import oracle
+    hfx = _hfx()
+    m = W.graphene_bilayer(4)
+    B = oracle.Basis(m)
+    ctx = hfx.Context().load(m)
+    assert ctx.nbf == 120 and ctx.nshell == 48
+    D = W.random_symmetric(m.nbf, 14, 0.1)
+    F, st = ctx.build_fock(D)
+    ref, _, _ = _fock_ref(B, D)
+    _, _, ost = B.jk(D, 1e-10)
+    assert st.quartets_fp64 == ost[0]
+    assert np.abs(F - ref).max() < 1e-10 * max(1.0, np.abs(ref).max())
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "graphene8_oracle_scf.json")))
+    assert g["converged"]
+    r = ctx.scf(e_tol=g["e_tol"], d_rms_tol=g["d_rms_tol"], max_iter=200)
+    assert r["converged"]
+    assert abs(r["energy"] - g["energy"]) < 1e-8, (r["energy"], g["energy"])
+    m5 = W.graphene_bilayer(W.GRAPHENE_SIZES["0.5nm"])
+    c5 = hfx.Context().load(m5)
+    assert c5.nbf == 660
+    D5 = W.random_orthonormal_density(m5.nbf, m5.nocc, 15)
+    dD = torch.tensor(D5, device="cuda")
+    J, K = torch.empty_like(dD), torch.empty_like(dD)
+    s = torch.cuda.current_stream().cuda_stream
+    c5.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s)
+    c5.build_2e_dev(dD.data_ptr(), 0.0, -1.0, K.data_ptr(), s)
+    torch.cuda.synchronize()
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    B5 = oracle.Basis(m5)
+    bf = B5.shell_bf
+    for a, b in [(0, 0), (1, 2), (2, 5), (3, 130), (262, 7)]:
+        Jb, Kb = B5.jk_block(a, b, D5, 1e-10)
+        na, nb = Jb.shape
+        assert np.abs(J[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Jb).max() < 1e-10, (a, b)
+        assert np.abs(K[bf[a]:bf[a] + na, bf[b]:bf[b] + nb] - Kb).max() < 1e-10, (a, b)

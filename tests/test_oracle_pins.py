@@ -541,3 +541,50 @@ def test_jk_8fold_equals_brute_force_spd(water_spd):
     eri = B.eri_full()
     assert np.allclose(J8, np.einsum("mnls,ls->mn", eri, D), atol=1e-12, rtol=0)
     assert np.allclose(K8, np.einsum("mlns,ls->mn", eri, D), atol=1e-12, rtol=0)
+
+
+# ---- SP shells and the graphene workload -----------------------------------------------
+
+def test_sp_shell_is_an_s_and_a_p_shell(oracle_lib):
+    """An SP (L) shell is by definition an s and a p shell sharing its
+    exponents: integrals over a molecule with SP shells equal those with the
+    two shells written out (s coefficients, then p coefficients)."""
+    import oracle
+    base = W.graphene_bilayer(1)   # two carbons, one per layer
+    ex = []
+    for sh in base.shells:
+        if sh.l == W.SP:
+            ex.append(W.Shell(sh.atom, 0, sh.exps, sh.coefs))
+            ex.append(W.Shell(sh.atom, 1, sh.exps, sh.coefs_p))
+        else:
+            ex.append(sh)
+    written = W.Molecule(base.Z.copy(), base.xyz.copy(), ex)
+    Bsp, Bex = oracle.Basis(base), oracle.Basis(written)
+    assert Bsp.nbf == Bex.nbf == 30 and Bsp.nshell == Bex.nshell == 12
+    for a, b in zip(Bsp.one_electron(), Bex.one_electron()):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    D = W.random_symmetric(30, 7, 0.3)
+    J1, K1, s1 = Bsp.jk(D, 0.0)
+    J2, K2, s2 = Bex.jk(D, 0.0)
+    assert s1 == s2   # the same quartets; sums agree up to the threads' summation order
+    assert np.abs(J1 - J2).max() <= 1e-14 * np.abs(J1).max() and np.abs(K1 - K2).max() <= 1e-14 * np.abs(K1).max()
+    # the SP shell's s and p parts use their own coefficients
+    S = Bsp.one_electron()[0]
+    assert np.allclose(np.diag(S), 1.0, atol=1e-13)
+
+
+def test_graphene_sizes_match_the_papers_table():
+    """Atoms, shells and basis functions of the five bilayers equal the
+    paper's table of chemical systems (appendix A, Table 4: 44/176/660,
+    120/480/1,800, 220/880/3,300, 356/1,424/5,340, 2,016/8,064/30,240)."""
+    table = {"0.5nm": (44, 176, 660), "1nm": (120, 480, 1800), "1.5nm": (220, 880, 3300),
+             "2nm": (356, 1424, 5340), "5nm": (2016, 8064, 30240)}
+    for name, n in W.GRAPHENE_SIZES.items():
+        m = W.graphene_bilayer(n)
+        assert (m.natom, m.nshell, m.nbf) == table[name], name
+        xyz = m.xyz / W.ANGSTROM_TO_BOHR
+        lay = xyz[:, 2] < 1.0
+        assert lay.sum() == n
+        d = np.sqrt(((xyz[lay][:, None] - xyz[lay][None]) ** 2).sum(-1)) + 9 * np.eye(n)
+        assert abs(d.min() - W.CC_BOND) < 1e-12          # honeycomb bond length within a layer
+        assert abs(xyz[~lay, 2].min() - W.INTERLAYER) < 1e-12

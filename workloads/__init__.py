@@ -80,15 +80,32 @@ STO3G_H = {
     ]
 }
 
-NCART = {0: 1, 1: 3, 2: 6}
+# Synthetic carbon basis with the shape of a split-valence basis with one d
+# shell (the paper's graphene runs, section 5.2, use 6-31G(d), whose data are
+# not available here): a 6-primitive 1s shell, a 3-primitive and a
+# 1-primitive SP (L) shell -- s and p sharing exponents, with separate
+# coefficients -- and one Cartesian d shell: 4 shells, 15 functions per
+# carbon.  Exponents are even-tempered and synthetic; l = -1 marks SP.
+SP = -1
+BASIS_CARBON = {
+    6: [
+        (0, tuple(0.9 * 3.4 ** k for k in range(6)), (0.05, 0.20, 0.40, 0.32, 0.13, 0.03)),
+        (SP, tuple(0.22 * 3.0 ** k for k in range(3)), (0.45, 0.40, -0.10), (0.30, 0.50, 0.30)),
+        (SP, (0.12,), (1.0,), (1.0,)),
+        (2, (0.8,), (1.0,)),
+    ],
+}
+
+NCART = {SP: 4, 0: 1, 1: 3, 2: 6}
 
 
 @dataclass
 class Shell:
     atom: int
-    l: int
+    l: int                   # 0, 1, 2, or SP (-1): an s and a p shell sharing exponents
     exps: np.ndarray
-    coefs: np.ndarray
+    coefs: np.ndarray        # s coefficients for SP
+    coefs_p: np.ndarray = None   # SP only: p coefficients
 
     @property
     def nbf(self) -> int:
@@ -133,17 +150,22 @@ class Molecule:
             sh_off[1:] = np.cumsum(sh_np)[:-1]
         exps = np.concatenate([np.asarray(s.exps, float) for s in self.shells]) if nsh else np.zeros(0)
         coefs = np.concatenate([np.asarray(s.coefs, float) for s in self.shells]) if nsh else np.zeros(0)
+        coefs_p = (np.concatenate([np.asarray(s.coefs_p if s.l == SP else np.zeros(len(s.exps)), float)
+                                   for s in self.shells]) if nsh else np.zeros(0))
         return dict(natom=self.natom, Z=np.ascontiguousarray(self.Z, dtype=np.int32),
                     xyz=np.ascontiguousarray(self.xyz, dtype=np.float64),
                     nshell=nsh, sh_atom=sh_atom, sh_l=sh_l, sh_np=sh_np, sh_off=sh_off,
-                    exps=np.ascontiguousarray(exps), coefs=np.ascontiguousarray(coefs))
+                    exps=np.ascontiguousarray(exps), coefs=np.ascontiguousarray(coefs),
+                    coefs_p=np.ascontiguousarray(coefs_p))
 
 
 def attach_basis(Z: Sequence[int], xyz_bohr: np.ndarray, basis: dict, name: str = "") -> Molecule:
     shells = []
     for a, z in enumerate(Z):
-        for (l, ex, co) in basis[int(z)]:
-            shells.append(Shell(a, l, np.array(ex, dtype=np.float64), np.array(co, dtype=np.float64)))
+        for entry in basis[int(z)]:
+            l, ex, co = entry[:3]
+            cp = np.array(entry[3], dtype=np.float64) if l == SP else None
+            shells.append(Shell(a, l, np.array(ex, dtype=np.float64), np.array(co, dtype=np.float64), cp))
     return Molecule(np.asarray(Z, dtype=np.int32), np.asarray(xyz_bohr, dtype=np.float64), shells, name)
 
 
@@ -216,6 +238,47 @@ def water_cluster(n: int, seed: int, basis: dict = BASIS_SPD, return_redraws: bo
     xyz = np.concatenate(placed) * ANGSTROM_TO_BOHR
     m = attach_basis([8, 1, 1] * n, xyz, basis, name=f"water_cluster(n={n}, seed={seed})")
     return (m, redraws) if return_redraws else m
+
+
+# Graphene bilayer (section 5.2): two AB-stacked honeycomb layers of carbon,
+# C-C 1.42 A, layers 3.35 A apart.
+CC_BOND = 1.42
+INTERLAYER = 3.35
+# atoms per layer of the paper's five systems (Table 4: 44, 120, 220, 356 and
+# 2,016 carbon atoms in two layers)
+GRAPHENE_SIZES = {"0.5nm": 22, "1nm": 60, "1.5nm": 110, "2nm": 178, "5nm": 1008}
+
+
+def honeycomb_sites(n: int) -> np.ndarray:
+    """The n honeycomb sites (Angstrom, z = 0) nearest the centre of a
+    hexagon, ties broken by the lattice indices (i, j, sublattice)."""
+    a1 = np.array([1.5 * CC_BOND, np.sqrt(3.0) / 2 * CC_BOND])
+    a2 = np.array([1.5 * CC_BOND, -np.sqrt(3.0) / 2 * CC_BOND])
+    basis = [np.zeros(2), np.array([CC_BOND, 0.0])]
+    centre = np.array([-CC_BOND, 0.0])   # a hexagon centre: distance CC_BOND to its six atoms
+    m = 1
+    while True:
+        cand = []
+        for i in range(-m, m + 1):
+            for j in range(-m, m + 1):
+                for b in range(2):
+                    p = i * a1 + j * a2 + basis[b]
+                    cand.append((round(float(((p - centre) ** 2).sum()), 9), i, j, b, p))
+        cand.sort(key=lambda t: t[:4])
+        if len(cand) >= 4 * n and cand[n - 1][0] < (m * CC_BOND) ** 2:
+            break
+        m += 1
+    return np.array([np.append(c[4] - centre, 0.0) for c in cand[:n]])
+
+
+def graphene_bilayer(n_per_layer: int, basis: dict = BASIS_CARBON) -> Molecule:
+    """AB-stacked bilayer flake of 2 n_per_layer carbon atoms: layer 2 is
+    layer 1 shifted by one C-C bond in the plane and INTERLAYER along z.
+    Deterministic (no random draw)."""
+    lay = honeycomb_sites(n_per_layer)
+    top = lay + np.array([CC_BOND, 0.0, INTERLAYER])
+    xyz = np.concatenate([lay, top]) * ANGSTROM_TO_BOHR
+    return attach_basis([6] * (2 * n_per_layer), xyz, basis, name=f"graphene_bilayer({2 * n_per_layer} C)")
 
 
 def h2(R_bohr: float = 1.4) -> Molecule:
