@@ -194,7 +194,10 @@ hfx_status hfx_build_2e_dev(hfx_ctx *ctx, const double *dD, double cj, double ck
  * K(D_d) of each density in the same layout, so that for example an
  * unrestricted build forms F_a = H + J_a + J_b - K_a and F_b = H + J_a + J_b
  * - K_b from the alpha and beta densities.  FP64 throughout (the context's
- * precision is ignored); digestion by device-wide atomics.  Work buffers of
+ * precision is ignored).  Digestion as the class's plan: LDS-staged classes
+ * keep one set of bra rows per density in LDS and take the densities in
+ * groups that fit (the integrals are evaluated once per group), the others
+ * use device-wide atomics.  Work buffers of
  * 3 x ndens matrices (and the ket lists' D_cd per density) are allocated on
  * the first call with a larger ndens and kept by the context.  stats as in
  * hfx_build_2e_dev (quartets counted once per quartet). */

@@ -5,7 +5,7 @@
 #define HFX_DECL(cid)                                        \
     extern "C" const void* hfx_class_kernel_##cid(int);      \
     extern "C" const void* hfx_class_kernel_kr_##cid(int);   \
-    extern "C" const void* hfx_class_kernel_multi_##cid(void); \
+    extern "C" const void* hfx_class_kernel_multi_##cid(int); \
     extern "C" const void* hfx_schwarz_kernel_##cid(void);
 HFX_FOR_EACH_CID(HFX_DECL)
 
@@ -13,7 +13,7 @@ HFX_FOR_EACH_CID(HFX_DECL)
 #define HFX_RPTR(cid) hfx_class_kernel_kr_##cid,
 #define HFX_SPTR(cid) hfx_schwarz_kernel_##cid,
 #define HFX_MPTR(cid) hfx_class_kernel_multi_##cid,
-static const void* (*const kMultiLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_MPTR)};
+static const void* (*const kMultiLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_MPTR)};
 static const void* (*const kClassLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_KPTR)};
 static const void* (*const kClassLookupKr[21])(int) = {HFX_FOR_EACH_CID(HFX_RPTR)};
 static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPTR)};
@@ -100,13 +100,13 @@ extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, i
 }
 
 
-// Multi-density kernel of class cid (persistent; args->work set): nblocks
-// workgroups, LDS = the class's FP64 Boys rows.
-extern "C" hipError_t hfx_launch_class_multi(int cid, int nblocks, size_t lds_bytes, hipStream_t stream,
+// Multi-density kernel of class cid (persistent; args->work set), digestion
+// mode 0 (LDS rows per density) or 1 (global atomics): nblocks workgroups.
+extern "C" hipError_t hfx_launch_class_multi(int cid, int mode, int nblocks, size_t lds_bytes, hipStream_t stream,
                                              const ClassArgs* args) {
     if (nblocks <= 0) return hipSuccess;
     if (!args->work) return hipErrorInvalidValue;
-    const void* fn = kMultiLookup[cid]();
+    const void* fn = kMultiLookup[cid](mode);
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -122,8 +122,8 @@ extern "C" hipError_t hfx_launch_class_multi(int cid, int nblocks, size_t lds_by
 extern "C" hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs) {
     long long sc = 0;
     int rg = 0;
-    for (int v = 0; v < 32 + 12 + 1; ++v) {
-        const void* fn = v < 32 ? kClassLookup[cid](v) : (v < 44 ? kClassLookupKr[cid](v - 32) : kMultiLookup[cid]());
+    for (int v = 0; v < 32 + 12 + 2; ++v) {
+        const void* fn = v < 32 ? kClassLookup[cid](v) : (v < 44 ? kClassLookupKr[cid](v - 32) : kMultiLookup[cid](v - 44));
         if (!fn) continue;
         hipFuncAttributes fa;
         const hipError_t e = hipFuncGetAttributes(&fa, fn);

@@ -49,7 +49,8 @@ template <int NA, int NB, int NC, int ND, int MODE>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                        int fc, int fd, int spos, const double* dab, double* jab, double* FI,
                                        double* FJ, const double* __restrict__ D, double* W, int N,
-                                       int RS, int cb, int db, const double* __restrict__ dket, double* WK) {
+                                       int RS, int cb, int db, const double* __restrict__ dket, double* WK,
+                                       double* wket) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
@@ -77,7 +78,7 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 #pragma unroll
             for (int mn = 0; mn < NA * NB; ++mn) v += I[mn * NC * ND + l * ND + s] * dab[mn];
             if constexpr (MODE == 0)
-                atomicAdd(a.wket + (size_t)(l * ND + s) * a.nket_list + spos, cj2 * v);
+                atomicAdd(wket + (size_t)(l * ND + s) * a.nket_list + spos, cj2 * v);
             else
                 atomicAdd(W + (size_t)(fc + l) * N + fd + s, cj2 * v);
         }
@@ -265,9 +266,10 @@ __device__ __forceinline__ void digest_rolled(const double* I, double g, const C
                                               int fc, int fd, int spos, const double* dab, double* jab,
                                               double* FI, double* FJ, const double* __restrict__ D,
                                               double* W, int N, int RS, int cb, int db,
-                                              const double* __restrict__ dket, double* WK) {
+                                              const double* __restrict__ dket, double* WK, double* wket) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
+    (void)wket;   // the ket block's J goes straight into W (rolled digestion)
 #pragma unroll 1
     for (int mn = 0; mn < NA * NB; ++mn) {
         double v = 0.0;
@@ -341,7 +343,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
                                             const PairInfo& bra, int fc, int fd, int spos, const double* dab,
                                             double* jab, double* FI, double* FJ, const double* __restrict__ D,
                                             double* W, int N, int RS, int cb, int db,
-                                            const double* __restrict__ dket, double* WK) {
+                                            const double* __restrict__ dket, double* WK, double* wket) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     constexpr int NCD = NC * ND;
@@ -358,7 +360,7 @@ __device__ __forceinline__ void digest_pass(int k, const double* I, double g, co
 #pragma unroll 1
         for (int n = 0; n < NB; ++n) v += I[n * NCD + ls] * dab[k * NB + n];
         if constexpr (MODE == 0)
-            atomicAdd(a.wket + (size_t)ls * a.nket_list + spos, cj2 * v);
+            atomicAdd(wket + (size_t)ls * a.nket_list + spos, cj2 * v);
         else
             atomicAdd(W + (size_t)(fc + ls / ND) * N + fd + ls % ND, cj2 * v);
     }
@@ -520,7 +522,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
                                                       a.knprim, bra.AB, a.ket[s].AB, t64, Ik);
             digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
-                                              db, a.dket, Wm);
+                                              db, a.dket, Wm, a.wket);
             if (k == 0) ++n64;
         }
     }
@@ -544,10 +546,10 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         }
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
             digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
-                                                a.dket, Wm);
+                                                a.dket, Wm, a.wket);
         else
             digest<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db, a.dket,
-                                         Wm);
+                                         Wm, a.wket);
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
     // outside the task's windows)
@@ -751,19 +753,23 @@ __global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
     }
 }
 
-// Several densities in one pass over the integrals (FP64, global atomics):
-// every quartet of the task is evaluated once and digested for each density
-// d < a.ndens (D'_d, its gathered D'_cd and its J and K accumulators at
-// offsets d dstride / d kstride), the J updates into a.W and the K updates
-// into a.WK.  The bra block's J sums are reduced over each wave per ket
-// iteration (all lanes of a wave iterate together).  Tasks may be blocks of
-// bras (register-tiled plans): each bra keeps the kets of its own screened
-// prefix, the test the planner used.
-template <class E>
+// Several densities in one pass over the integrals (FP64): every quartet of
+// the task is evaluated once and digested for each density d < a.ndens
+// (D'_d, its gathered D'_cd, its J and K accumulators and its ket-block J
+// accumulator at offsets d dstride / d kstride), the J updates into a.W (the
+// ket block's via a.wket in MODE 0) and the K updates into a.WK.  MODE 0
+// stages each density's bra rows of K in LDS (a.ndens row sets; the host
+// groups the densities so that they fit), MODE 1 uses global atomics.  The
+// bra block's J sums are reduced over each wave per ket iteration (all lanes
+// of a wave iterate together).  Tasks may be blocks of bras (register-tiled
+// plans): each bra keeps the kets of its own screened prefix, the test the
+// planner used.
+template <class E, int MODE>
 __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int ti, const double* t64) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NAB * NC * ND;
     constexpr int NT = E::WGS;
+    extern __shared__ __align__(16) double lds[];
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int4 task = a.tasks[ti];
     if (task.x < 0) return;
@@ -778,6 +784,21 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
         const int N = bra.ld;
         const size_t moff = (size_t)a.moff[bra.mol];
         const double sbra = bra.a != bra.b ? 2.0 : 1.0;
+        // LDS rows of density d at F0 + d (NA + NB) a.rs, windows as in class_task
+        int RS = N, cb = 0, db = 0, half = N;
+        if (a.win) {
+            RS = a.rs;
+            half = RS / 2;
+            const int wc = task.w & 0xffff, wd = task.w >> 16;
+            cb = wc * a.win;
+            db = wd == wc ? cb : wd * a.win - half;
+        }
+        double* F0 = lds + LdsLayout<E, 0>::ROWS;
+        const int rowset = (NA + NB) * a.rs;
+        if constexpr (MODE == 0) {
+            for (int x = tid; x < a.ndens * rowset; x += NT) F0[x] = 0.0;
+            __syncthreads();
+        }
         for (int base = 0; base < nwork; base += NT) {
             const int it = base + tid;
             bool valid = it < nwork;
@@ -803,6 +824,8 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
                 double* WJ = a.W + (size_t)d * a.dstride + moff;
                 double* WKd = a.WK + (size_t)d * a.dstride + moff;
                 const double* dket = a.dket + (size_t)d * a.kstride;
+                double* wket = a.wket + (size_t)d * a.kstride;
+                double* FI = F0 + d * rowset;
                 double dab[NAB], jt[NAB];
 #pragma unroll
                 for (int mn = 0; mn < NAB; ++mn) {
@@ -811,14 +834,14 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
                 }
                 if (valid) {
                     if constexpr (E::PASSES)
-                        digest_pass<NA, NB, NC, ND, 1>(k, I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd,
-                                                       WJ, N, 0, 0, 0, dket, WKd);
+                        digest_pass<NA, NB, NC, ND, MODE>(k, I, g, a, bra, kb.x, kb.y, s, dab, jt, FI, FI + NA * RS,
+                                                          Dd, WJ, N, RS, cb, db, dket, WKd, wket);
                     else if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-                        digest_rolled<NA, NB, NC, ND, 1>(I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd,
-                                                         WJ, N, 0, 0, 0, dket, WKd);
+                        digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jt, FI, FI + NA * RS,
+                                                            Dd, WJ, N, RS, cb, db, dket, WKd, wket);
                     else
-                        digest<NA, NB, NC, ND, 1>(I, g, a, bra, kb.x, kb.y, s, dab, jt, nullptr, nullptr, Dd, WJ, N,
-                                                  0, 0, 0, dket, WKd);
+                        digest<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jt, FI, FI + NA * RS, Dd, WJ,
+                                                     N, RS, cb, db, dket, WKd, wket);
                 }
 #pragma unroll
                 for (int mn = 0; mn < NAB; ++mn) {
@@ -828,12 +851,27 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
                 }
             }
         }
+        if constexpr (MODE == 0) {   // each density's K rows into its K accumulator
+            __syncthreads();
+            for (int x = tid; x < a.ndens * rowset; x += NT) {
+                const double v = F0[x];
+                if (v != 0.0) {
+                    const int d = x / rowset, j = x - d * rowset;
+                    const int row = j < NA * RS ? bra.bfa + j / RS : bra.bfb + (j - NA * RS) / RS;
+                    const int lc = j < NA * RS ? j % RS : (j - NA * RS) % RS;
+                    const int col = lc + (lc < half ? cb : db);
+                    if (col < N && j < (NA + NB) * RS)
+                        atomicAdd(a.WK + (size_t)d * a.dstride + moff + (size_t)row * N + col, v);
+                }
+            }
+            __syncthreads();
+        }
     }
     const unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
     if (lane == 0 && a.counters && c64) atomicAdd(a.counters + 0, c64);
 }
 
-template <class E>
+template <class E, int MODE>
 __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
@@ -849,7 +887,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task_multi<E>(a, 8 * k + x, lds);
+        class_task_multi<E, MODE>(a, 8 * k + x, lds);
     }
 }
 
@@ -1047,7 +1085,9 @@ struct ClassKernelsKr {
     extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
         return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
     }                                                                                                  \
-    extern "C" const void* hfx_class_kernel_multi_##cid(void) { return (const void*)k_class_multi<Eval##cid>; } \
+    extern "C" const void* hfx_class_kernel_multi_##cid(int mode) {                                   \
+        return mode ? (const void*)k_class_multi<Eval##cid, 1> : (const void*)k_class_multi<Eval##cid, 0>; \
+    }                                                                                                  \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }
 
 // Per-class translation unit of a large class: the full evaluator (Schwarz
@@ -1078,5 +1118,7 @@ struct ClassKernelsKr {
     extern "C" const void* hfx_class_kernel_##cid(int variant) {                                       \
         return ClassKernels<Eval##cid, Eval##cid##A>::get(variant);                                    \
     }                                                                                                  \
-    extern "C" const void* hfx_class_kernel_multi_##cid(void) { return (const void*)k_class_multi<Eval##cid>; } \
+    extern "C" const void* hfx_class_kernel_multi_##cid(int mode) {                                   \
+        return mode ? (const void*)k_class_multi<Eval##cid, 1> : (const void*)k_class_multi<Eval##cid, 0>; \
+    }                                                                                                  \
     extern "C" const void* hfx_schwarz_kernel_##cid(void) { return (const void*)k_schwarz<Eval##cid>; }

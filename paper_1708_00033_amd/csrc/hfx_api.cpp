@@ -129,6 +129,7 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_kpos);
         dfree(L.d_dket);
         dfree(L.d_dket_multi);
+        dfree(L.d_wket_multi);
         L.dket_multi_cap = 0;
     }
     c->ketlists.clear();
@@ -157,6 +158,8 @@ static void release_system(hfx_ctx* c) {
     dfree(c->d_Wrep);
     dfree(c->d_multi);
     c->multi_cap = 0;
+    dfree(c->d_multi_work);
+    c->multi_work_cap = 0;
     dfree(c->d_Dp);
     dfree(c->d_tmpD);
     dfree(c->d_tmpF);
@@ -1320,10 +1323,31 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
     for (auto& KL : c->ketlists)
         if (KL.dket_multi_cap < ndens) {
             dfree(KL.d_dket_multi);
+            dfree(KL.d_wket_multi);
             KL.dket_multi_cap = 0;
             HIPCK(dalloc(&KL.d_dket_multi, (size_t)ndens * KL.ncd * KL.n));
+            HIPCK(dalloc(&KL.d_wket_multi, (size_t)ndens * KL.ncd * KL.n));
             KL.dket_multi_cap = ndens;
         }
+    // densities per launch of a plan: as many LDS row sets as fit beside the
+    // Boys rows (MODE 0), else all of them with global atomics (MODE 1)
+    std::vector<int> group(c->plans.size()), gmode(c->plans.size());
+    size_t nwork = 0;
+    for (size_t pi = 0; pi < c->plans.size(); ++pi) {
+        const SubPlan& P = c->plans[pi];
+        const size_t budget = 160 * 1024 - 256;
+        const size_t fit = P.lds_tab[0] < budget ? (budget - P.lds_tab[0]) / std::max<size_t>(1, P.lds_bytes) : 0;
+        const bool lds = P.mode == 0 && !P.priv && fit >= 1;
+        gmode[pi] = lds ? 0 : 1;
+        group[pi] = lds ? (int)std::min<size_t>(fit, (size_t)ndens) : ndens;
+        nwork += 8 * (size_t)((ndens + group[pi] - 1) / group[pi]);
+    }
+    if (c->multi_work_cap < nwork) {
+        dfree(c->d_multi_work);
+        c->multi_work_cap = 0;
+        HIPCK(dalloc(&c->d_multi_work, nwork));
+        c->multi_work_cap = nwork;
+    }
     double* Dp = c->d_multi;
     double* WJ = Dp + (size_t)ndens * nn;
     double* WK = WJ + (size_t)ndens * nn;
@@ -1333,11 +1357,14 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
         HIPCK(hfx_prepare_density(dD + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,
                                   c->max_ld, Dp + (size_t)d * nn, c->d_dmax, st));
     HIPCK(hfx_fill(WJ, 2 * (size_t)ndens * nn, 0.0, st));
-    for (auto& KL : c->ketlists)
+    for (auto& KL : c->ketlists) {
+        HIPCK(hfx_fill(KL.d_wket_multi, (size_t)ndens * KL.ncd * KL.n, 0.0, st));
         for (int d = 0; d < ndens; ++d)
             HIPCK(hfx_gather_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]),
                                  Dp + (size_t)d * nn, c->d_moff, KL.d_dket_multi + (size_t)d * KL.ncd * KL.n, st));
-    HIPCK(hfx_fill_u64(c->d_work, 16 * (int)c->plans.size(), st));
+    }
+    HIPCK(hfx_fill_u64(c->d_multi_work, (int)nwork, st));
+    size_t wofs = 0;
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         const SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
@@ -1362,18 +1389,34 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
         a.cj = 1.0;    // J updates into W: (W + W^T)/8 = J
         a.ck = -1.0;   // K updates into WK: (WK + WK^T)/8 = K
         a.nshards = 1;
-        a.work = c->d_work + 16 * pi;
         a.qlen = P.ntask / 8;
         a.ketq = KL.d_q;
         a.kpos = KL.d_kpos;
         a.tau = c->opt.schwarz_tau;
         a.same = P.B == P.K;
-        a.ndens = ndens;
+        a.win = c->win;
+        a.rs = c->rs;
         a.dstride = (long long)nn;
         a.kstride = (long long)KL.ncd * KL.n;
         const int nblocks = ((std::min(P.ntask, 2048) + 7) / 8) * 8;   // resident or queued: queues drain either way
-        HIPCK(hfx_launch_class_multi(P.cid, nblocks, P.lds_tab[0], st, &a));
+        for (int d0 = 0; d0 < ndens; d0 += group[pi]) {
+            ClassArgs b = a;
+            b.ndens = std::min(group[pi], ndens - d0);
+            b.D = Dp + (size_t)d0 * nn;
+            b.W = WJ + (size_t)d0 * nn;
+            b.WK = WK + (size_t)d0 * nn;
+            b.dket = KL.d_dket_multi + (size_t)d0 * a.kstride;
+            b.wket = KL.d_wket_multi + (size_t)d0 * a.kstride;
+            b.work = c->d_multi_work + wofs;
+            wofs += 8;
+            const size_t lds = P.lds_tab[0] + (gmode[pi] == 0 ? (size_t)b.ndens * P.lds_bytes : 0);
+            HIPCK(hfx_launch_class_multi(P.cid, gmode[pi], nblocks, lds, st, &b));
+        }
     }
+    for (auto& KL : c->ketlists)   // each density's ket-block J sums into its J accumulator
+        for (int d = 0; d < ndens; ++d)
+            HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]),
+                                  KL.d_wket_multi + (size_t)d * KL.ncd * KL.n, c->d_moff, WJ + (size_t)d * nn, st));
     for (int d = 0; d < ndens; ++d) {
         if (dJ)
             HIPCK(hfx_assemble(nullptr, WJ + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,

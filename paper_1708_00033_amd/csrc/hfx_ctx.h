@@ -26,7 +26,8 @@ struct KetList {
     double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
     double* d_dket = nullptr;   // D'_cd of every ket, gathered per build, same layout
     double* d_dket_multi = nullptr;   // the same for each density of a multi-density build
-    int dket_multi_cap = 0;           // densities it holds
+    double* d_wket_multi = nullptr;   // and the ket-block J accumulators
+    int dket_multi_cap = 0;           // densities they hold
     int4* d_kbf = nullptr;      // per ket: (bfa, bfb, a, b)
     int* d_kpos = nullptr;      // per ket: position in its pair class's Q-sorted list
     int ncd = 1;
@@ -135,6 +136,8 @@ struct hfx_ctx {
     // multi-density builds: D' and the J and K accumulators of each density
     double* d_multi = nullptr;
     int multi_cap = 0;
+    unsigned long long* d_multi_work = nullptr;   // queue counters: 8 per (plan, density group)
+    size_t multi_work_cap = 0;
     double* d_Dp = nullptr;
     double* d_tmpD = nullptr;   // host-variant staging
     double* d_tmpF = nullptr;
@@ -217,7 +220,8 @@ int hfx_class_has_kr(int cid, int kp);
 hipError_t hfx_launch_class_kr(int cid, int mode, int kp, int nbl, int nblocks, size_t lds_bytes, hipStream_t stream,
                                const ClassArgs* args);
 int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, size_t lds_bytes);
-hipError_t hfx_launch_class_multi(int cid, int nblocks, size_t lds_bytes, hipStream_t stream, const ClassArgs* args);
+hipError_t hfx_launch_class_multi(int cid, int mode, int nblocks, size_t lds_bytes, hipStream_t stream,
+                                  const ClassArgs* args);
 hipError_t hfx_launch_schwarz(int cid, const PairInfo* pairs, int npairs, const PrimPair* prim, const double* boys,
                               double* Q, hipStream_t stream);
 }

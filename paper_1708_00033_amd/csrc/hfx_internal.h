@@ -56,7 +56,8 @@ struct ClassArgs {
                                         // (W is replica 0); 0: one shared W
     // multi-density builds (k_class_multi): ndens densities D' (and their J
     // accumulators W, K accumulators WK) dstride elements apart, their
-    // gathered D'_cd kstride elements apart
+    // gathered D'_cd (dket) and ket-block J accumulators (wket) kstride
+    // elements apart
     int ndens;
     long long dstride, kstride;
     double* WK;
