@@ -219,10 +219,15 @@ def batched_bench(args, log):
         bres, _ = bctx.batch_scf()
         t_bscf = time.perf_counter() - t
         t = time.perf_counter()
+        gres, _ = bctx.batch_scf(graph=1)   # each iteration's device work replayed from HIP graphs
+        t_gscf = time.perf_counter() - t
+        dEg = max(abs(a["energy"] - b["energy"]) for a, b in zip(gres, bres))
+        t = time.perf_counter()
         sres = [c.scf() for c in ctxs[:32]]
         t_sscf32 = time.perf_counter() - t
         dE = max(abs(b["energy"] - r["energy"]) for b, r in zip(bres[:32], sres))
-        log(f"batched SCF of 256 clusters: {t_bscf:.1f} s; 32 single SCFs: {t_sscf32:.1f} s")
+        log(f"batched SCF of 256 clusters: {t_bscf:.1f} s eager, {t_gscf:.1f} s from graphs "
+            f"(max |dE| {dEg:.1e}); 32 single SCFs: {t_sscf32:.1f} s")
     # whole-build model flops (the roofline model of the class kernels) per second
     model = class_flop_model()
     flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
@@ -239,6 +244,9 @@ def batched_bench(args, log):
             "class_ms_fp64": cms64, "class_ms_mixed": cmsmx,
             "scf": {"batched_s": t_bscf, "batched_converged": int(sum(r["converged"] for r in bres)),
                     "batched_max_iterations": int(max(r["iterations"] for r in bres)),
+                    "graph_replay_s": t_gscf, "graph_segments_captured": int(gres[0]["graph_segments"]),
+                    "graph_converged": int(sum(r["converged"] for r in gres)),
+                    "graph_max_abs_dE_vs_eager": dEg, "speedup_graph_vs_eager": t_bscf / t_gscf,
                     "one_by_one_first32_s": t_sscf32, "one_by_one_256_estimate_s": t_sscf32 * 8,
                     "speedup_batched_vs_one_by_one_est": t_sscf32 * 8 / t_bscf,
                     "max_abs_dE_first32": dE},

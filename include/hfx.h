@@ -108,12 +108,16 @@ typedef struct {
     double lindep;         /* S eigenvalues below this are dropped (default 1e-7) */
     hfx_guess *model;      /* HFX_GUESS_LEARNED: the network (SAD when its
                               prediction is rejected, see hfx_guess_apply) */
+    int graph;             /* hfx_batch_scf: 1 = replay each iteration's device work
+                              from HIP graphs (default 0: eager launches) */
 } hfx_scf_options;
 
 typedef struct {
     double energy, e_nuc;
     int iterations, converged, guess_used, ndropped;
     double t_total_s, t_fock_s;
+    int graph_segments;    /* hfx_batch_scf with graph = 1: iteration segments
+                              replayed from captured graphs (0..3) */
 } hfx_scf_result;
 
 typedef struct {
@@ -253,7 +257,14 @@ hfx_status hfx_scf(hfx_ctx *ctx, const hfx_scf_options *opt, hfx_scf_result *res
 /* SCF of every molecule of a batch (hfx_load_batch) in lockstep: per
  * iteration one batched Fock build for all molecules, then per molecule the
  * energy and Pulay DIIS, and one batched eigensolve (rocSOLVER, each
- * X^T F X padded to the largest molecule).  guess: SAD or CORE, or
+ * X^T F X padded to the largest molecule).  opt->graph = 1: the matrices of
+ * every molecule live in NP x NP slots (NP = the largest basis) so that each
+ * step is one batched launch, and an iteration is three captured HIP graphs
+ * -- (a) Fock build, energies, DIIS error X^T (F D S - S D F) X and its Gram
+ * row, (b) extrapolation and X^T F X, (c) orbitals, density, rms change --
+ * replayed from the second iteration on, with the batched eigensolve and the
+ * small DIIS solve (host) between them; a segment whose capture fails runs
+ * eagerly (res[].graph_segments tells how many were captured).  guess: SAD or CORE, or
  * opt->D0 as a ragged host density (hfx_batch_layout offsets); the learned
  * guess runs per molecule (hfx_scf).  res[nmol]: per molecule (times are
  * the whole batch's).  D_out (optional): ragged host densities.  A

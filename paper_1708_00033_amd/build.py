@@ -43,7 +43,7 @@ def sources() -> list:
     gen = sorted(glob.glob(os.path.join(GEN, "eri_class_*.hip")))
     # largest classes first so the pool finishes early
     gen = sorted(gen, key=lambda s: -int(os.path.basename(s)[10:12]))
-    own = [os.path.join(CSRC, f) for f in ("eri_dispatch.hip", "misc_kernels.hip", "guess.hip", "noalloc.hip", "hfx_api.cpp",
+    own = [os.path.join(CSRC, f) for f in ("eri_dispatch.hip", "misc_kernels.hip", "guess.hip", "noalloc.hip", "batch_scf.hip", "hfx_api.cpp",
                                             "scf.cpp", "boys_table.cpp")]
     return gen + own
 

@@ -92,6 +92,7 @@ extern "C" hfx_status hfx_default_scf_options(hfx_scf_options* o) {
     o->D0 = nullptr;
     o->lindep = 1e-7;
     o->model = nullptr;
+    o->graph = 0;
     return HFX_OK;
 }
 

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <vector>
@@ -527,6 +528,7 @@ extern "C" hfx_status hfx_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_re
     res->guess_used = guess_used;
     res->ndropped = run.ndropped;
     res->t_fock_s = run.t_fock;
+    res->graph_segments = 0;
     res->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (D_out) HIPCK(hipMemcpy(D_out, D.p, nn * 8, hipMemcpyDeviceToHost));
     if (C_out) {   // column-major n x nmo -> row-major
@@ -569,17 +571,434 @@ double dev_sum(hfx_ctx* c, int np, DevBuf& part, std::vector<double>& parth, boo
 
 }  // namespace
 
+// ---- batched SCF with captured iterations ---------------------------------------
+// The same steps as the eager batched driver below, on padded NP x NP slots
+// (batch_scf.hip) so that each step is one launch for all molecules, and the
+// device work of an iteration replayed from HIP graphs: (a) Fock build,
+// energies, DIIS error X^T (F D S - S D F) X, ring store and Gram row;
+// (b) extrapolation and projection X^T F X; (c) orbitals C = X C', aufbau
+// density, rms change.  Between them: the batched eigensolve and the small
+// DIIS solve on the host (one copy of the energies and Gram rows per
+// iteration).  Iteration 1 runs eagerly (library workspaces, kernel
+// attributes), then each segment is captured once; a segment whose capture
+// fails runs eagerly from then on.
+extern "C" {
+hipError_t hfx_bscf_pack(const double* rag, const long long* moff, const int* dim, int nmol, int NP, double* pad,
+                         hipStream_t st);
+hipError_t hfx_bscf_energy(const double* D, const double* H, const double* F, const long long* moff, const int* dim,
+                           int nmol, double* E, hipStream_t st);
+hipError_t hfx_bscf_antisym(const double* A, int nmol, int NP, double* out, hipStream_t st);
+hipError_t hfx_bscf_ring_store(const double* src, int nmol, int NP, const int* slot, int dmax, double* ring,
+                               hipStream_t st);
+hipError_t hfx_bscf_ring_dots(const double* e, const double* ring, int nmol, int NP, int dmax, double* dots,
+                              hipStream_t st);
+hipError_t hfx_bscf_ring_lincomb(const double* ring, const double* coef, int nmol, int NP, int dmax, double* out,
+                                 hipStream_t st);
+hipError_t hfx_bscf_occ_cols(const double* C, const int* nocc, int nmol, int NP, double* out, hipStream_t st);
+hipError_t hfx_bscf_dsq(const double* Dn, const double* D, const int* dim, int nmol, int NP, double* sq,
+                        hipStream_t st);
+hipError_t hfx_bscf_take_density(const double* Dn, const int* active, const long long* moff, const int* dim, int nmol,
+                                 int NP, double* Dpad, double* rag, hipStream_t st);
+}
+
+namespace {
+
+struct GraphSeg {
+    hipGraphExec_t exec = nullptr;
+    bool eager = false;   // capture failed once: run eagerly
+    ~GraphSeg() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
+struct StreamGuard {
+    hipStream_t s = nullptr;
+    ~StreamGuard() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+}  // namespace
+
+static hfx_status batch_scf_graph(hfx_ctx* c, const hfx_scf_options& o, hfx_scf_result* res, double* D_out,
+                                  int* segments_captured) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int nmol = c->nmol;
+    const size_t ne = c->nelem;
+    const int NP = std::max(1, c->max_ld);
+    const size_t slot = (size_t)NP * NP, all = slot * nmol;
+    const int dmax = std::max(0, o.diis_max), dring = std::max(1, dmax);
+    rocblas_handle h = c->blas;
+    StreamGuard sg;
+    HIPCK(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+    hipStream_t st = sg.s;
+    BLASCK(rocblas_set_stream(h, st));
+    BLASCK(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+    const double one = 1.0, zero = 0.0;
+    const bool timing = c->timing;
+    c->timing = false;   // no events inside captured work
+    struct TimingRestore {
+        hfx_ctx* c;
+        bool t;
+        ~TimingRestore() {
+            c->timing = t;
+            rocblas_set_stream(c->blas, 0);
+        }
+    } timing_restore{c, timing};
+
+    // ---- guess (ragged) ----
+    DevBuf D, F;
+    HIPCK(D.alloc(ne));
+    HIPCK(F.alloc(ne));
+    bool core = false;
+    int guess_used = o.guess;
+    if (o.D0) {
+        for (size_t i = 0; i < ne; ++i)
+            if (!std::isfinite(o.D0[i])) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: non-finite D0");
+        HIPCK(hipMemcpy(D.p, o.D0, ne * 8, hipMemcpyHostToDevice));
+        guess_used = -1;
+    } else if (o.guess == HFX_GUESS_CORE) {
+        core = true;
+    } else if (o.guess == HFX_GUESS_SAD) {
+        std::vector<double> Ds;
+        hfx_status s = sad_guess(c, Ds);
+        if (s != HFX_OK) return s;
+        HIPCK(hipMemcpy(D.p, Ds.data(), ne * 8, hipMemcpyHostToDevice));
+    } else {
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: unknown guess");
+    }
+
+    // ---- padded slots ----
+    DevBuf Sp, Xp, Dp, Fp, T1, T2, Ep, Fx, P, C, Cw, Dn, Wv, Ew, ringF, ringE;
+    for (DevBuf* b : {&Sp, &Xp, &Dp, &Fp, &T1, &T2, &Ep, &Fx, &P, &C, &Cw, &Dn}) HIPCK(b->alloc(all));
+    HIPCK(Wv.alloc((size_t)NP * nmol));
+    HIPCK(Ew.alloc((size_t)NP * nmol));
+    HIPCK(ringF.alloc(all * dring));
+    HIPCK(ringE.alloc(all * dring));
+    HIPCK(hipMemsetAsync(ringF.p, 0, all * dring * 8, st));   // eager set-up, never captured
+    HIPCK(hipMemsetAsync(ringE.p, 0, all * dring * 8, st));
+    DevBuf dE, dots, coef, dsq;
+    HIPCK(dE.alloc(nmol));
+    HIPCK(dots.alloc((size_t)nmol * dring));
+    HIPCK(coef.alloc((size_t)nmol * dring));
+    HIPCK(dsq.alloc(nmol));
+    int *d_slot = nullptr, *d_active = nullptr, *d_nk = nullptr, *d_nocc = nullptr;
+    rocblas_int* info = nullptr;
+    HIPCK(hipMalloc((void**)&d_slot, nmol * sizeof(int)));
+    HIPCK(hipMalloc((void**)&d_active, nmol * sizeof(int)));
+    HIPCK(hipMalloc((void**)&d_nk, nmol * sizeof(int)));
+    HIPCK(hipMalloc((void**)&d_nocc, nmol * sizeof(int)));
+    HIPCK(hipMalloc((void**)&info, nmol * sizeof(rocblas_int)));
+    struct IntBufs {
+        void* p[5];
+        ~IntBufs() {
+            for (void* q : p)
+                if (q) (void)hipFree(q);
+        }
+    } int_bufs{{d_slot, d_active, d_nk, d_nocc, info}};
+
+    // ---- orthogonalisers: one batched eigensolve of the padded S blocks ----
+    HIPCK(hfx_pad_blocks(c->d_S, c->d_moff, c->d_mdim, nmol, NP, kPadDiag, P.p, st));
+    BLASCK(rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, NP, P.p, NP,
+                                            (rocblas_stride)slot, Wv.p, NP, Ew.p, NP, info, nmol));
+    std::vector<double> wh((size_t)NP * nmol);
+    std::vector<rocblas_int> infoh(nmol);
+    HIPCK(hipMemcpyAsync(wh.data(), Wv.p, wh.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(infoh.data(), info, nmol * sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    for (int m = 0; m < nmol; ++m)
+        if (infoh[m] != 0) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: overlap eigensolve failed");
+    HIPCK(hipMemsetAsync(Xp.p, 0, all * 8, st));
+    std::vector<int> nk(nmol), nocc(nmol), ndrop(nmol);
+    for (int m = 0; m < nmol; ++m) {
+        const int n = c->mol[m].nbf;
+        std::vector<int> keep;
+        for (int i = 0; i < n; ++i)
+            if (wh[(size_t)m * NP + i] >= o.lindep) keep.push_back(i);
+        nk[m] = (int)keep.size();
+        nocc[m] = c->mol[m].nocc;
+        ndrop[m] = n - nk[m];
+        if (nk[m] < std::max(1, nocc[m]))
+            return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: overlap matrix too singular for the occupied space");
+        DevBuf U, Us, X;
+        HIPCK(U.alloc((size_t)n * n));
+        HIPCK(Us.alloc((size_t)n * nk[m]));
+        HIPCK(X.alloc((size_t)n * nk[m]));
+        HIPCK(hipMemcpy2DAsync(U.p, (size_t)n * 8, P.p + (size_t)m * slot, (size_t)NP * 8, (size_t)n * 8, n,
+                               hipMemcpyDeviceToDevice, st));
+        int* dk = nullptr;
+        HIPCK(hipMalloc((void**)&dk, nk[m] * sizeof(int)));
+        HIPCK(hipMemcpyAsync(dk, keep.data(), nk[m] * sizeof(int), hipMemcpyHostToDevice, st));
+        hipError_t e = hfx_scale_cols(U.p, Wv.p + (size_t)m * NP, dk, n, nk[m], Us.p, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(dk);
+        HIPCK(e);
+        if (nk[m] == n)
+            BLASCK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, Us.p, n, U.p, n,
+                                 &zero, X.p, n));
+        else
+            HIPCK(hipMemcpyAsync(X.p, Us.p, (size_t)n * nk[m] * 8, hipMemcpyDeviceToDevice, st));
+        HIPCK(hipMemcpy2DAsync(Xp.p + (size_t)m * slot, (size_t)NP * 8, X.p, (size_t)n * 8, (size_t)n * 8, nk[m],
+                               hipMemcpyDeviceToDevice, st));
+        HIPCK(hipStreamSynchronize(st));
+    }
+    HIPCK(hipMemcpyAsync(d_nk, nk.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_nocc, nocc.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCK(hfx_bscf_pack(c->d_S, c->d_moff, c->d_mdim, nmol, NP, Sp.p, st));
+
+    auto gemm = [&](rocblas_operation ta, rocblas_operation tb, const double* A, const double* B, double* Cm) {
+        return rocblas_dgemm_strided_batched(h, ta, tb, NP, NP, NP, &one, A, NP, (rocblas_stride)slot, B, NP,
+                                             (rocblas_stride)slot, &zero, Cm, NP, (rocblas_stride)slot, nmol);
+    };
+    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+#define SEGCK(call)                                                                    \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) return hfx_hip_check(c, _e, #call);                      \
+    } while (0)
+#define SEGBLAS(call)                                                                  \
+    do {                                                                               \
+        if ((call) != rocblas_status_success) return hfx_fail(c, HFX_ERR_DEVICE, #call); \
+    } while (0)
+    // (a) build, energies, DIIS error, ring store, Gram row
+    auto seg_a = [&]() -> hfx_status {
+        hfx_status s = hfx_build_internal(c, D.p, 2.0, 1.0, c->d_H, F.p, st, nullptr, 0, 1);
+        if (s != HFX_OK) return s;
+        SEGCK(hfx_bscf_energy(D.p, c->d_H, F.p, c->d_moff, c->d_mdim, nmol, dE.p, st));
+        SEGCK(hfx_bscf_pack(F.p, c->d_moff, c->d_mdim, nmol, NP, Fp.p, st));
+        SEGBLAS(gemm(N_, N_, Fp.p, Dp.p, T1.p));   // F D
+        SEGBLAS(gemm(N_, N_, T1.p, Sp.p, T2.p));   // F D S
+        SEGCK(hfx_bscf_antisym(T2.p, nmol, NP, T1.p, st));   // F D S - S D F
+        SEGBLAS(gemm(N_, N_, T1.p, Xp.p, T2.p));
+        SEGBLAS(gemm(T_, N_, Xp.p, T2.p, Ep.p));   // X^T (F D S - S D F) X
+        SEGCK(hfx_bscf_ring_store(Ep.p, nmol, NP, d_slot, dring, ringE.p, st));
+        SEGCK(hfx_bscf_ring_store(Fp.p, nmol, NP, d_slot, dring, ringF.p, st));
+        SEGCK(hfx_bscf_ring_dots(Ep.p, ringE.p, nmol, NP, dring, dots.p, st));
+        return HFX_OK;
+    };
+    // (b) extrapolated F, projection, padding of the eigenproblem
+    auto seg_b = [&]() -> hfx_status {
+        SEGCK(hfx_bscf_ring_lincomb(ringF.p, coef.p, nmol, NP, dring, Fx.p, st));
+        SEGBLAS(gemm(N_, N_, Fx.p, Xp.p, T1.p));
+        SEGBLAS(gemm(T_, N_, Xp.p, T1.p, P.p));   // X^T F X
+        SEGCK(hfx_pad_rest(d_nk, nmol, NP, kPadDiag, P.p, st));
+        return HFX_OK;
+    };
+    // (c) orbitals, aufbau density, rms change, new density of the active molecules
+    auto seg_c = [&]() -> hfx_status {
+        SEGBLAS(gemm(N_, N_, Xp.p, P.p, C.p));   // C = X C'
+        SEGCK(hfx_bscf_occ_cols(C.p, d_nocc, nmol, NP, Cw.p, st));
+        SEGBLAS(gemm(N_, T_, Cw.p, C.p, Dn.p));   // C_occ C_occ^T
+        SEGCK(hfx_bscf_dsq(Dn.p, Dp.p, c->d_mdim, nmol, NP, dsq.p, st));
+        SEGCK(hfx_bscf_take_density(Dn.p, d_active, c->d_moff, c->d_mdim, nmol, NP, Dp.p, D.p, st));
+        return HFX_OK;
+    };
+#undef SEGCK
+#undef SEGBLAS
+    auto eig = [&]() -> hfx_status {
+        BLASCK(rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, NP, P.p, NP,
+                                                (rocblas_stride)slot, Wv.p, NP, Ew.p, NP, info, nmol));
+        return HFX_OK;
+    };
+    GraphSeg ga, gb, gc;
+    int captured = 0;
+    auto run = [&](GraphSeg& g, const std::function<hfx_status()>& seq, bool may_capture) -> hfx_status {
+        if (g.exec) {
+            HIPCK(hipGraphLaunch(g.exec, st));
+            return HFX_OK;
+        }
+        if (!may_capture || g.eager) return seq();
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            g.eager = true;
+            return seq();
+        }
+        hfx_status s = seq();
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(st, &graph);
+        if (s == HFX_OK && e == hipSuccess && graph && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            ++captured;
+            HIPCK(hipGraphLaunch(g.exec, st));
+            return HFX_OK;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        g.exec = nullptr;
+        g.eager = true;   // the captured work did not run: run it now
+        (void)hipGetLastError();
+        return seq();
+    };
+
+    // ---- host DIIS state per molecule (the eager driver's rules) ----
+    struct Mol {
+        std::vector<double> B;
+        int m = 0, head = 0, iterations = 0;
+        double energy = 0.0, e_old = 0.0;
+        bool have_old = false, converged = false;
+    };
+    std::vector<Mol> mols(nmol);
+    std::vector<int> slot_h(nmol, 0), active(nmol, 1);
+    std::vector<double> Eh(nmol), dotsh((size_t)nmol * dring), coefh((size_t)nmol * dring), sqh(nmol);
+    HIPCK(hipMemcpyAsync(d_active, active.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCK(hipMemsetAsync(Dp.p, 0, all * 8, st));
+    if (core) {   // diagonalise H: H stored in every molecule's ring slot 0, segments (b), (c) eagerly
+        std::vector<int> s0(nmol, 0);
+        HIPCK(hipMemcpyAsync(d_slot, s0.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCK(hfx_bscf_pack(c->d_H, c->d_moff, c->d_mdim, nmol, NP, Fx.p, st));
+        HIPCK(hfx_bscf_ring_store(Fx.p, nmol, NP, d_slot, dring, ringF.p, st));
+        std::fill(coefh.begin(), coefh.end(), 0.0);
+        for (int m = 0; m < nmol; ++m) coefh[(size_t)m * dring] = 1.0;
+        HIPCK(hipMemcpyAsync(coef.p, coefh.data(), coefh.size() * 8, hipMemcpyHostToDevice, st));
+        hfx_status s = seg_b();
+        if (s == HFX_OK) s = eig();
+        if (s == HFX_OK) s = seg_c();
+        if (s != HFX_OK) return s;
+        HIPCK(hipMemsetAsync(ringF.p, 0, all * dring * 8, st));
+    } else {
+        HIPCK(hfx_bscf_pack(D.p, c->d_moff, c->d_mdim, nmol, NP, Dp.p, st));
+    }
+    double t_fock = 0.0;
+    int nconv = 0;
+    for (int it = 1; it <= o.max_iter && nconv < nmol; ++it) {
+        // ring slot of this iteration's vector per active molecule
+        for (int m = 0; m < nmol; ++m) {
+            Mol& M = mols[m];
+            if (M.converged) {
+                slot_h[m] = -1;
+                continue;
+            }
+            if (dmax > 0) {
+                int sl;
+                diis_make_room(M.B, M.m, M.head, dmax, &sl);
+                slot_h[m] = sl;
+            } else {
+                slot_h[m] = 0;
+            }
+        }
+        HIPCK(hipMemcpyAsync(d_slot, slot_h.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+        auto tf = std::chrono::steady_clock::now();
+        hfx_status s = run(ga, seg_a, it > 1);
+        if (s != HFX_OK) return s;
+        HIPCK(hipMemcpyAsync(Eh.data(), dE.p, nmol * 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipMemcpyAsync(dotsh.data(), dots.p, dotsh.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        t_fock += std::chrono::duration<double>(std::chrono::steady_clock::now() - tf).count();
+        std::fill(coefh.begin(), coefh.end(), 0.0);
+        for (int m = 0; m < nmol; ++m) {
+            Mol& M = mols[m];
+            if (M.converged) continue;
+            const double Ek = Eh[m] + c->mol[m].enuc;
+            if (!std::isfinite(Ek)) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: non-finite energy");
+            M.energy = Ek;
+            M.iterations = it;
+            double* cm = coefh.data() + (size_t)m * dring;
+            if (dmax == 0) {
+                cm[0] = 1.0;
+                continue;
+            }
+            for (int i = 0; i < M.m; ++i) {   // the new last row and column of B
+                const double v = dotsh[(size_t)m * dring + (M.head + i) % dmax];
+                M.B[i * M.m + (M.m - 1)] = v;
+                M.B[(M.m - 1) * M.m + i] = v;
+            }
+            int use = M.m;
+            std::vector<double> cf;
+            while (use >= 2) {
+                const int q = use + 1;
+                std::vector<double> A((size_t)q * q, 0.0);
+                for (int i = 0; i < use; ++i)
+                    for (int j = 0; j < use; ++j) A[i * q + j] = M.B[i * M.m + j];
+                for (int i = 0; i < use; ++i) A[i * q + use] = A[use * q + i] = -1.0;
+                std::vector<double> ev = small_sym_eigs(A, q);
+                double amax = 0.0, amin = 1e300;
+                for (double e : ev) {
+                    amax = std::max(amax, std::fabs(e));
+                    amin = std::min(amin, std::fabs(e));
+                }
+                std::vector<double> rhs(q, 0.0);
+                rhs[use] = -1.0;
+                if (amin > 0.0 && amax / amin <= 1e14 && small_solve(A, rhs, q)) {
+                    cf.assign(rhs.begin(), rhs.begin() + use);
+                    break;
+                }
+                M.head = (M.head + 1) % dmax;   // drop the oldest vector
+                std::vector<double> nb((size_t)(M.m - 1) * (M.m - 1));
+                for (int i = 1; i < M.m; ++i)
+                    for (int j = 1; j < M.m; ++j) nb[(i - 1) * (M.m - 1) + (j - 1)] = M.B[i * M.m + j];
+                M.B.swap(nb);
+                --M.m;
+                use = M.m;
+            }
+            if (cf.empty())
+                cm[slot_h[m]] = 1.0;   // no extrapolation: this iteration's F
+            else
+                for (int i = 0; i < M.m; ++i) cm[(M.head + i) % dmax] = cf[i];
+        }
+        HIPCK(hipMemcpyAsync(coef.p, coefh.data(), coefh.size() * 8, hipMemcpyHostToDevice, st));
+        s = run(gb, seg_b, it > 1);
+        if (s == HFX_OK) s = eig();
+        if (s == HFX_OK) s = run(gc, seg_c, it > 1);
+        if (s != HFX_OK) return s;
+        HIPCK(hipMemcpyAsync(sqh.data(), dsq.p, nmol * 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipMemcpyAsync(infoh.data(), info, nmol * sizeof(rocblas_int), hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        bool changed = false;
+        for (int m = 0; m < nmol; ++m) {
+            Mol& M = mols[m];
+            if (M.converged) continue;
+            if (infoh[m] != 0) return hfx_fail(c, HFX_ERR_NUMERICAL, "hfx_batch_scf: eigensolver did not converge");
+            const int n = c->mol[m].nbf;
+            const double drms = std::sqrt(sqh[m] / ((double)n * n));
+            if (M.have_old && std::fabs(M.energy - M.e_old) < o.e_tol && drms < o.d_rms_tol) {
+                M.converged = true;
+                active[m] = 0;
+                changed = true;
+                ++nconv;
+            }
+            M.e_old = M.energy;
+            M.have_old = true;
+        }
+        if (changed) HIPCK(hipMemcpyAsync(d_active, active.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+        if (c->opt.log_level > 0)
+            std::fprintf(stderr, "[hfx batch scf, graphs] it %3d  converged %d / %d\n", it, nconv, nmol);
+    }
+    HIPCK(hipStreamSynchronize(st));
+    const double t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int m = 0; m < nmol; ++m) {
+        const Mol& M = mols[m];
+        res[m].energy = M.energy;
+        res[m].e_nuc = c->mol[m].enuc;
+        res[m].iterations = M.iterations;
+        res[m].converged = M.converged ? 1 : 0;
+        res[m].guess_used = guess_used;
+        res[m].ndropped = ndrop[m];
+        res[m].t_fock_s = t_fock;
+        res[m].t_total_s = t_total;
+    }
+    if (segments_captured) *segments_captured = captured;
+    if (D_out) HIPCK(hipMemcpy(D_out, D.p, ne * 8, hipMemcpyDeviceToHost));
+    return nconv == nmol ? HFX_OK : hfx_fail(c, HFX_ERR_NOT_CONVERGED, "hfx_batch_scf: not converged within max_iter");
+}
+
 extern "C" hfx_status hfx_batch_scf(hfx_ctx* c, const hfx_scf_options* opt, hfx_scf_result* res, double* D_out) {
     if (!c || !res) return c ? hfx_fail(c, HFX_ERR_INVALID_ARG, "null pointer") : HFX_ERR_INVALID_ARG;
     if (!c->loaded) return hfx_fail(c, HFX_ERR_STATE, "hfx_batch_scf: nothing loaded");
     hfx_scf_options o;
     if (opt) o = *opt; else hfx_default_scf_options(&o);
     if (o.max_iter < 1 || o.diis_max < 0 || o.diis_max > 32 || !(o.e_tol > 0) || !(o.d_rms_tol > 0) ||
-        !(o.lindep > 0) || !(o.lindep < 1.0))
+        !(o.lindep > 0) || !(o.lindep < 1.0) || o.graph < 0 || o.graph > 1)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: invalid options");
     if (o.guess == HFX_GUESS_LEARNED && !o.D0)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "hfx_batch_scf: the learned guess runs per molecule (hfx_scf)");
     HIPCK(hipSetDevice(c->opt.device));
+    if (o.graph) {
+        int segs = 0;
+        hfx_status s = batch_scf_graph(c, o, res, D_out, &segs);
+        if (s == HFX_OK || s == HFX_ERR_NOT_CONVERGED)
+            for (int m = 0; m < c->nmol; ++m) res[m].graph_segments = segs;
+        return s;
+    }
+    for (int m = 0; m < c->nmol; ++m) res[m].graph_segments = 0;
     auto t0 = std::chrono::steady_clock::now();
     const int nmol = c->nmol;
     const size_t ne = c->nelem;

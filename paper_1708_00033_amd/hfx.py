@@ -67,13 +67,13 @@ class hfx_options(C.Structure):
 class hfx_scf_options(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("e_tol", C.c_double), ("d_rms_tol", C.c_double),
                 ("diis_max", C.c_int), ("guess", C.c_int), ("D0", C.POINTER(C.c_double)),
-                ("lindep", C.c_double), ("model", C.c_void_p)]
+                ("lindep", C.c_double), ("model", C.c_void_p), ("graph", C.c_int)]
 
 
 class hfx_scf_result(C.Structure):
     _fields_ = [("energy", C.c_double), ("e_nuc", C.c_double), ("iterations", C.c_int),
                 ("converged", C.c_int), ("guess_used", C.c_int), ("ndropped", C.c_int),
-                ("t_total_s", C.c_double), ("t_fock_s", C.c_double)]
+                ("t_total_s", C.c_double), ("t_fock_s", C.c_double), ("graph_segments", C.c_int)]
 
 
 class hfx_fock_stats(C.Structure):
@@ -433,7 +433,8 @@ class Context:
         if st not in (HFX_OK, HFX_ERR_NOT_CONVERGED):
             self._check(st)
         out = [dict(energy=r.energy, e_nuc=r.e_nuc, iterations=r.iterations, converged=bool(r.converged),
-                    guess_used=r.guess_used, ndropped=r.ndropped, t_total_s=r.t_total_s, t_fock_s=r.t_fock_s)
+                    guess_used=r.guess_used, ndropped=r.ndropped, t_total_s=r.t_total_s, t_fock_s=r.t_fock_s,
+                    graph_segments=r.graph_segments)
                for r in res]
         return out, D
 
