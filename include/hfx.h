@@ -92,7 +92,8 @@ typedef struct {
     int precision;         /* HFX_PREC_FP64 or HFX_PREC_MIXED */
     double fp32_tau;       /* MIXED: FP32 iff Q_ab Q_cd max|D| < fp32_tau (default
                               1e-7); the classes with a d-d bra and a d-d or d-p
-                              ket stay FP64 */
+                              ket stay FP64.  One launch per class evaluates each
+                              task's FP64 kets and its FP32 suffix (Q-sorted). */
     int digest;            /* HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE */
     int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
@@ -236,8 +237,8 @@ hfx_status hfx_build_2e_shard_dev(hfx_ctx *ctx, const double *dD, double cj, dou
  * fixed 32 MiB device array of the library, one per GPU, held until the
  * process ends, instead of context memory (the context's screened plans and
  * ket lists, made at hfx_load, are read as usual).
- * Limit: 16 x (sum of nbf_m^2) bytes plus 68 KiB within 32 MiB (one molecule:
- * nbf <= 1446) and at most 512 launch plans; a larger system gives
+ * Limit: 16 x (sum of nbf_m^2) bytes plus 106.5 KiB within 32 MiB (one molecule:
+ * nbf <= 1445) and at most 512 launch plans; a larger system gives
  * HFX_ERR_INVALID_ARG and launches nothing.  Every call on a GPU, whatever
  * its context, shares that GPU's array, which keeps the last call's contents;
  * each call clears what it accumulates.  Calls that overlap in time on one
@@ -298,8 +299,8 @@ hfx_status hfx_set_class_tuning(hfx_ctx *ctx, int cls, int task_quartets, int xc
                                 int digest);
 
 /* Mixed builds (class index 0..20, or -1 for all): 1 (default) evaluates
- * the class's FP32-eligible quartets with its FP32 kernel, 0 keeps the class
- * in FP64 (never less accurate).  Chosen per class by the autotuner. */
+ * the class's FP32-eligible quartets in FP32 (its mixed kernel), 0 keeps the
+ * class in FP64 (never less accurate).  Chosen per class by the autotuner. */
 hfx_status hfx_set_class_precision(hfx_ctx *ctx, int cls, int fp32);
 
 /* Per-class plan counts: counts[21*4] = {unique quartets, integrals,
@@ -320,8 +321,7 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
  * (HFX_DIGEST_*),
  * work-items per workgroup, launch form (0..4 as in hfx_set_class_tuning),
  * workgroups of the FP64 kernel, bras per task}; *ms = summed event time of
- * the timed launches (a mixed build times its FP64 and FP32 kernels
- * together). */
+ * the timed launches. */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);
 

@@ -407,20 +407,30 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One class, one digestion mode, one precision (FP32 = 0: FP64 evaluation;
-// FP32 = 1: FP32 evaluation widened to FP64 before digestion).  A mixed
-// build launches both over complementary ket ranges of every task: the FP64
-// kernel below split[r], the FP32 kernel from split[r] on.
+// A wave's evaluated-quartet counts (per-lane running counts) into the
+// class's counter slot of this workgroup.  All lanes of the wave call it.
+__device__ __forceinline__ void flush_counts(const ClassArgs& a, unsigned c64, unsigned c32) {
+    const unsigned long long s64 = (unsigned long long)wave_sum((double)c64);
+    const unsigned long long s32 = (unsigned long long)wave_sum((double)c32);
+    if ((threadIdx.x & 63) == 0 && a.counters) {
+        const int slot = (int)(blockIdx.x % HFX_CNT_SLOTS);
+        if (s64) atomicAdd(a.counters + slot * HFX_CNT_STRIDE, s64);
+        if (s32) atomicAdd(a.counters + (HFX_CNT_SLOTS + slot) * HFX_CNT_STRIDE, s32);
+    }
+}
+
+// One class, one digestion mode, one precision scheme (FP32 = 0: FP64
+// evaluation; FP32 = 1, a mixed build: every task's kets below split[task]
+// in FP64, the rest, a suffix of its Q-sorted range, in FP32 widened to FP64
+// before digestion, both in the same launch and into the same LDS rows).
 //
-// LDS of a class kernel: the class's Boys rows in the kernel's precision
-// (padded rows, BOYS_LROW64 / BOYS_LROW32 apart), then (MODE 0) the bra rows
-// F_I, F_J of the current task.
-template <class E, int FP32>
+// LDS of a class kernel: the class's FP64 Boys rows (padded rows,
+// BOYS_LROW64 apart; the FP32 evaluation rounds their coefficients), then
+// (MODE 0) the bra rows F_I, F_J of the current task.
+template <class E>
 struct LdsLayout {
     static constexpr int L = E::LA + E::LB + E::LC + E::LD;
-    static constexpr int T64 = FP32 ? 0 : boys_rows(L) * BOYS_LROW64;   // doubles
-    static constexpr int T32 = FP32 ? boys_rows(L) * BOYS_LROW32 : 0;   // floats
-    static constexpr int ROWS = T64 + T32 / 2;               // offset of the bra rows, doubles
+    static constexpr int ROWS = boys_rows(L) * BOYS_LROW64;   // offset of the bra rows, doubles
 };
 
 // Uniform per workgroup: padding tasks (XCD striping) and other shards' bras do nothing.
@@ -428,18 +438,12 @@ __device__ __forceinline__ bool task_active(const ClassArgs& a, const int4 task)
     return task.x >= 0 && (a.nshards <= 1 || task.x % a.nshards == a.shard);
 }
 
-template <class E, int FP32>
-__device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64, float* t32) {
-    using LL = LdsLayout<E, FP32>;
-    if constexpr (FP32) {
-        const float* __restrict__ g32 = a.boys32 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-        for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
-            t32[(i / BOYS_ROW) * BOYS_LROW32 + i % BOYS_ROW] = g32[i];
-    } else {
-        const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-        for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
-            t64[(i / BOYS_ROW) * BOYS_LROW64 + i % BOYS_ROW] = g64[i];
-    }
+template <class E>
+__device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64) {
+    using LL = LdsLayout<E>;
+    const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
+    for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
+        t64[(i / BOYS_ROW) * BOYS_LROW64 + i % BOYS_ROW] = g64[i];
     __syncthreads();
 }
 
@@ -457,8 +461,11 @@ __device__ __forceinline__ void task_sync() {
 
 // One task (one bra, a range of its kets) on the lanes of the workgroup or
 // (WAVE) of one wave, whose bra rows are the wave's own LDS region.
+// Evaluated quartets go to the lane's running counts cnt64 / cnt32.
 template <class E, int MODE, int FP32, bool WAVE = false>
-__device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, const double* t64, const float* t32) {
+__device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, const double* t64, unsigned& cnt64,
+                                           unsigned& cnt32) {
+    static_assert(!(FP32 && E::PASSES), "classes evaluated in passes are FP64 only");
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NA * NB * NC * ND;
     constexpr int NT = WAVE ? 64 : E::WGS;   // lanes of the task
@@ -467,11 +474,9 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     const int4 task = a.tasks[ti];
     const int r = task.x;
     if (!task_active(a, task)) return;
-    // kets [s0, send) of the list; a mixed build's part keeps one side of the task's split
-    int s0 = task.y, send = task.z;
-    if (a.part == 1) send = min(send, a.split[ti]);
-    else if (a.part == 2) s0 = max(s0, a.split[ti]);
-    if (s0 >= send) return;                                   // uniform: nothing of this part here
+    // kets [s0, send) of the list: [s0, split) in FP64, [split, send) in FP32
+    const int s0 = task.y, send = task.z;
+    const int split = FP32 ? min(max(a.split[ti], s0), send) : send;
     const PairInfo bra = a.bra[r];
     // the bra's molecule: its blocks of D' and W, leading dimension ld
     const int N = bra.ld;
@@ -491,7 +496,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         db = wd == wc ? cb : wd * a.win - half;
     }
     // a wave's region is (NA + NB) a.rs doubles (a.rs >= RS for every molecule of a batch)
-    double* FI = lds + LdsLayout<E, FP32>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB) * a.rs : 0);
+    double* FI = lds + LdsLayout<E>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB) * a.rs : 0);
     double* FJ = FI + NA * RS;
     if constexpr (MODE == 0) {
         for (int i = tid; i < (NA + NB) * RS; i += NT) FI[i] = 0.0;
@@ -519,36 +524,50 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             const int4 kb = a.kbf[s];
             const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
             double Ik[NB * NC * ND];
-            E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
-                                                      a.knprim, bra.AB, a.ket[s].AB, t64, Ik);
+            E::template run_pass<double, BOYS_LROW64>(k, (const double*)(a.prim + bra.prim_off), bra.nprim,
+                                                      a.kprim + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, Ik);
             digest_pass<NA, NB, NC, ND, MODE>(k, Ik, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb,
                                               db, a.dket, Wm, a.wket);
             if (k == 0) ++n64;
         }
     }
-    for (int s = s0 + tid; s < send && !E::PASSES; s += NT) {
-        const int4 kb = a.kbf[s];   // ket's first basis functions and shells
-        const int fc = kb.x, fd = kb.y;
-        const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
-        const double* kab = a.ket[s].AB;   // read only by classes with a p or d ket
+    // The task's kets in slots of 64 consecutive kets, dealt to the task's
+    // waves in turn (wave w takes slots w, w + nw, ...): the FP64 part
+    // [s0, split) fills the first slots and the FP32 part [split, send) the
+    // rest, so every slot is uniform in precision and the two parts cost at
+    // most one partial slot more than one part (a per-lane choice, or one
+    // loop per part over the whole workgroup, costs a full workgroup
+    // iteration per task, which short tasks cannot hide).  With one part this
+    // is the plain interleaving s = s0 + tid + i NT.
+    const int nw = NT / 64, wv = tid >> 6, ln = tid & 63;
+    const int slots64 = (split - s0 + 63) >> 6;
+    const int slots = slots64 + ((send - split + 63) >> 6);
+    for (int j = wv; j < slots && !E::PASSES; j += nw) {
+        const bool lo = j < slots64;   // wave-uniform
+        const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
+        if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
         double I[NI];
-        if constexpr (!FP32) {
-            E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
-                                                 a.knprim, bra.AB, kab, t64, I);
+        if (!FP32 || lo) {
+            E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
+                                                 kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
             ++n64;
-        } else {
+        } else if constexpr (FP32) {
+            // FP32 primitive copies, the FP64 Boys rows rounded
             float If[NI];
-            E::template run<float, BOYS_LROW32>(a.prim + bra.prim_off, bra.nprim, a.kprim + s, kfs, kps,
-                                                a.knprim, bra.AB, kab, t32, If);
+            E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
+                                                a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
 #pragma unroll
             for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
             ++n32;
         }
+        // the block (either precision) digested in FP64
+        const int4 kb = a.kbf[s];   // ket's first basis functions and shells
+        const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
         if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
                                                 a.dket, Wm, a.wket);
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, fc, fd, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db, a.dket,
+            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db, a.dket,
                                          Wm, a.wket);
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
@@ -562,15 +581,8 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
             atomicAdd(Wm + (size_t)(bra.bfa + m) * N + bra.bfb + n, 2.0 * a.cj * v);
         }
     }
-    // quartet counters (one atomic per wave)
-    {
-        unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
-        unsigned long long c32 = (unsigned long long)wave_sum((double)n32);
-        if (lane == 0 && a.counters) {
-            if (c64) atomicAdd(a.counters + 0, c64);
-            if (c32) atomicAdd(a.counters + 1, c32);
-        }
-    }
+    cnt64 += n64;
+    cnt32 += n32;
     if constexpr (MODE == 0) {
         task_sync<WAVE>();
         for (int i = tid; i < (NA + NB) * RS; i += NT) {
@@ -595,7 +607,7 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
 // ket block's J sum over the block goes out in one atomic per component; each
 // bra has its own LDS rows F_I, F_J (MODE 0).  FP64 only.
 template <class E, int MODE, int KP, int NBL>
-__device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, const double* t64) {
+__device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, const double* t64, unsigned& cnt64) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NCD = NC * ND, NI = NAB * NCD;
     constexpr int NT = E::WGS;
@@ -630,7 +642,7 @@ __device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, 
         db = wd == wc ? cb : wd * a.win - half;
     }
     constexpr int ROWS = (NA + NB);
-    double* F0 = lds + LdsLayout<E, 0>::ROWS;   // bra i's rows at F0 + i ROWS a.rs
+    double* F0 = lds + LdsLayout<E>::ROWS;   // bra i's rows at F0 + i ROWS a.rs
     if constexpr (MODE == 0) {
         for (int i = tid; i < nb * ROWS * a.rs; i += NT) F0[i] = 0.0;
         __syncthreads();
@@ -705,10 +717,7 @@ __device__ __forceinline__ void class_task_kr(const ClassArgs& a, const int ti, 
             if (lane == 0) atomicAdd(Wm + (size_t)(bra[i].bfa + mn / NB) * N + bra[i].bfb + mn % NB, 2.0 * a.cj * v);
         }
     }
-    {
-        const unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
-        if (lane == 0 && a.counters && c64) atomicAdd(a.counters + 0, c64);
-    }
+    cnt64 += n64;
     if constexpr (MODE == 0) {
         __syncthreads();
         for (int i = tid; i < nb * ROWS * a.rs; i += NT) {
@@ -737,7 +746,8 @@ __global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
     double* t64 = lds;
-    load_boys_lds<E, 0>(a, t64, nullptr);
+    load_boys_lds<E>(a, t64);
+    unsigned cnt64 = 0;
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -749,8 +759,9 @@ __global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task_kr<E, MODE, KP, NBL>(a, 8 * k + x, t64);
+        class_task_kr<E, MODE, KP, NBL>(a, 8 * k + x, t64, cnt64);
     }
+    flush_counts(a, cnt64, 0);
 }
 
 // Several densities in one pass over the integrals (FP64): every quartet of
@@ -765,7 +776,8 @@ __global__ __launch_bounds__(E::WGS) void k_class_kr(const ClassArgs a) {
 // plans): each bra keeps the kets of its own screened prefix, the test the
 // planner used.
 template <class E, int MODE>
-__device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int ti, const double* t64) {
+__device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int ti, const double* t64,
+                                                 unsigned& cnt64) {
     constexpr int NA = hfx_ncart(E::LA), NB = hfx_ncart(E::LB), NC = hfx_ncart(E::LC), ND = hfx_ncart(E::LD);
     constexpr int NAB = NA * NB, NI = NAB * NC * ND;
     constexpr int NT = E::WGS;
@@ -793,7 +805,7 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
             cb = wc * a.win;
             db = wd == wc ? cb : wd * a.win - half;
         }
-        double* F0 = lds + LdsLayout<E, 0>::ROWS;
+        double* F0 = lds + LdsLayout<E>::ROWS;
         const int rowset = (NA + NB) * a.rs;
         if constexpr (MODE == 0) {
             for (int x = tid; x < a.ndens * rowset; x += NT) F0[x] = 0.0;
@@ -809,14 +821,13 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
             const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
             double I[E::PASSES ? NB * NC * ND : NI];
             if (valid) {
+                const double* bp = (const double*)(a.prim + bra.prim_off);
                 if constexpr (E::PASSES)
-                    E::template run_pass<double, BOYS_LROW64>(k, a.prim + bra.prim_off, bra.nprim, a.kprim + s,
-                                                              a.nket_list * a.knprim, a.nket_list, a.knprim, bra.AB,
-                                                              a.ket[s].AB, t64, I);
+                    E::template run_pass<double, BOYS_LROW64>(k, bp, bra.nprim, a.kprim + s, a.nket_list * a.knprim,
+                                                              a.nket_list, a.knprim, bra.AB, a.ket[s].AB, t64, I);
                 else
-                    E::template run<double, BOYS_LROW64>(a.prim + bra.prim_off, bra.nprim, a.kprim + s,
-                                                         a.nket_list * a.knprim, a.nket_list, a.knprim, bra.AB,
-                                                         a.ket[s].AB, t64, I);
+                    E::template run<double, BOYS_LROW64>(bp, bra.nprim, a.kprim + s, a.nket_list * a.knprim,
+                                                         a.nket_list, a.knprim, bra.AB, a.ket[s].AB, t64, I);
                 if (k == 0) ++n64;
             }
             for (int d = 0; d < a.ndens; ++d) {
@@ -867,15 +878,15 @@ __device__ __forceinline__ void class_task_multi(const ClassArgs& a, const int t
             __syncthreads();
         }
     }
-    const unsigned long long c64 = (unsigned long long)wave_sum((double)n64);
-    if (lane == 0 && a.counters && c64) atomicAdd(a.counters + 0, c64);
+    cnt64 += n64;
 }
 
 template <class E, int MODE>
 __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
-    load_boys_lds<E, 0>(a, lds, nullptr);
+    load_boys_lds<E>(a, lds);
+    unsigned cnt64 = 0;
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -887,8 +898,9 @@ __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task_multi<E, MODE>(a, 8 * k + x, lds);
+        class_task_multi<E, MODE>(a, 8 * k + x, lds, cnt64);
     }
+    flush_counts(a, cnt64, 0);
 }
 
 // Static launch: workgroup i runs task task_off + i (a plan's tasks may span
@@ -896,13 +908,26 @@ __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
 template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
+    __shared__ unsigned long long wg_count[2];   // the workgroup's counts: one global add each
     const int ti = a.task_off + (int)blockIdx.x;
     const int4 task = a.tasks[ti];
     if (!task_active(a, task)) return;
-    double* t64 = lds;
-    float* t32 = reinterpret_cast<float*>(lds);
-    load_boys_lds<E, FP32>(a, t64, t32);
-    class_task<E, MODE, FP32>(a, ti, t64, t32);
+    if (threadIdx.x == 0) wg_count[0] = wg_count[1] = 0;
+    load_boys_lds<E>(a, lds);   // ends with a barrier
+    unsigned cnt64 = 0, cnt32 = 0;
+    class_task<E, MODE, FP32>(a, ti, lds, cnt64, cnt32);
+    const unsigned long long s64 = (unsigned long long)wave_sum((double)cnt64);
+    const unsigned long long s32 = (unsigned long long)wave_sum((double)cnt32);
+    if ((threadIdx.x & 63) == 0) {
+        if (s64) atomicAdd(&wg_count[0], s64);
+        if (s32) atomicAdd(&wg_count[1], s32);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && a.counters) {
+        const int slot = (int)(blockIdx.x % HFX_CNT_SLOTS);
+        if (wg_count[0]) atomicAdd(a.counters + slot * HFX_CNT_STRIDE, wg_count[0]);
+        if (wg_count[1]) atomicAdd(a.counters + (HFX_CNT_SLOTS + slot) * HFX_CNT_STRIDE, wg_count[1]);
+    }
 }
 
 // Persistent launch: a resident grid; a workgroup on XCD x (workgroup index
@@ -915,9 +940,8 @@ template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
-    double* t64 = lds;
-    float* t32 = reinterpret_cast<float*>(lds);
-    load_boys_lds<E, FP32>(a, t64, t32);   // once per resident workgroup
+    load_boys_lds<E>(a, lds);   // once per resident workgroup
+    unsigned cnt64 = 0, cnt32 = 0;
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -929,8 +953,9 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, FP32>(a, 8 * k + x, t64, t32);
+        class_task<E, MODE, FP32>(a, 8 * k + x, lds, cnt64, cnt32);
     }
+    flush_counts(a, cnt64, cnt32);
 }
 
 // Persistent launch with one task per wave: each wave of a resident
@@ -941,9 +966,8 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
 template <class E, int MODE, int FP32>
 __global__ __launch_bounds__(E::WGS) void k_class_wave(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
-    double* t64 = lds;
-    float* t32 = reinterpret_cast<float*>(lds);
-    load_boys_lds<E, FP32>(a, t64, t32);
+    load_boys_lds<E>(a, lds);
+    unsigned cnt64 = 0, cnt32 = 0;
     const int x0 = blockIdx.x & 7;
     for (int q = 0; q < 8;) {
         const int x = (x0 + q) & 7;
@@ -954,8 +978,9 @@ __global__ __launch_bounds__(E::WGS) void k_class_wave(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, FP32, true>(a, 8 * k + x, t64, t32);
+        class_task<E, MODE, FP32, true>(a, 8 * k + x, lds, cnt64, cnt32);
     }
+    flush_counts(a, cnt64, cnt32);
 }
 
 // Schwarz bound of every pair of one pair class: Q = sqrt(max (mn|mn)) with
@@ -975,7 +1000,7 @@ __global__ __launch_bounds__(HFX_WG) void k_schwarz(const PairInfo* __restrict__
     const PairInfo pr = pairs[i];
     double I[NA * NB * NA * NB];
     // ket read from the array-of-structures layout: field stride 1, primitive stride 10 doubles
-    E::template run<double>(prim + pr.prim_off, pr.nprim, (const double*)(prim + pr.prim_off), 1,
+    E::template run<double>((const double*)(prim + pr.prim_off), pr.nprim, (const double*)(prim + pr.prim_off), 1,
                             (int)(sizeof(PrimPair) / sizeof(double)), pr.nprim, pr.AB, pr.AB,
                             boys + (size_t)boys_block(E::LA + E::LB + E::LC + E::LD) * BOYS_NT * BOYS_ROW, I);
     double mx = 0.0;
@@ -1000,7 +1025,8 @@ template <class E>
 struct ClassKernelsOne {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
-    // variant = 4 persistent + 2 mode + fp32; bit 4: one task per wave (persistent)
+    // variant = 4 persistent + 2 mode + mixed (FP64 prefix and FP32 suffix of
+    // every task); bit 4: one task per wave (persistent)
     static const void* get(int variant) {
         if (variant & 16) {
             if constexpr (kOnlyFp64Global) {
@@ -1064,12 +1090,12 @@ struct ClassKernelsKr {
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = false;                                                          \
-        template <typename R, int BS = BOYS_ROW>                                                       \
-        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
-                                                   int kfs, int kps, int nkp, const double* ab,        \
-                                                   const double* cd, const R* tab, R* out) {           \
-            fname<R, BS>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),          \
-                         R(cd[1]), R(cd[2]), tab, out);                                                \
+        template <typename R, int BS = BOYS_ROW, typename SP = double, typename TT = R>                \
+        __device__ __forceinline__ static void run(const SP* bp, int nbp, const SP* kq0, int kfs,      \
+                                                   int kps, int nkp, const double* ab,                 \
+                                                   const double* cd, const TT* tab, R* out) {          \
+            fname<R, BS, SP, TT>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),  \
+                                 R(cd[1]), R(cd[2]), tab, out);                                        \
         }                                                                                              \
         template <typename R, int BS, int KP>                                                          \
         __device__ __forceinline__ static void run_kr(const PrimPair* bp, int nbp,                     \
@@ -1096,15 +1122,15 @@ struct ClassKernelsKr {
     struct Eval##cid {                                                                                 \
         static constexpr int LA = la_, LB = lb_, LC = lc_, LD = ld_, WGS = wgs_;                       \
         static constexpr bool PASSES = true;                                                           \
-        template <typename R, int BS = BOYS_ROW>                                                       \
-        __device__ __forceinline__ static void run(const PrimPair* bp, int nbp, const double* kq0,     \
-                                                   int kfs, int kps, int nkp, const double* ab,        \
-                                                   const double* cd, const R* tab, R* out) {           \
-            fname<R, BS>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),          \
-                         R(cd[1]), R(cd[2]), tab, out);                                                \
+        template <typename R, int BS = BOYS_ROW, typename SP = double, typename TT = R>                \
+        __device__ __forceinline__ static void run(const SP* bp, int nbp, const SP* kq0, int kfs,      \
+                                                   int kps, int nkp, const double* ab,                 \
+                                                   const double* cd, const TT* tab, R* out) {          \
+            fname<R, BS, SP, TT>(bp, nbp, kq0, kfs, kps, nkp, R(ab[0]), R(ab[1]), R(ab[2]), R(cd[0]),  \
+                                 R(cd[1]), R(cd[2]), tab, out);                                        \
         }                                                                                              \
         template <typename R, int BS = BOYS_ROW>                                                       \
-        __device__ __forceinline__ static void run_pass(int k, const PrimPair* bp, int nbp,            \
+        __device__ __forceinline__ static void run_pass(int k, const double* bp, int nbp,              \
                                                         const double* kq0, int kfs, int kps, int nkp,  \
                                                         const double* ab, const double* cd,            \
                                                         const R* tab, R* out) {                        \

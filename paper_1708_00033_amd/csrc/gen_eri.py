@@ -206,15 +206,18 @@ class ClassGen:
             self.vrr(e, f, 0)
         lines = []
         L = self.L
-        lines.append(f"template <typename R, int BS = BOYS_ROW>\n__device__ __forceinline__ void {fname}(")
-        lines.append("    const PrimPair* __restrict__ bp, int nbp, const double* __restrict__ kq0, int kfs, int kps,")
+        # R: evaluation precision; SP: storage of the primitive data (the FP32
+        # evaluation reads FP32 copies); TT: the Boys table rows
+        lines.append("template <typename R, int BS = BOYS_ROW, typename SP = double, typename TT = R>")
+        lines.append(f"__device__ __forceinline__ void {fname}(")
+        lines.append("    const SP* __restrict__ bp, int nbp, const SP* __restrict__ kq0, int kfs, int kps,")
         lines.append("    int nkp, const R AB0, const R AB1, const R AB2, const R CD0, const R CD1, const R CD2,")
-        lines.append("    const R* __restrict__ boys_tab, R* __restrict__ out) {")
+        lines.append("    const TT* __restrict__ boys_tab, R* __restrict__ out) {")
         for a in acc_name.values():
             lines.append(f"  R {a} = R(0);")
         lines.append("  // ket primitives (per lane, structure of arrays: field stride kfs, primitive stride kps)")
         lines.append("  for (int ik = 0; ik < nkp; ++ik) {")
-        lines.append("    const double* kq = kq0 + ik * kps;")
+        lines.append("    const SP* kq = kq0 + ik * kps;")
         lines.append("    const R q = R(kq[0]), i2q = R(kq[kfs]), Kk = R(kq[8 * kfs]);")
         lines.append("    const R Q0 = R(kq[2 * kfs]), Q1 = R(kq[3 * kfs]), Q2 = R(kq[4 * kfs]);")
         lines.append("    const R QC0 = R(kq[5 * kfs]), QC1 = R(kq[6 * kfs]), QC2 = R(kq[7 * kfs]);")
@@ -223,7 +226,7 @@ class ClassGen:
         # waves per SIMD hide the recurrence latency) and compiles faster
         # one bra primitive: scalar loads at a uniform address in the constant
         # address space, then the Boys function and the recurrences
-        blk = ["const HFX_CONST_AS double* B = (const HFX_CONST_AS double*)(bp + IB);",
+        blk = ["const HFX_CONST_AS SP* B = (const HFX_CONST_AS SP*)(bp + (IB) * HFX_PRIM_FIELDS);",
                "const R p = R(B[0]), i2p = R(B[1]), Kb = R(B[8]);",
                "const R PA0 = R(B[5]), PA1 = R(B[6]), PA2 = R(B[7]);",
                "const R PQ0 = R(B[2]) - Q0, PQ1 = R(B[3]) - Q1, PQ2 = R(B[4]) - Q2;",
@@ -336,14 +339,14 @@ def main(out_dir):
         if cid in PASS_CLASSES:
             for k in range(ncart(la)):
                 extra.append(ClassGen(la, lb, lc, ld).emit(f"{fname}_p{k}", a_sel=k))
-            sw = ["template <typename R, int BS = BOYS_ROW>",
-                  f"__device__ __forceinline__ void {fname}_pass(int k, const PrimPair* __restrict__ bp, int nbp,",
-                  "    const double* __restrict__ kq0, int kfs, int kps, int nkp, const R AB0, const R AB1,",
-                  "    const R AB2, const R CD0, const R CD1, const R CD2, const R* __restrict__ boys_tab,",
+            sw = ["template <typename R, int BS = BOYS_ROW, typename SP = double, typename TT = R>",
+                  f"__device__ __forceinline__ void {fname}_pass(int k, const SP* __restrict__ bp, int nbp,",
+                  "    const SP* __restrict__ kq0, int kfs, int kps, int nkp, const R AB0, const R AB1,",
+                  "    const R AB2, const R CD0, const R CD1, const R CD2, const TT* __restrict__ boys_tab,",
                   "    R* __restrict__ out) {", "  switch (k) {"]
             for k in range(ncart(la)):
-                sw.append(f"    case {k}: {fname}_p{k}<R, BS>(bp, nbp, kq0, kfs, kps, nkp, AB0, AB1, AB2, CD0, CD1, CD2, "
-                          "boys_tab, out); break;")
+                sw.append(f"    case {k}: {fname}_p{k}<R, BS, SP, TT>(bp, nbp, kq0, kfs, kps, nkp, AB0, AB1, AB2, CD0, "
+                          "CD1, CD2, boys_tab, out); break;")
             sw += ["    default: break;", "  }", "}"]
             extra.append("\n".join(sw))
         hdr = ["// Generated by gen_eri.py: Obara-Saika / Head-Gordon-Pople evaluator.",

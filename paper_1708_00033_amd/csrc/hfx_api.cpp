@@ -117,6 +117,7 @@ static void release_system(hfx_ctx* c) {
     dfree(c->d_work);
     drop_graph(c);
     dfree(c->d_prim);
+    dfree(c->d_prim32);
     for (int k = 0; k < 6; ++k) {
         dfree(c->d_pairs[k]);
         c->npair[k] = 0;
@@ -125,6 +126,7 @@ static void release_system(hfx_ctx* c) {
         dfree(L.d_pairs);
         dfree(L.d_q);
         dfree(L.d_soa);
+        dfree(L.d_soa32);
         dfree(L.d_wket);
         dfree(L.d_kbf);
         dfree(L.d_kpos);
@@ -226,14 +228,12 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
     }
     std::vector<double> tab((size_t)BOYS_NL * BOYS_NT * BOYS_ROW);
     hfx_boys_table(tab.data());
-    std::vector<float> tab32(tab.begin(), tab.end());
-    if (dalloc(&c->d_boys64, tab.size()) != hipSuccess || dalloc(&c->d_boys32, tab.size()) != hipSuccess ||
-        dalloc(&c->d_dmax, 1) != hipSuccess || dalloc(&c->d_counters, 43) != hipSuccess) {
+    if (dalloc(&c->d_boys64, tab.size()) != hipSuccess || dalloc(&c->d_dmax, 1) != hipSuccess ||
+        dalloc(&c->d_counters, HFX_CNT_WORDS + 1) != hipSuccess) {
         hfx_destroy(c);
         return HFX_ERR_OOM;
     }
-    if (hipMemcpy(c->d_boys64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_boys32, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(c->d_boys64, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
         hfx_destroy(c);
         return HFX_ERR_DEVICE;
     }
@@ -245,7 +245,7 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         hfx_destroy(c);
         return HFX_ERR_DEVICE;
     }
-    c->d_bad = (int*)(c->d_counters + 42);
+    c->d_bad = (int*)(c->d_counters + HFX_CNT_WORDS);
     *out = c;
     return HFX_OK;
 }
@@ -255,7 +255,6 @@ extern "C" void hfx_destroy(hfx_ctx* c) {
     (void)hipSetDevice(c->opt.device);
     release_system(c);
     dfree(c->d_boys64);
-    dfree(c->d_boys32);
     dfree(c->d_dmax);
     dfree(c->d_counters);
     c->d_bad = nullptr;
@@ -350,16 +349,15 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->rs * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
     const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
-    P.lds_tab[0] = (size_t)boys_lds_bytes(Ltot, false);   // FP64 kernel
-    P.lds_tab[1] = (size_t)boys_lds_bytes(Ltot, true);    // FP32 kernel of a mixed build
+    P.lds_tab = (size_t)boys_lds_bytes(Ltot, false);   // FP64 rows (the mixed kernels' FP32 part reads them too)
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
-    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab[0] <= 160 * 1024 - 256) ? 0 : 1;
+    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab <= 160 * 1024 - 256) ? 0 : 1;
     P.priv = digest == HFX_DIGEST_PRIVATE;   // global-atomic kernels into the per-XCD copies
     // workgroup size: the class's alternative (smaller) size when two such
     // workgroups fit in LDS, else its default (a large group keeps the waves
     // per CU up when LDS admits one workgroup per CU)
-    P.alt = hfx_class_wgs(P.cid, 1) != hfx_class_wgs(P.cid, 0) && 2 * P.lds(false) <= 160 * 1024 - 512;
+    P.alt = hfx_class_wgs(P.cid, 1) != hfx_class_wgs(P.cid, 0) && 2 * P.lds() <= 160 * 1024 - 512;
     // register-tiled persistent form (launch form 3): blocks of two
     // Q-adjacent bras of one molecule when their rows fit in LDS, else one
     const int form = c->tune_persist[P.cid];
@@ -367,7 +365,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
         P.kr = true;
         P.alt = 0;
         P.nbl = form == 3 ? 2 : 1;
-        if (P.mode == 0 && P.lds(false) > 160 * 1024 - 256) P.nbl = 1;
+        if (P.mode == 0 && P.lds() > 160 * 1024 - 256) P.nbl = 1;
     }
     // one task per block of bras: the block's ket range in a group is the
     // longest of its bras' screened prefixes; the kernel keeps, per bra, only
@@ -443,17 +441,16 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.wave = 0;
     if (c->tune_persist[P.cid] == 2) {
         P.wave = WGS / 64;
-        if (P.lds(false) > 160 * 1024 - 256) P.wave = 0;   // does not fit: one task per workgroup
+        if (P.lds() > 160 * 1024 - 256) P.wave = 0;   // does not fit: one task per workgroup
     }
     if (P.kr) {
-        int nb = hfx_class_resident_blocks_kr(P.cid, P.mode, KL.kp, P.nbl, P.lds(false));
+        int nb = hfx_class_resident_blocks_kr(P.cid, P.mode, KL.kp, P.nbl, P.lds());
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a register-tiled class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[0] = P.nblocks[1] = ((nb + 7) / 8) * 8;
     }
     for (int mx = 0; mx < (P.kr ? 0 : (P.fp64_only ? 1 : 2)); ++mx) {
-        const size_t lds = P.lds(mx != 0);
-        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, lds);
+        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, P.lds());
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs
@@ -495,7 +492,7 @@ static hfx_status replan(hfx_ctx* c) {
     for (int i = 0; i < 21; ++i) rank[order[i]] = i;
     std::stable_sort(c->plans.begin(), c->plans.end(),
                      [&](const SubPlan& x, const SubPlan& y) { return rank[x.cid] < rank[y.cid]; });
-    HIPCK(dalloc(&c->d_work, 16 * std::max<size_t>(c->plans.size(), 1)));   // FP64 and FP32 launches
+    HIPCK(dalloc(&c->d_work, 16 * std::max<size_t>(c->plans.size(), 1)));   // 8 queue counters per plan, 16 apart
     bool any_priv = false;
     for (const auto& p : c->plans) any_priv |= p.priv;
     if (any_priv && !c->d_Wrep) HIPCK(dalloc(&c->d_Wrep, kXcds * c->nelem));
@@ -789,6 +786,13 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
     }
     HIPCK(dalloc(&c->d_prim, prim.size()));
     HIPCK(hipMemcpy(c->d_prim, prim.data(), prim.size() * sizeof(PrimPair), hipMemcpyHostToDevice));
+    {   // FP32 copy, same layout, for the FP32 evaluation of mixed builds
+        std::vector<float> p32(prim.size() * HFX_PRIM_FIELDS);
+        const double* src = reinterpret_cast<const double*>(prim.data());
+        for (size_t i = 0; i < p32.size(); ++i) p32[i] = (float)src[i];
+        HIPCK(dalloc(&c->d_prim32, p32.size()));
+        HIPCK(hipMemcpy(c->d_prim32, p32.data(), p32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
 
     // ---- Schwarz bounds on the GPU (FP64 class kernels on (ab|ab)) ----
     const bool keep_qshell = nmol == 1;
@@ -926,6 +930,11 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
             HIPCK(hipMemcpy(KL.d_pairs, sub.data(), n * sizeof(PairInfo), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_q, q.data(), n * sizeof(double), hipMemcpyHostToDevice));
             HIPCK(hipMemcpy(KL.d_soa, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+            {
+                const std::vector<float> soa32(soa.begin(), soa.end());
+                HIPCK(dalloc(&KL.d_soa32, soa32.size()));
+                HIPCK(hipMemcpy(KL.d_soa32, soa32.data(), soa32.size() * sizeof(float), hipMemcpyHostToDevice));
+            }
             c->ketlists.push_back(KL);
             klist.push_back(std::move(sub));
             kpos.push_back(std::move(sp));
@@ -1127,6 +1136,19 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
 
 // ---- the Fock build -------------------------------------------------------------------
 
+// Per class, FP64 and FP32 evaluated-quartet counts: the sums of their slots.
+static hipError_t read_counters(const unsigned long long* d, long long* cnt) {
+    std::vector<unsigned long long> w(HFX_CNT_WORDS);
+    const hipError_t e = hipMemcpy(w.data(), d, w.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < 42; ++k) {
+        unsigned long long t = 0;
+        for (int j = 0; j < HFX_CNT_SLOTS; ++j) t += w[(size_t)k * HFX_CNT_SLOTS * HFX_CNT_STRIDE + j * HFX_CNT_STRIDE];
+        cnt[k] = (long long)t;
+    }
+    return hipSuccess;
+}
+
 hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck, const double* dH, double* dOut,
                               hipStream_t st, hfx_fock_stats* stats, int shard, int nshards) {
     BuildBufs b;
@@ -1148,7 +1170,7 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
     auto t0 = std::chrono::steady_clock::now();
     if (c->timing) collect_timing(c);
     HIPCK(hfx_fill_u64(bufs.dmax, 1, st));
-    HIPCK(hfx_fill_u64(bufs.counters, 43, st));   // 42 quartet counters + the non-finite flag
+    HIPCK(hfx_fill_u64(bufs.counters, HFX_CNT_WORDS + 1, st));   // quartet counters + the non-finite flag
     HIPCK(hfx_prepare_density(dD, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff, c->max_ld, bufs.Dp,
                               bufs.dmax, st));
     HIPCK(hfx_fill(bufs.W, nn, 0.0, st));
@@ -1182,20 +1204,21 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         a.dket = KL.d_dket;
         a.prim = c->d_prim;
         a.kprim = KL.d_soa;
+        a.prim32 = c->d_prim32;
+        a.kprim32 = KL.d_soa32;
         a.nket_list = KL.n;
         a.knprim = KL.kp;
-        a.split = P.d_split;
+        a.split = mx ? P.d_split : nullptr;
         a.win = c->win;
         a.rs = c->rs;
         a.moff = c->d_moff;
         a.tasks = P.d_tasks;
         a.boys64 = c->d_boys64;
-        a.boys32 = c->d_boys32;
         a.D = bufs.Dp;
         a.W = P.priv ? c->d_Wrep : bufs.W;
         a.wrep = P.priv ? (long long)nn : 0;
         a.wket = KL.d_wket;
-        a.counters = bufs.counters + 2 * cid;
+        a.counters = bufs.counters + (size_t)cid * HFX_CNT_CLASS;
         a.cj = cj;
         a.ck = ck;
         a.shard = shard;
@@ -1206,38 +1229,25 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         a.tau = c->opt.schwarz_tau;
         a.same = P.B == P.K;
         a.qlen = P.ntask / 8;
-        a.part = mx ? 1 : 0;
         a.task_off = 0;
         // a static grid of ntask workgroups is cut into launches of at most
         // kMaxGroups (2^20 x 1024 lanes < 2^32 work-items; a multiple of 8
         // keeps workgroup i on XCD i mod 8 in step with the task queues)
         constexpr int kMaxGroups = 1 << 20;
-        auto launch = [&](ClassArgs& x, int fp32) -> hfx_status {
-            if (P.kr) {
-                HIPCK(hfx_launch_class_kr(cid, P.mode, KL.kp, P.nbl, P.nblocks[0], P.lds(false), st, &x));
-                return HFX_OK;
-            }
-            if (P.persist) {
-                HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, fp32, P.nblocks[fp32], P.lds(fp32 != 0), st,
-                                       &x));
-                return HFX_OK;
-            }
-            for (int off = 0; off < P.ntask; off += kMaxGroups) {
-                x.task_off = off;
-                HIPCK(hfx_launch_class(cid, P.alt, 0, P.mode, fp32, std::min(kMaxGroups, P.ntask - off),
-                                       P.lds(fp32 != 0), st, &x));
-            }
-            return HFX_OK;
-        };
         if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
-        hfx_status ls = launch(a, 0);
-        if (ls != HFX_OK) return ls;
-        if (mx) {   // the same tasks' kets from their split on, in FP32
-            ClassArgs b = a;
-            b.part = 2;
-            b.work = P.persist ? bufs.work + 16 * pi + 8 : nullptr;
-            ls = launch(b, 1);
-            if (ls != HFX_OK) return ls;
+        // one launch per plan; a mixed build's kernel evaluates each task's
+        // kets before its split in FP64 and the rest in FP32
+        const int m = mx ? 1 : 0;
+        if (P.kr) {
+            HIPCK(hfx_launch_class_kr(cid, P.mode, KL.kp, P.nbl, P.nblocks[0], P.lds(), st, &a));
+        } else if (P.persist) {
+            HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, m, P.nblocks[m], P.lds(), st, &a));
+        } else {
+            for (int off = 0; off < P.ntask; off += kMaxGroups) {
+                a.task_off = off;
+                HIPCK(hfx_launch_class(cid, P.alt, 0, P.mode, m, std::min(kMaxGroups, P.ntask - off), P.lds(), st,
+                                       &a));
+            }
         }
         if (c->timing && P.ev1) {
             HIPCK(hipEventRecord(P.ev1, st));
@@ -1253,14 +1263,14 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
     c->last_stream = st;
     if (stats) {
         HIPCK(hipStreamSynchronize(st));
-        unsigned long long cnt[42];
+        long long cnt[42];
         int bad = 0;
-        HIPCK(hipMemcpy(cnt, bufs.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        HIPCK(read_counters(bufs.counters, cnt));
         HIPCK(hipMemcpy(&bad, bufs.bad, sizeof(int), hipMemcpyDeviceToHost));
         stats->quartets_fp64 = stats->quartets_fp32 = stats->integrals = stats->prim_quartets = 0;
         for (int k = 0; k < 21; ++k) {
-            stats->quartets_fp64 += (long long)cnt[2 * k];
-            stats->quartets_fp32 += (long long)cnt[2 * k + 1];
+            stats->quartets_fp64 += cnt[2 * k];
+            stats->quartets_fp32 += cnt[2 * k + 1];
             stats->integrals += c->totals[k].integrals;
             stats->prim_quartets += c->totals[k].prim;
         }
@@ -1337,7 +1347,7 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         const SubPlan& P = c->plans[pi];
         const size_t budget = 160 * 1024 - 256;
-        const size_t fit = P.lds_tab[0] < budget ? (budget - P.lds_tab[0]) / std::max<size_t>(1, P.lds_bytes) : 0;
+        const size_t fit = P.lds_tab < budget ? (budget - P.lds_tab) / std::max<size_t>(1, P.lds_bytes) : 0;
         const bool lds = P.mode == 0 && !P.priv && fit >= 1;
         gmode[pi] = lds ? 0 : 1;
         group[pi] = lds ? (int)std::min<size_t>(fit, (size_t)ndens) : ndens;
@@ -1353,7 +1363,7 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
     double* WJ = Dp + (size_t)ndens * nn;
     double* WK = WJ + (size_t)ndens * nn;
     HIPCK(hfx_fill_u64(c->d_dmax, 1, st));
-    HIPCK(hfx_fill_u64(c->d_counters, 43, st));
+    HIPCK(hfx_fill_u64(c->d_counters, HFX_CNT_WORDS + 1, st));
     for (int d = 0; d < ndens; ++d)
         HIPCK(hfx_prepare_density(dD + (size_t)d * nn, c->d_cscale, c->nmol, c->d_moff, c->d_mdim, c->d_mboff,
                                   c->max_ld, Dp + (size_t)d * nn, c->d_dmax, st));
@@ -1381,12 +1391,11 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
         a.tasks = P.d_tasks;
         a.moff = c->d_moff;
         a.boys64 = c->d_boys64;
-        a.boys32 = c->d_boys32;
         a.D = Dp;
         a.W = WJ;
         a.WK = WK;
         a.dket = KL.d_dket_multi;
-        a.counters = c->d_counters + 2 * P.cid;
+        a.counters = c->d_counters + (size_t)P.cid * HFX_CNT_CLASS;
         a.cj = 1.0;    // J updates into W: (W + W^T)/8 = J
         a.ck = -1.0;   // K updates into WK: (WK + WK^T)/8 = K
         a.nshards = 1;
@@ -1410,7 +1419,7 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
             b.wket = KL.d_wket_multi + (size_t)d0 * a.kstride;
             b.work = c->d_multi_work + wofs;
             wofs += 8;
-            const size_t lds = P.lds_tab[0] + (gmode[pi] == 0 ? (size_t)b.ndens * P.lds_bytes : 0);
+            const size_t lds = P.lds_tab + (gmode[pi] == 0 ? (size_t)b.ndens * P.lds_bytes : 0);
             HIPCK(hfx_launch_class_multi(P.cid, gmode[pi], nblocks, lds, st, &b));
         }
     }
@@ -1429,13 +1438,13 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
     c->last_stream = st;
     if (stats) {
         HIPCK(hipStreamSynchronize(st));
-        unsigned long long cnt[42];
+        long long cnt[42];
         int bad = 0;
-        HIPCK(hipMemcpy(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        HIPCK(read_counters(c->d_counters, cnt));
         HIPCK(hipMemcpy(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost));
         stats->quartets_fp64 = stats->quartets_fp32 = stats->integrals = stats->prim_quartets = 0;
         for (int k = 0; k < 21; ++k) {
-            stats->quartets_fp64 += (long long)cnt[2 * k];
+            stats->quartets_fp64 += cnt[2 * k];
             stats->integrals += c->totals[k].integrals;
             stats->prim_quartets += c->totals[k].prim;
         }

@@ -23,6 +23,7 @@ struct KetList {
     PairInfo* d_pairs = nullptr;
     double* d_q = nullptr;
     double* d_soa = nullptr;
+    float* d_soa32 = nullptr;   // its FP32 copy (the FP32 evaluation of mixed builds)
     double* d_wket = nullptr;   // ket-block J accumulator, ncart(l_c) ncart(l_d) x n
     double* d_dket = nullptr;   // D'_cd of every ket, gathered per build, same layout
     double* d_dket_multi = nullptr;   // the same for each density of a multi-density build
@@ -42,7 +43,7 @@ struct SubPlan {
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;     // bra rows F_I, F_J (LDS digestion)
-    size_t lds_tab[2] = {0, 0};   // Boys rows in LDS for the FP64 / FP32 kernel
+    size_t lds_tab = 0;       // the class's FP64 Boys rows in LDS
     int mode = 0;             // digestion actually used (LDS may fall back to global)
     // timing (when enabled): events around this launch, summed milliseconds
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -51,16 +52,14 @@ struct SubPlan {
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
     // LDS of a workgroup: bra rows (one set per wave with one task per wave) and Boys rows
-    size_t lds(bool mx) const {
-        return (mode == 0 ? lds_bytes * (wave ? wave : nbl) : 0) + lds_tab[mx ? 1 : 0];
-    }
+    size_t lds() const { return (mode == 0 ? lds_bytes * (wave ? wave : nbl) : 0) + lds_tab; }
     bool persist = false;     // persistent launch through per-XCD work counters
     int wave = 0;             // > 0: one task per wave (persistent), this many waves per workgroup
     bool kr = false;          // register-tiled persistent kernel (ket primitives in registers), FP64
     bool priv = false;        // private digestion: global atomics into the per-XCD copies of W
     int nbl = 1;              // bras per task (register-tiled blocks of Q-adjacent bras)
     int alt = 0;              // 1: the class's alternative workgroup size
-    int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / FP32 kernel
+    int nblocks[2] = {0, 0};  // resident grid (multiple of 8) for the FP64 / the mixed kernel
 };
 
 struct ClassTotals {
@@ -108,6 +107,7 @@ struct hfx_ctx {
     std::vector<int> shell_atom;
     // device data
     PrimPair* d_prim = nullptr;
+    float* d_prim32 = nullptr;          // FP32 copy (HFX_PRIM_FIELDS floats per primitive pair)
     PairInfo* d_pairs[6] = {nullptr};   // significant pairs per pair class, Q descending (bras)
     int npair[6] = {0};
     std::vector<KetList> ketlists;      // per pair class and primitive count (kets)
@@ -124,10 +124,9 @@ struct hfx_ctx {
                          1, 1, 1, 1, 1, 1, 1, 1, 1, 1};   // mixed builds: FP32 kernel for eligible quartets
     int tune_digest[21] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
                            -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // -1: opt.digest
-    unsigned long long* d_work = nullptr;        // 8 queue counters per plan
+    unsigned long long* d_work = nullptr;        // 8 queue counters per plan (16 apart)
     std::vector<double> Qshell;         // nshell x nshell Schwarz bounds (host)
     double* d_boys64 = nullptr;
-    float* d_boys32 = nullptr;
     double* d_cscale = nullptr;
     double* d_S = nullptr;
     double* d_H = nullptr;
@@ -142,7 +141,7 @@ struct hfx_ctx {
     double* d_tmpD = nullptr;   // host-variant staging
     double* d_tmpF = nullptr;
     unsigned long long* d_dmax = nullptr;
-    unsigned long long* d_counters = nullptr;  // 2 per class
+    unsigned long long* d_counters = nullptr;  // HFX_CNT_WORDS quartet-counter words, then the non-finite flag
     int* d_bad = nullptr;
     rocblas_handle blas = nullptr;
     hipGraphExec_t graph_exec = nullptr;   // captured build (hfx_graph_capture)
@@ -156,7 +155,7 @@ struct hfx_ctx {
 
 // Per-build scratch of one Fock build: the accumulator W and the
 // component-scaled density D' (ragged, nelem doubles each), the max|D| word,
-// 42 quartet counters followed by the non-finite flag, and 16 queue counters
+// the quartet counters (HFX_CNT_WORDS) followed by the non-finite flag, and 16 queue counters
 // per launch plan.  Context memory by default (hfx_ctx_bufs); the no-alloc
 // entry point passes a static device array instead.
 struct BuildBufs {

@@ -18,6 +18,7 @@ struct PrimPair {
     double K;
     double pad;
 };
+#define HFX_PRIM_FIELDS 10   // elements of one PrimPair (an FP32 copy has the same layout in floats)
 
 // One shell pair in canonical orientation: shells a (higher l) and b, their
 // first basis functions, its primitive pairs, its Schwarz bound and A - B.
@@ -43,8 +44,11 @@ struct ClassArgs {
     const double* __restrict__ dket;    // per build: D'_cd of every ket, [component][ket position]
     const PrimPair* __restrict__ prim;  // all primitive pairs (bra access)
     const double* __restrict__ kprim;   // ket primitives, structure of arrays
+    const float* __restrict__ prim32;   // FP32 copies of both (mixed builds: the FP32 evaluation reads
+    const float* __restrict__ kprim32;  // them without conversions)
     int nket_list, knprim;
-    const int* __restrict__ split;      // per task: kets below this list position use FP64 (mixed builds)
+    const int* __restrict__ split;      // mixed builds, per task: kets below this list position use FP64,
+                                        // the rest FP32 (one launch evaluates both parts)
     const int4* __restrict__ tasks;     // (bra index, first ket, end ket, window code wc | wd << 16); bra -1:
                                         // empty.  Task 8k + x is entry k of XCD x's queue.  Register-tiled
                                         // plans: bra index | (bras in the block - 1) << 28
@@ -66,18 +70,26 @@ struct ClassArgs {
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
                                             // launch); null: one task per workgroup
     int qlen;                           // entries per XCD queue (tasks = 8 qlen)
-    int part;                           // mixed builds: 1 = kets before split[r] (FP64 kernel),
-                                        // 2 = kets from split[r] on (FP32 kernel); 0 = all kets
     const long long* __restrict__ moff; // per molecule: element offset of its blocks in D', W
     const double* __restrict__ boys64;
-    const float* __restrict__ boys32;
     const double* __restrict__ D;       // component-scaled density D'
     double* __restrict__ W;             // accumulator, F_2e = s (W + W^T) s / 8
     double* __restrict__ wket;          // LDS mode: ket-block J sums, [component][ket position]
-    unsigned long long* __restrict__ counters;  // [0] FP64 quartets, [1] FP32 quartets
+    unsigned long long* __restrict__ counters;  // the class's quartet counters (HFX_CNT_CLASS words)
     int shard, nshards;                 // only bras with r % nshards == shard (1 shard: all)
     double cj, ck;                      // W_ab += cj*2 g D_cd ; W_ac -= ck g D_bd
 };
+
+// Evaluated-quartet counters of a build: per class, FP64 then FP32, each
+// spread over HFX_CNT_SLOTS words one 128-byte line apart (a workgroup adds
+// into slot blockIdx mod HFX_CNT_SLOTS), summed on the host.  Kernels add once
+// per wave at the end of a persistent launch, once per workgroup in the
+// static form: one hot word per class taking an atomic per wave and task cost
+// more than some classes' integrals.
+#define HFX_CNT_SLOTS 8
+#define HFX_CNT_STRIDE 16
+#define HFX_CNT_CLASS (2 * HFX_CNT_SLOTS * HFX_CNT_STRIDE)
+#define HFX_CNT_WORDS (21 * HFX_CNT_CLASS)   // then one word: the non-finite flag
 
 // Index (0..7) of the accelerator complex die (XCD) the wave runs on, read
 // from the hardware register.  It only selects which private copy of the
@@ -166,6 +178,20 @@ __device__ __forceinline__ float boys_taylor(const float* __restrict__ row, floa
     return f;
 }
 
+// FP32 value from the FP64 rows (the mixed kernels keep one table in LDS):
+// the NO leading coefficients rounded to FP32, then the same Horner steps.
+template <int NO>
+__device__ __forceinline__ float boys_taylor(const double* __restrict__ row, float d) {
+    static_assert(NO <= 6, "FP32 Taylor order");
+    const double2* r2 = reinterpret_cast<const double2*>(row);
+    const double2 c01 = r2[0], c23 = r2[1], c45 = r2[2];
+    const float c[6] = {(float)c01.x, (float)c01.y, (float)c23.x, (float)c23.y, (float)c45.x, (float)c45.y};
+    float f = c[NO - 1];
+#pragma unroll
+    for (int j = NO - 2; j >= 0; --j) f = c[j] + f * d;
+    return f;
+}
+
 template <typename R> struct BoysOrder;
 template <> struct BoysOrder<double> { static constexpr int value = BOYS_ORDER64; };
 template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32; };
@@ -179,9 +205,9 @@ template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32;
 // F_{m+1} = ((2m+1) F_m - e^{-T})/(2T), stable for T >> m (for L = 1 the
 // exponential term is below rounding and dropped).
 // tab: the order-L block (followed by the order-0 block when L = 1), rows S
-// elements apart.
-template <typename R, int L, int S = BOYS_ROW>
-__device__ __forceinline__ void boys_eval(R T, R* F, const R* __restrict__ tab) {
+// elements apart, in the evaluation's precision or (FP32 evaluation) FP64.
+template <typename R, int L, int S = BOYS_ROW, typename TT = R>
+__device__ __forceinline__ void boys_eval(R T, R* F, const TT* __restrict__ tab) {
     constexpr int NO = BoysOrder<R>::value;
     if constexpr (L <= 1) {
         if (T < R(BOYS_TMAX)) {

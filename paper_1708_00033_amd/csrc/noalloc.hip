@@ -28,13 +28,12 @@ std::mutex g_mu;
 unsigned char* g_scratch[kMaxDevices] = {nullptr};   // device address of `scratch` per device
 
 // Layout of the array (byte offsets).
-constexpr size_t kCountersOff = 0;      // 43 x u64: 42 quartet counters, then the non-finite flag
-constexpr size_t kDmaxOff = 512;        // 1 x u64
-constexpr size_t kWorkOff = 4096;       // 16 x u64 per launch plan
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kCountersOff = 0;      // HFX_CNT_WORDS quartet-counter words, then the non-finite flag
+constexpr size_t kDmaxOff = align256((HFX_CNT_WORDS + 1) * sizeof(unsigned long long));   // 1 x u64
+constexpr size_t kWorkOff = kDmaxOff + 256;   // 16 x u64 per launch plan
 constexpr size_t kMaxPlans = 512;
 constexpr size_t kMatOff = kWorkOff + kMaxPlans * 16 * sizeof(unsigned long long);   // D', then W
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -74,7 +73,7 @@ extern "C" hfx_status hfx_build_2e_noalloc_dev(hfx_ctx* c, const double* dD, dou
     if (e != hipSuccess) return hfx_hip_check(c, e, "hipSetDevice");
     BuildBufs b;
     b.counters = reinterpret_cast<unsigned long long*>(base + kCountersOff);
-    b.bad = reinterpret_cast<int*>(b.counters + 42);
+    b.bad = reinterpret_cast<int*>(b.counters + HFX_CNT_WORDS);
     b.dmax = reinterpret_cast<unsigned long long*>(base + kDmaxOff);
     b.work = reinterpret_cast<unsigned long long*>(base + kWorkOff);
     b.Dp = reinterpret_cast<double*>(base + kMatOff);

@@ -120,9 +120,10 @@ def test_mixed_precision_dimer(dimer):
 
 @pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1), (2, -1)])
 def test_mixed_precision_16_waters(persistent, digest):
-    """A mixed build runs an FP64 kernel before each bra's split and an FP32
-    kernel from it on; a 16-water cluster puts a large share in FP32.  Both
-    launch forms and both digestions agree with FP64 within tolerance."""
+    """A mixed build evaluates each task's kets before its split in FP64 and
+    the rest in FP32, in one launch; a 16-water cluster puts a large share in
+    FP32.  Every launch form and both digestions agree with FP64 within
+    tolerance."""
     m = W.water_cluster(16, 77)
     D = W.random_orthonormal_density(m.nbf, m.nocc, 5)
     F64, s64 = _hfx().Context().load(m).build_fock(D)
@@ -242,8 +243,10 @@ def test_screening_threshold_edge(dimer):
 
 
 def test_cluster64_sampled_blocks():
-    """Full-size 64-water build in the benchmark's launch configuration,
-    checked on shell blocks the oracle computes one by one."""
+    """Full-size 64-water build with the library's default launch forms
+    (static workgroup tasks; the benchmark's autotuned persistent forms are
+    covered against the stored oracle golden in test_gpu_fp32_full), checked
+    on four shell blocks of J and K that the oracle computes one by one."""
     import torch
     import oracle
     m = W.cluster64_config()
