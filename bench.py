@@ -294,9 +294,11 @@ def graphene_bench(args, log):
 def large_bench(args, log):
     """512 waters (9728 basis functions), Schwarz tau 1e-11: the full build
     (or one GPU's share, bra pairs r with r mod G = 0, of a G-GPU build) in
-    FP64 and mixed with every class's FP32 kernel (with --large-tuned also
-    mixed with the FP32 kernel only for the classes it ran faster), from a
-    rank-2560 projector density; with --large-scf also full SCF."""
+    FP64 and mixed (every class's FP32 evaluation on; with --large-tuned also
+    mixed with FP32 only for the classes where it ran faster), from a
+    rank-2560 projector density, every class in the persistent launch form
+    with LDS digestion (--large-static: the library's default static form);
+    with --large-scf also full SCF."""
     import numpy as np
     import torch
     import workloads as W
@@ -306,6 +308,8 @@ def large_bench(args, log):
     t0 = time.time()
     ctx = hfx.Context(device=0, schwarz_tau=1e-11).load(mol)
     t_load = time.time() - t0
+    if not args.large_static:
+        ctx.set_class_tuning(-1, 32768, 0, 1, -1)
     counts = ctx.class_counts()
     quartets = int(counts[:, 0].sum())
     log(f"512 waters loaded in {t_load:.1f} s: nbf={ctx.nbf} quartets={quartets:.4e}")
@@ -319,7 +323,9 @@ def large_bench(args, log):
                        + ("" if G == 1 else f"; one GPU's share (1/{G} of the bra pairs) of a {G}-GPU build"),
            "nbf": ctx.nbf, "quartets_per_build": quartets, "integrals_per_build": int(counts[:, 1].sum()),
            "primitive_quartets_per_build": int(counts[:, 2].sum()), "load_s": t_load, "shards": G,
-           "digest_modes": sorted(set(p["mode"] for p in ctx.plans()))}
+           "digest_modes": sorted(set(p["mode"] for p in ctx.plans())),
+           "launch_form": "static (library default)" if args.large_static else
+                          "persistent, 32768 quartets per task, LDS digestion where the rows fit"}
     Gtn = torch.empty_like(D)
     class_ms = {}
     legs = ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"))
@@ -381,6 +387,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
     ap.add_argument("--no-large", action="store_true", help="skip the 512-water FP64 and mixed builds")
+    ap.add_argument("--large-static", action="store_true",
+                    help="512 waters: the library's default static launches instead of the persistent form")
     ap.add_argument("--large-tuned", action="store_true",
                     help="512 waters: also a mixed build with the FP32 kernel only where it ran faster")
     ap.add_argument("--no-graphene", action="store_true", help="skip the graphene bilayers")
@@ -555,7 +563,7 @@ def main():
     flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave"}[dom["persistent"]]
+    form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave", 3: "k_class_kr", 4: "k_class_kr"}[dom["persistent"]]
     import gen_eri   # on the path after class_flop_model(); "A": the class's alternative workgroup size
     alt = "A" if dom["wgs"] != gen_eri.wg_size(dom["cls"]) else ""
     kname = f"{form}<Eval{dom['cls']}{alt}, {dom['mode']}, 0> grid {dom['blocks'] * dom['wgs']}"

@@ -3,7 +3,7 @@
 // evaluated in long double from the everywhere-convergent positive series
 //   F_m(T) = e^{-T} sum_{k>=0} (2T)^k / ((2m+1)(2m+3)...(2m+2k+1)),
 // stored per order L as rows F_{L+j}(T_k)/j!, j = 0..7 (Taylor coefficients),
-// the order-L block at position boys_block(L).
+// the order-L block at position boys_block(L); then e^{-T_k} for every k.
 #include <cmath>
 
 #include "hfx_internal.h"
@@ -14,6 +14,7 @@ void hfx_boys_table(double* tab) {
     for (int k = 0; k < BOYS_NT; ++k) {
         const long double T = (long double)k * (long double)BOYS_DT;
         const long double eT = expl(-T);
+        tab[BOYS_EXP_OFF + k] = (double)eT;
         for (int m = 0; m < mmax; ++m) {
             long double term = 1.0L / (2 * m + 1), sum = term;
             for (int j = 1; j < 4000; ++j) {

@@ -430,7 +430,7 @@ __device__ __forceinline__ void flush_counts(const ClassArgs& a, unsigned c64, u
 template <class E>
 struct LdsLayout {
     static constexpr int L = E::LA + E::LB + E::LC + E::LD;
-    static constexpr int ROWS = boys_rows(L) * BOYS_LROW64;   // offset of the bra rows, doubles
+    static constexpr int ROWS = BOYS_NT * BOYS_LROW64;   // offset of the bra rows, doubles
 };
 
 // Uniform per workgroup: padding tasks (XCD striping) and other shards' bras do nothing.
@@ -442,8 +442,9 @@ template <class E>
 __device__ __forceinline__ void load_boys_lds(const ClassArgs& a, double* t64) {
     using LL = LdsLayout<E>;
     const double* __restrict__ g64 = a.boys64 + (size_t)boys_block(LL::L) * BOYS_NT * BOYS_ROW;
-    for (int i = threadIdx.x; i < boys_entries(LL::L); i += E::WGS)
+    for (int i = threadIdx.x; i < boys_entries(); i += E::WGS)
         t64[(i / BOYS_ROW) * BOYS_LROW64 + i % BOYS_ROW] = g64[i];
+    for (int k = threadIdx.x; k < BOYS_NT; k += E::WGS) t64[k * BOYS_LROW64 + BOYS_EXP_SLOT] = a.boys64[BOYS_EXP_OFF + k];
     __syncthreads();
 }
 

@@ -56,6 +56,11 @@ static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}}
 static hfx_status replan(hfx_ctx* c);
 
 constexpr int kXcds = 8;   // XCDs of an MI355X: private digestion keeps one copy of W per XCD
+// Primitive cutoff: a primitive pair whose Gaussian overlap factor
+// exp(-alpha beta / p |AB|^2) is below this is dropped from its shell pair
+// (its contribution to any integral is below 1e-20 of the pair's unscreened
+// scale, far under the quartet screening threshold).
+constexpr double kPrimCut = 1e-20;
 
 // A captured build replays the launch arguments (plans, task buffers,
 // precision split) of the moment it was captured: drop it whenever those
@@ -226,7 +231,7 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         for (int k = 0; k < 21 && ok; ++k) ok = r.scratch[k] <= kScratchBudget;
         if (!ok) { delete c; return HFX_ERR_DEVICE; }
     }
-    std::vector<double> tab((size_t)BOYS_NL * BOYS_NT * BOYS_ROW);
+    std::vector<double> tab((size_t)BOYS_TAB_ENTRIES);
     hfx_boys_table(tab.data());
     if (dalloc(&c->d_boys64, tab.size()) != hipSuccess || dalloc(&c->d_dmax, 1) != hipSuccess ||
         dalloc(&c->d_counters, HFX_CNT_WORDS + 1) != hipSuccess) {
@@ -348,8 +353,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     // with empty tasks (r = -1).
     P.lds_bytes = (size_t)(ncart(kPairL[B][0]) + ncart(kPairL[B][1])) * c->rs * sizeof(double);
     P.fp64_only = nint >= 600;   // see ClassKernels in eri_impl.h
-    const int Ltot = kPairL[B][0] + kPairL[B][1] + kPairL[K][0] + kPairL[K][1];
-    P.lds_tab = (size_t)boys_lds_bytes(Ltot, false);   // FP64 rows (the mixed kernels' FP32 part reads them too)
+    P.lds_tab = (size_t)boys_lds_bytes();   // FP64 rows (the mixed kernels' FP32 part reads them too)
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
     P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab <= 160 * 1024 - 256) ? 0 : 1;
@@ -752,11 +756,14 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
                 const double ab2 = pi.AB[0] * pi.AB[0] + pi.AB[1] * pi.AB[1] + pi.AB[2] * pi.AB[2];
                 pi.prim_off = (int)prim.size();
                 int np = 0;
-                double kmax = 0.0;
                 for (int i = 0; i < SA.nprim; ++i)
                     for (int j = 0; j < SB.nprim; ++j) {
                         const double al = c->exps[SA.prim_off + i], be = c->exps[SB.prim_off + j];
                         const double p = al + be, mu = al * be / p;
+                        const double ek = std::exp(-mu * ab2);
+                        // primitive cutoff: a product of primitives whose Gaussian
+                        // overlap factor is below kPrimCut is left out of the pair
+                        if (ek < kPrimCut) continue;
                         PrimPair pp;
                         pp.p = p;
                         pp.inv2p = 0.5 / p;
@@ -766,20 +773,15 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
                         pp.PA[0] = pp.P[0] - SA.x;
                         pp.PA[1] = pp.P[1] - SA.y;
                         pp.PA[2] = pp.P[2] - SA.z;
-                        const double ek = std::exp(-mu * ab2);
                         // sqrt(2 pi^{5/2}) = sqrt(2) pi^{5/4}
                         pp.K = c->coefs[SA.prim_off + i] * c->coefs[SB.prim_off + j] * ek * 1.4142135623730951 *
                                std::pow(M_PI, 1.25) / p;
                         pp.pad = 0.0;
-                        kmax = std::max(kmax, ek);
                         prim.push_back(pp);
                         ++np;
                     }
                 pi.nprim = np;
-                if (kmax < 1e-40) {   // Gaussian overlap exp(-mu R^2) < 1e-40 for every primitive pair
-                    prim.resize(pi.prim_off);
-                    continue;
-                }
+                if (np == 0) continue;   // every product below the cutoff: the pair vanishes
                 if (prim.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many primitive pairs");
                 all[pair_class(SA.l, SB.l)].push_back(pi);
             }

@@ -110,9 +110,10 @@ __device__ __forceinline__ int hfx_xcc_id() {
 // so that F_L(T) = sum_j block_L[k*8 + j] (T_k - T)^j about the nearest grid
 // point (dF_m/dT = -F_{m+1}); one aligned row is one cache line.  Blocks are
 // stored in the order 1, 0, 2, 3, ... (boys_block) so that the order-0 rows
-// directly follow the order-1 rows: a class of total angular momentum L
-// needs one contiguous range (two blocks for L = 1), which the class kernels
-// copy into LDS.
+// directly follow the order-1 rows: read from global memory, a class of
+// total angular momentum L = 1 takes F_0 from the order-0 row.  The class
+// kernels copy only their order's block into LDS, each row followed by
+// e^{-T_k}: there a class with L = 1 gets F_0 = 2T F_1 + e^{-T} from one row.
 #define BOYS_DT 0.1
 #define BOYS_INV_DT 10.0
 #define BOYS_TMAX 40.0
@@ -122,21 +123,20 @@ __device__ __forceinline__ int hfx_xcc_id() {
 #define BOYS_ORDER64 8   // Taylor terms, FP64 (|T - T_k| <= 0.05: remainder < 1e-15 F)
 #define BOYS_ORDER32 5   // Taylor terms, FP32 (remainder < 3e-9 F)
 
-void hfx_boys_table(double* tab);   // host, BOYS_NL * BOYS_NT * BOYS_ROW entries
+#define BOYS_EXP_OFF (BOYS_NL * BOYS_NT * BOYS_ROW)   // e^{-T_k}, k < BOYS_NT, after the blocks
+#define BOYS_TAB_ENTRIES (BOYS_EXP_OFF + BOYS_NT)
+void hfx_boys_table(double* tab);   // host, BOYS_TAB_ENTRIES entries
 
 __host__ __device__ constexpr int boys_block(int L) { return L == 0 ? 1 : (L == 1 ? 0 : L); }
-// table rows a class of total angular momentum L reads (from its block on)
-__host__ __device__ constexpr int boys_rows(int L) { return (L == 1 ? 2 : 1) * BOYS_NT; }
-__host__ __device__ constexpr int boys_entries(int L) { return boys_rows(L) * BOYS_ROW; }
-// Row strides of the LDS copy of a class's rows: 80 bytes (FP64) and 48
-// bytes (FP32) instead of 64 and 32, so that the 16-byte reads of lanes at
+// LDS copy of a class's block: BOYS_NT rows of BOYS_LROW64 doubles, the
+// row's 8 coefficients, then e^{-T_k} (BOYS_EXP_SLOT), then one pad.  An
+// 80-byte stride instead of 64 makes the 16-byte reads of lanes at
 // different rows start in 8 distinct groups of 4 of the 32 LDS banks rather
-// than in 2 (64 bytes: 16 banks) or 4 (32 bytes) of them.
+// than in 2.
 #define BOYS_LROW64 10
-#define BOYS_LROW32 12
-__host__ __device__ constexpr int boys_lds_bytes(int L, bool fp32) {
-    return fp32 ? boys_rows(L) * BOYS_LROW32 * 4 : boys_rows(L) * BOYS_LROW64 * 8;
-}
+#define BOYS_EXP_SLOT 8
+__host__ __device__ constexpr int boys_entries() { return BOYS_NT * BOYS_ROW; }
+__host__ __device__ constexpr int boys_lds_bytes() { return BOYS_NT * BOYS_LROW64 * 8; }
 
 __device__ __forceinline__ double hfx_sqrt(double x) { return sqrt(x); }
 // 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps
@@ -192,13 +192,21 @@ __device__ __forceinline__ float boys_taylor(const double* __restrict__ row, flo
     return f;
 }
 
+__host__ __device__ constexpr double boys_inv_fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
 template <typename R> struct BoysOrder;
 template <> struct BoysOrder<double> { static constexpr int value = BOYS_ORDER64; };
 template <> struct BoysOrder<float> { static constexpr int value = BOYS_ORDER32; };
 
 // F[0..L] at T.  Below BOYS_TMAX: Taylor expansion of F_L about the nearest
 // grid point, then the downward recursion F_m = (2T F_{m+1} + e^{-T})/(2m+1)
-// (for L = 1 both orders come from their tables, no exponential needed).
+// (for L = 1: from the LDS rows, e^{-T} = e^{-T_k} e^{T_k - T} with a short
+// series for the second factor; from the global table, F_0 from its own
+// row, no exponential needed).
 // For L <= 1 the two regimes are branches; for L >= 2 both are evaluated
 // with one shared exponential and selected per lane.
 // Above: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 to FP64 there) and the upward recursion
@@ -214,7 +222,18 @@ __device__ __forceinline__ void boys_eval(R T, R* F, const TT* __restrict__ tab)
             const int k = (int)(T * R(BOYS_INV_DT) + R(0.5));
             const R d = R(k) * R(BOYS_DT) - T;
             F[L] = boys_taylor<NO>(tab + k * S, d);
-            if constexpr (L == 1) F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * S, d);
+            if constexpr (L == 1) {
+                if constexpr (S > BOYS_EXP_SLOT) {
+                    // e^{d}, |d| <= 0.05: 9 terms (FP64), 5 (FP32), Horner
+                    constexpr int NE = sizeof(R) == 8 ? 9 : 5;
+                    R ed = R(boys_inv_fact(NE - 1));
+#pragma unroll
+                    for (int j = NE - 2; j >= 0; --j) ed = R(boys_inv_fact(j)) + ed * d;
+                    F[0] = R(2) * T * F[1] + R(tab[k * S + BOYS_EXP_SLOT]) * ed;
+                } else {
+                    F[0] = boys_taylor<NO>(tab + (BOYS_NT + k) * S, d);
+                }
+            }
         } else {
             const R rt = hfx_rsqrt(T);
             F[0] = R(0.886226925452758013649083741671) * rt;   // sqrt(pi)/2 / sqrt(T)
