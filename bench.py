@@ -28,8 +28,11 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 SETUP_FLOPS = 20            # per primitive quartet: p+q, 1/(p+q), rho, P-Q, T, prefactor, W-P, W-Q
 BOYS_FLOPS_TAYLOR = 3 * 7 + 4  # 8-term Taylor at the nearest grid point
+# sources that determine the class kernels and their launch plans: counter
+# readings stored under profiles/ apply only while these are unchanged
 KERNEL_SOURCES = ["paper_1708_00033_amd/csrc/eri_impl.h", "paper_1708_00033_amd/csrc/hfx_internal.h",
-                  "paper_1708_00033_amd/csrc/gen_eri.py"]
+                  "paper_1708_00033_amd/csrc/gen_eri.py", "paper_1708_00033_amd/csrc/hfx_api.cpp",
+                  "paper_1708_00033_amd/csrc/eri_dispatch.hip"]
 
 
 def class_flop_model():
@@ -291,11 +294,13 @@ def graphene_bench(args, log):
     return out
 
 
-def large_bench(args, log):
+def large_bench(args, log, fp32_classes=None):
     """512 waters (9728 basis functions), Schwarz tau 1e-11: the full build
     (or one GPU's share, bra pairs r with r mod G = 0, of a G-GPU build) in
-    FP64 and mixed (every class's FP32 evaluation on; with --large-tuned also
-    mixed with FP32 only for the classes where it ran faster), from a
+    FP64 and mixed (FP32 evaluation on for the classes in fp32_classes, the
+    64-water precision autotuner's choice, else for every class; with
+    --large-tuned also mixed with FP32 only for the classes where the
+    all-FP32 build ran faster), from a
     rank-2560 projector density, every class in the persistent launch form
     with LDS digestion (--large-static: the library's default static form);
     with --large-scf also full SCF."""
@@ -331,9 +336,12 @@ def large_bench(args, log):
     legs = ((hfx.HFX_PREC_FP64, G64, "fp64"), (hfx.HFX_PREC_MIXED, Gmx, "mixed"))
     if args.large_tuned:
         legs += ((hfx.HFX_PREC_MIXED, Gtn, "mixed_tuned"),)
+    for k in range(21):
+        ctx.set_class_precision(k, int(fp32_classes is None or hfx.CLASS_NAMES[k] in fp32_classes))
+    out["fp32_classes"] = "all" if fp32_classes is None else list(fp32_classes)
     for prec, Go, tag in (() if args.large_no_builds else legs):
         if tag == "mixed_tuned":
-            # per class, the FP32 kernel only where the all-FP32 build ran the class faster
+            # per class, FP32 only where the mixed build ran the class faster
             for k in range(21):
                 ctx.set_class_precision(k, int(class_ms["mixed"][k] < class_ms["fp64"][k]))
         ctx.configure(precision=prec)
@@ -569,14 +577,23 @@ def main():
     kname = f"{form}<Eval{dom['cls']}{alt}, {dom['mode']}, 0> grid {dom['blocks'] * dom['wgs']}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
+    counted = None
     prof = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if os.path.exists(prof):
         with open(prof) as fh:
             pj = json.load(fh)
-        # per profiled launch form of the dominant class: {kernel: {"hbm_bytes_per_launch": ...}}
+        # per profiled launch: {kernel: {"hbm_bytes_per_launch": ..., "counted_fp64_flops_per_launch": ...}}
         kernels = pj.get("kernels", {pj.get("kernel"): pj})
         if pj.get("source_hash") == source_hash() and kname in kernels:
             traffic = kernels[kname].get("hbm_bytes_per_launch")
+            cf = kernels[kname].get("counted_fp64_flops_per_launch")
+            if cf:
+                # FP64 VALU instructions counted by the hardware (ADD, MUL,
+                # transcendental: 64 flops per wave instruction, FMA: 128),
+                # over the live HIP-event duration of the launch
+                ach = cf / (avg_ms * 1e-3) / 1e12
+                counted = {"flops_per_launch": cf, "achieved": ach, "frac": ach / FP64_PEAK_TFLOPS,
+                           "note": "every lane of a counted wave instruction taken as active"}
     res = {
         "metric": "screened ERI quartets/s + Fock-build time, FP64 vs mixed @1e-6 Eh, 1 GPU",
         "value": value,
@@ -606,7 +623,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": kname, "class": hfx.CLASS_NAMES[dom["cls"]],
                      "ket_nprim": dom["ket_nprim"], "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": traffic, "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch),
+                     "traffic": traffic, "counted": counted,
+                     "avg_launch_ms": avg_ms, "flops_per_launch": float(flops_launch),
                      "quartets_per_launch": dom["quartets"], "primitive_quartets_per_launch": dom["prim"]},
         "build_flops_model_tflops": total_flops / (dt64 / args.steps) / 1e12,
         "build_frac_fp64_peak": total_flops / (dt64 / args.steps) / 1e12 / FP64_PEAK_TFLOPS,
@@ -623,7 +641,7 @@ def main():
     if not args.no_graphene:
         res["graphene"] = graphene_bench(args, log)
     if not args.no_large:
-        res["large"] = large_bench(args, log)
+        res["large"] = large_bench(args, log, fp32_classes)
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -147,11 +147,8 @@ hfx_status hfx_create(const hfx_options *opt, hfx_ctx **out);
 /* Load geometry and basis (section 4.1 shells).  Z[natom] nuclear charges,
  * xyz_bohr[natom*3], shells[nshell] (copied).  Computes normalisation,
  * shell-pair data, Schwarz bounds (on the GPU), the screened quartet plan,
- * and S, H = T + V, E_nuc.  Products of primitives whose Gaussian overlap
- * factor exp(-alpha beta/(alpha+beta) |AB|^2) is below 1e-20 are left out
- * of their shell pair (a pair with none left is dropped).  charge: total
- * molecular charge (even electron count required).  Replaces any previously
- * loaded system. */
+ * and S, H = T + V, E_nuc.  charge: total molecular charge (even electron
+ * count required).  Replaces any previously loaded system. */
 hfx_status hfx_load(hfx_ctx *ctx, int natom, const int *Z, const double *xyz_bohr, int nshell,
                     const hfx_shell *shells, int charge);
 

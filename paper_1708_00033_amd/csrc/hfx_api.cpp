@@ -56,11 +56,6 @@ static const int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}}
 static hfx_status replan(hfx_ctx* c);
 
 constexpr int kXcds = 8;   // XCDs of an MI355X: private digestion keeps one copy of W per XCD
-// Primitive cutoff: a primitive pair whose Gaussian overlap factor
-// exp(-alpha beta / p |AB|^2) is below this is dropped from its shell pair
-// (its contribution to any integral is below 1e-20 of the pair's unscreened
-// scale, far under the quartet screening threshold).
-constexpr double kPrimCut = 1e-20;
 
 // A captured build replays the launch arguments (plans, task buffers,
 // precision split) of the moment it was captured: drop it whenever those
@@ -756,14 +751,11 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
                 const double ab2 = pi.AB[0] * pi.AB[0] + pi.AB[1] * pi.AB[1] + pi.AB[2] * pi.AB[2];
                 pi.prim_off = (int)prim.size();
                 int np = 0;
+                double kmax = 0.0;
                 for (int i = 0; i < SA.nprim; ++i)
                     for (int j = 0; j < SB.nprim; ++j) {
                         const double al = c->exps[SA.prim_off + i], be = c->exps[SB.prim_off + j];
                         const double p = al + be, mu = al * be / p;
-                        const double ek = std::exp(-mu * ab2);
-                        // primitive cutoff: a product of primitives whose Gaussian
-                        // overlap factor is below kPrimCut is left out of the pair
-                        if (ek < kPrimCut) continue;
                         PrimPair pp;
                         pp.p = p;
                         pp.inv2p = 0.5 / p;
@@ -773,15 +765,24 @@ static hfx_status load_batch(hfx_ctx* c, int nmol, const int* natom_m, const int
                         pp.PA[0] = pp.P[0] - SA.x;
                         pp.PA[1] = pp.P[1] - SA.y;
                         pp.PA[2] = pp.P[2] - SA.z;
+                        const double ek = std::exp(-mu * ab2);
                         // sqrt(2 pi^{5/2}) = sqrt(2) pi^{5/4}
                         pp.K = c->coefs[SA.prim_off + i] * c->coefs[SB.prim_off + j] * ek * 1.4142135623730951 *
                                std::pow(M_PI, 1.25) / p;
                         pp.pad = 0.0;
+                        kmax = std::max(kmax, ek);
                         prim.push_back(pp);
                         ++np;
                     }
                 pi.nprim = np;
-                if (np == 0) continue;   // every product below the cutoff: the pair vanishes
+                // Gaussian overlap exp(-mu R^2) < 1e-40 for every primitive pair:
+                // the pair vanishes.  (Dropping single negligible primitive pairs
+                // would split the ket lists by primitive count into more, shorter
+                // lists: more tasks and LDS row flushes than the primitive work saved.)
+                if (kmax < 1e-40) {
+                    prim.resize(pi.prim_off);
+                    continue;
+                }
                 if (prim.size() > (size_t)0x7fffffff) return hfx_fail(c, HFX_ERR_INVALID_ARG, "too many primitive pairs");
                 all[pair_class(SA.l, SB.l)].push_back(pi);
             }
