@@ -1,13 +1,16 @@
 """Train the learned initial guess on converged densities from this SCF and
 evaluate it against the SAD start.
 
-    python -m paper_1708_00033_amd.guess_train --train 600 --eval 4 \\
+    python -m paper_1708_00033_amd.guess_train --train 2000 --eval 0 \\
         --out paper_1708_00033_amd/models/guess_water.npy --report guess_report.json
+    python -m paper_1708_00033_amd.guess_train --eval-only paper_1708_00033_amd/models/guess_water.npy \\
+        --eval 8 --report guess_eval.json
 
 Data: seeded water clusters of 4-32 molecules (training) and of 128
-molecules (evaluation).  For each training cluster the library runs FP64 SCF
-from SAD, then writes the pair features and the converged-minus-SAD blocks
-in the pair frames (hfx_guess_setup / hfx_guess_targets_dev).  Training runs
+molecules (evaluation).  The training clusters' FP64 SCFs from SAD run as
+batches (hfx_batch_scf); then for each cluster the library writes the pair
+features and the converged-minus-SAD blocks in the pair frames
+(hfx_guess_setup / hfx_guess_targets_dev).  Training runs
 the library's BF16 MFMA forward/backward and Adam (hfx_guess_grad_dev,
 hfx_guess_adam) on minibatches gathered on the device.  Evaluation: SCF
 iterations, SCF time and the converged energy from SAD and from the network.
@@ -27,39 +30,52 @@ def log(*a):
     print("[guess]", *a, flush=True)
 
 
-def collect(mols, hfx, torch, stream):
-    """Per pair type: features (rows) and target blocks, from converged SCF."""
+def collect(mols, hfx, torch, stream, chunk=128):
+    """Per pair type: features (rows) and target blocks, from converged SCF.
+    The SCFs run as batches of `chunk` molecules of similar size
+    (hfx_batch_scf, iterations replayed from HIP graphs); the features and
+    targets of each molecule then come from a single-molecule context."""
     X = [[], [], []]
     T = [[], [], []]
+    bctx = hfx.Context(device=0)
     ctx = hfx.Context(device=0)
     iters = []
     t0 = time.time()
-    for i, m in enumerate(mols):
-        ctx.load(m)
-        r = ctx.scf()
-        if not r["converged"]:
-            log(f"cluster {i} ({m.natom // 3} waters) did not converge; skipped")
-            continue
-        iters.append(r["iterations"])
-        Dsad = ctx.sad_density()
-        counts = ctx.guess_setup()
-        Xh, _, _ = ctx.guess_features()
-        dD = torch.tensor(r["D"], device="cuda")
-        dS = torch.tensor(Dsad, device="cuda")
-        dT = torch.empty(ctx.guess_packed_size(), dtype=torch.float32, device="cuda")
-        ctx.guess_targets_dev(dD.data_ptr(), dS.data_ptr(), dT.data_ptr(), stream.cuda_stream)
-        stream.synchronize()
-        Th = dT.cpu().numpy()
-        ro, to = 0, 0
-        for t, (c, w) in enumerate(zip(counts, hfx.GUESS_HEAD_OUT)):
-            X[t].append(Xh[ro:ro + c])
-            T[t].append(Th[to:to + c * w].reshape(c, w))
-            ro += c
-            to += c * w
-        if (i + 1) % 25 == 0:
-            log(f"collected {i + 1}/{len(mols)} clusters ({time.time() - t0:.0f} s, "
-                f"mean SAD-start iterations {np.mean(iters):.1f})")
+    order = sorted(range(len(mols)), key=lambda i: mols[i].nbf)
+    done = 0
+    for b0 in range(0, len(order), chunk):
+        part = [mols[i] for i in order[b0:b0 + chunk]]
+        bctx.load_batch(part)
+        res, Drag = bctx.batch_scf(graph=1)
+        nbf, _, off, _ = bctx.layout
+        for j, m in enumerate(part):
+            if not res[j]["converged"]:
+                log(f"a cluster of {m.natom // 3} waters did not converge; skipped")
+                continue
+            iters.append(res[j]["iterations"])
+            n = int(nbf[j])
+            D = Drag[int(off[j]):int(off[j]) + n * n].reshape(n, n)
+            ctx.load(m)
+            Dsad = ctx.sad_density()
+            counts = ctx.guess_setup()
+            Xh, _, _ = ctx.guess_features()
+            dD = torch.tensor(D, device="cuda")
+            dS = torch.tensor(Dsad, device="cuda")
+            dT = torch.empty(ctx.guess_packed_size(), dtype=torch.float32, device="cuda")
+            ctx.guess_targets_dev(dD.data_ptr(), dS.data_ptr(), dT.data_ptr(), stream.cuda_stream)
+            stream.synchronize()
+            Th = dT.cpu().numpy()
+            ro, to = 0, 0
+            for t, (c, w) in enumerate(zip(counts, hfx.GUESS_HEAD_OUT)):
+                X[t].append(Xh[ro:ro + c])
+                T[t].append(Th[to:to + c * w].reshape(c, w))
+                ro += c
+                to += c * w
+        done += len(part)
+        log(f"collected {done}/{len(mols)} clusters ({time.time() - t0:.0f} s, "
+            f"mean SAD-start iterations {np.mean(iters):.1f})")
     ctx.close()
+    bctx.close()
     X = [np.concatenate(x) if x else np.zeros((0, hfx.GUESS_NFEAT), np.float32) for x in X]
     T = [np.concatenate(x) if x else np.zeros((0, w), np.float32) for x, w in zip(T, hfx.GUESS_HEAD_OUT)]
     return X, T, iters
@@ -111,8 +127,8 @@ def _means(ev):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=600, help="training clusters (4-32 waters)")
-    ap.add_argument("--eval", type=int, default=4, help="128-water evaluation clusters")
+    ap.add_argument("--train", type=int, default=2000, help="training clusters (4-32 waters)")
+    ap.add_argument("--eval", type=int, default=8, help="128-water evaluation clusters")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
