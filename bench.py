@@ -571,10 +571,22 @@ def main():
     flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave", 3: "k_class_kr", 4: "k_class_kr"}[dom["persistent"]]
     import gen_eri   # on the path after class_flop_model(); "A": the class's alternative workgroup size
-    alt = "A" if dom["wgs"] != gen_eri.wg_size(dom["cls"]) else ""
-    kname = f"{form}<Eval{dom['cls']}{alt}, {dom['mode']}, 0> grid {dom['blocks'] * dom['wgs']}"
+
+    def launch_shape(p):
+        """Kernel symbol and grid of a plan's FP64 launch, as rocprofv3 names them."""
+        alt = "A" if p["wgs"] != gen_eri.wg_size(p["cls"]) else ""
+        if p["persistent"] in (3, 4):
+            return f"k_class_kr<Eval{p['cls']}{alt}, {p['mode']}, {p['ket_nprim']}, {p['bras_per_task']}> " \
+                   f"grid {p['blocks'] * p['wgs']}"
+        form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave"}[p["persistent"]]
+        return f"{form}<Eval{p['cls']}{alt}, {p['mode']}, 0> grid {p['blocks'] * p['wgs']}"
+
+    kname = launch_shape(dom)
+    # launches of one class against several ket lists can share a kernel and grid: the
+    # profiles key each by its position among them in a build
+    same = [q for q in plans64 if launch_shape(q) == kname]
+    kname_launch = f"{kname} launch {next(i for i, q in enumerate(same) if q is dom) + 1} of {len(same)}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
     counted = None
@@ -584,9 +596,9 @@ def main():
             pj = json.load(fh)
         # per profiled launch: {kernel: {"hbm_bytes_per_launch": ..., "counted_fp64_flops_per_launch": ...}}
         kernels = pj.get("kernels", {pj.get("kernel"): pj})
-        if pj.get("source_hash") == source_hash() and kname in kernels:
-            traffic = kernels[kname].get("hbm_bytes_per_launch")
-            cf = kernels[kname].get("counted_fp64_flops_per_launch")
+        if pj.get("source_hash") == source_hash() and kname_launch in kernels:
+            traffic = kernels[kname_launch].get("hbm_bytes_per_launch")
+            cf = kernels[kname_launch].get("counted_fp64_flops_per_launch")
             if cf:
                 # FP64 VALU instructions counted by the hardware (ADD, MUL,
                 # transcendental: 64 flops per wave instruction, FMA: 128),
@@ -620,7 +632,7 @@ def main():
                   "dE_vs_fp64_at_fixed_D": dE,
                   "build_flops_model_tflops": total_flops / (dtmx / args.steps) / 1e12,
                   "build_frac_fp64_peak": total_flops / (dtmx / args.steps) / 1e12 / FP64_PEAK_TFLOPS},
-        "roofline": {"bound": "alu", "kernel": kname, "class": hfx.CLASS_NAMES[dom["cls"]],
+        "roofline": {"bound": "alu", "kernel": kname, "launch": kname_launch, "class": hfx.CLASS_NAMES[dom["cls"]],
                      "ket_nprim": dom["ket_nprim"], "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "counted": counted,

@@ -23,10 +23,14 @@ from . import hfx
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
     (2048, 0, 0, -1), (2048, 1, 0, -1), (8192, 0, 0, -1), (8192, 1, 0, -1), (32768, 0, 0, -1), (32768, 1, 0, -1),
     (2048, 1, 1, -1), (8192, 1, 1, -1), (8192, 0, 0, 1), (32768, 0, 0, 1), (8192, 1, 2, -1), (32768, 0, 2, -1),
-    (32768, 0, 3, -1), (32768, 0, 4, -1), (8192, 1, 4, -1), (32768, 0, 1, 2))
+    (32768, 0, 3, -1), (32768, 0, 4, -1), (8192, 1, 4, -1), (32768, 0, 1, 2), (32768, 0, 1, -1))
 
 
-PREFERRED: Tuple[int, int, int, int] = (32768, 0, 0, -1)
+# Kept unless another candidate is clearly faster: the persistent form, whose
+# resident workgroups drain the XCD queues in order, re-reads the ket lists
+# from HBM several times less than one workgroup per task at about the same
+# speed.
+PREFERRED: Tuple[int, int, int, int] = (32768, 0, 1, -1)
 _PAD = (0, 0, 0, -1)
 
 

@@ -18,6 +18,8 @@ static const void* (*const kClassLookup[21])(int) = {HFX_FOR_EACH_CID(HFX_KPTR)}
 static const void* (*const kClassLookupKr[21])(int) = {HFX_FOR_EACH_CID(HFX_RPTR)};
 static const void* (*const kSchwarzLookup[21])(void) = {HFX_FOR_EACH_CID(HFX_SPTR)};
 
+extern "C" int hfx_class_wgs(int cid, int alt);
+
 // Register-tiled kernels: variant index of (digestion mode, ket primitive
 // count, bras per block), or -1 when the class has none for that count.
 static int kr_variant(int cid, int mode, int kp, int nbl) {
@@ -40,7 +42,7 @@ extern "C" hipError_t hfx_launch_class_kr(int cid, int mode, int kp, int nbl, in
         if (e != hipSuccess) return e;
     }
     void* kargs[] = {(void*)args};
-    return hipLaunchKernel(fn, dim3(nblocks), dim3(kEriClassInfo[cid].wgs), kargs, lds_bytes, stream);
+    return hipLaunchKernel(fn, dim3(nblocks), dim3(hfx_class_wgs(cid, 1)), kargs, lds_bytes, stream);
 }
 
 extern "C" int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, size_t lds_bytes) {
@@ -51,7 +53,7 @@ extern "C" int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, 
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
         return 0;
     int per_cu = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEriClassInfo[cid].wgs, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hfx_class_wgs(cid, 1), lds_bytes) != hipSuccess)
         return 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)

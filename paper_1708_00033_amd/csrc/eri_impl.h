@@ -1080,8 +1080,11 @@ struct ClassKernelsKr {
     }
 };
 
+// Register-tiled kernels use the class's alternative (smaller) workgroup
+// size: the ket primitives in registers need more than the 128 VGPRs a
+// 1024-lane workgroup leaves each lane.
 #define HFX_CLASS_KR(cid) \
-    extern "C" const void* hfx_class_kernel_kr_##cid(int v) { return ClassKernelsKr<Eval##cid>::get(v); }
+    extern "C" const void* hfx_class_kernel_kr_##cid(int v) { return ClassKernelsKr<Eval##cid##A>::get(v); }
 #define HFX_CLASS_NO_KR(cid) \
     extern "C" const void* hfx_class_kernel_kr_##cid(int) { return nullptr; }
 

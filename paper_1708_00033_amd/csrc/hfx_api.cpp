@@ -362,7 +362,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     const int form = c->tune_persist[P.cid];
     if ((form == 3 || form == 4) && hfx_class_has_kr(P.cid, KL.kp) && nbra < (1 << 28)) {
         P.kr = true;
-        P.alt = 0;
+        P.alt = 1;   // the register-tiled kernels use the class's alternative workgroup size
         P.nbl = form == 3 ? 2 : 1;
         if (P.mode == 0 && P.lds() > 160 * 1024 - 256) P.nbl = 1;
     }
