@@ -262,7 +262,7 @@ def graphene_bench(args, log):
     """The paper's own workload shape (section 5.2, Table 4): AB-stacked
     graphene bilayers with 15 basis functions per carbon in SP and d shells
     (synthetic exponents), one FP64 Fock build each from a projector density,
-    default launch configuration."""
+    every class in the persistent launch form."""
     import numpy as np
     import torch
     import workloads as W
@@ -275,6 +275,7 @@ def graphene_bench(args, log):
         t0 = time.time()
         ctx = hfx.Context(device=0).load(mol)
         t_load = time.time() - t0
+        ctx.set_class_tuning(-1, 32768, 0, 1, -1)
         counts = ctx.class_counts()
         q = int(counts[:, 0].sum())
         D = torch.tensor(W.random_orthonormal_density(mol.nbf, mol.nocc, 7), device="cuda:0")
