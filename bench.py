@@ -346,22 +346,26 @@ def large_bench(args, log, fp32_classes=None):
             for k in range(21):
                 ctx.set_class_precision(k, int(class_ms["mixed"][k] < class_ms["fp64"][k]))
         ctx.configure(precision=prec)
-        ctx.kernel_timing(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         st = ctx.build_2e_shard_dev(D.data_ptr(), 2.0, 1.0, 0, G, Go.data_ptr(), sp, stats=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        ms, n = ctx.kernel_times()
-        ctx.kernel_timing(False)
-        class_ms[tag] = ms
+        if args.large_tuned and tag != "mixed_tuned":   # per-class times: one more build with launch events
+            ctx.kernel_timing(True)
+            ctx.build_2e_shard_dev(D.data_ptr(), 2.0, 1.0, 0, G, Go.data_ptr(), sp)
+            torch.cuda.synchronize()
+            class_ms[tag], _ = ctx.kernel_times()
+            ctx.kernel_timing(False)
         q = int(st.quartets_fp64 + st.quartets_fp32)
         planned_share = int(sum(p["quartets"] for p in ctx.plans())) if G == 1 else None
         if G == 1 and (q != quartets or q != planned_share):
             raise RuntimeError(f"evaluated {q} quartets, planned {quartets}")
         out[tag] = {"share_build_s": dt, "share_quartets": q, "quartets_per_s": q / dt,
-                    "quartets_fp32": int(st.quartets_fp32),
-                    "class_ms": {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}}
+                    "quartets_fp32": int(st.quartets_fp32)}
+        if tag in class_ms:
+            ms = class_ms[tag]
+            out[tag]["class_ms"] = {hfx.CLASS_NAMES[k]: round(float(ms[k]), 1) for k in np.argsort(-ms)[:6]}
         log(f"512 waters {tag} share build: {dt:.2f} s, {q:.3e} quartets, {q / dt:.3e} quartets/s")
     if not args.large_no_builds:
         out["mixed"]["max_abs_dG_vs_fp64"] = (Gmx - G64).abs().max().item()
@@ -412,7 +416,8 @@ def main():
     ap.add_argument("--tuning", default="", help="profile runs: apply this saved autotuner table")
     ap.add_argument("--save-tuning", default="", help="write the autotuner table here")
     ap.add_argument("--profile", action="store_true",
-                    help="profiling run: synthetic projector density, FP64 builds only, no SCF and no CPU leg")
+                    help="profiling run: synthetic projector density, FP64 builds only (class launches on one "
+                         "stream), no SCF and no CPU leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (HBM-counter calibration for profiling runs)")
     args = ap.parse_args()
@@ -446,6 +451,9 @@ def main():
             autotune.apply(ctx, autotune.load(args.tuning))
         else:
             ctx.set_class_tuning(-1, *autotune.PREFERRED)
+        # launches in order on one stream, as in the builds the per-launch
+        # times come from: a dispatch's trace interval and counters are then its own
+        ctx.set_streams(1)
         for _ in range(args.warmup + args.steps):
             ctx.build_fock_dev(D.data_ptr(), F.data_ptr(), sptr)
         torch.cuda.synchronize()
@@ -483,13 +491,18 @@ def main():
         for _ in range(args.warmup):
             ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr)
         torch.cuda.synchronize()
-        ctx.kernel_timing(True)
-        torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(nsteps):
             ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
+        # per-launch durations: the same builds again with HIP events around
+        # every class launch (the library then keeps the launches in order on
+        # this one stream, so each pair of events brackets only its kernel)
+        ctx.kernel_timing(True)
+        for _ in range(nsteps):
+            ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), sptr)
+        torch.cuda.synchronize()
         ms, n = ctx.kernel_times()
         plans = ctx.plans()
         ctx.kernel_timing(False)

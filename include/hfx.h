@@ -315,6 +315,16 @@ hfx_status hfx_class_counts(const hfx_ctx *ctx, long long *counts);
 hfx_status hfx_kernel_timing(hfx_ctx *ctx, int enable);
 hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 
+/* Streams of a build's class launches (1..4, default 2): with n > 1 the
+ * launches are dealt round-robin over the caller's stream and n - 1 side
+ * streams that the context owns, forked from and joined back into the
+ * caller's stream (also under HIP graph capture), so a launch starts on the
+ * CUs that the previous one frees while its last tasks finish.  While kernel
+ * timing is enabled every launch runs on the caller's stream, in order, so
+ * that its events bracket only its own kernel.  Results are unchanged up to
+ * the order of floating-point sums. */
+hfx_status hfx_set_streams(hfx_ctx *ctx, int n);
+
 /* Launches of a build: one per (quartet class, ket primitive count).
  * info[12] = {class index, ket primitives per pair, workgroup tasks, unique
  * quartets, primitive quartets, integrals, timed launches, digestion used

@@ -245,6 +245,14 @@ extern "C" hfx_status hfx_create(const hfx_options* opt, hfx_ctx** out) {
         hfx_destroy(c);
         return HFX_ERR_DEVICE;
     }
+    bool ev_ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int s = 0; s < hfx_ctx::kMaxStreams - 1 && ev_ok; ++s)
+        ev_ok = hipStreamCreateWithFlags(&c->side[s], hipStreamNonBlocking) == hipSuccess &&
+                hipEventCreateWithFlags(&c->ev_join[s], hipEventDisableTiming) == hipSuccess;
+    if (!ev_ok) {
+        hfx_destroy(c);
+        return HFX_ERR_DEVICE;
+    }
     c->d_bad = (int*)(c->d_counters + HFX_CNT_WORDS);
     *out = c;
     return HFX_OK;
@@ -259,6 +267,11 @@ extern "C" void hfx_destroy(hfx_ctx* c) {
     dfree(c->d_counters);
     c->d_bad = nullptr;
     if (c->blas) rocblas_destroy_handle(c->blas);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (int s = 0; s < hfx_ctx::kMaxStreams - 1; ++s) {
+        if (c->side[s]) (void)hipStreamDestroy(c->side[s]);
+        if (c->ev_join[s]) (void)hipEventDestroy(c->ev_join[s]);
+    }
     delete c;
 }
 
@@ -1094,6 +1107,14 @@ extern "C" hfx_status hfx_kernel_timing(hfx_ctx* c, int enable) {
     return HFX_OK;
 }
 
+extern "C" hfx_status hfx_set_streams(hfx_ctx* c, int n) {
+    if (!c) return HFX_ERR_INVALID_ARG;
+    if (n < 1 || n > hfx_ctx::kMaxStreams)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG, "set_streams: between 1 and 4 streams");
+    c->nstreams = n;
+    return HFX_OK;
+}
+
 extern "C" hfx_status hfx_kernel_times(hfx_ctx* c, double* ms, long long* launches) {
     if (!c) return HFX_ERR_INVALID_ARG;
     collect_timing(c);
@@ -1164,6 +1185,38 @@ hfx_status hfx_build_internal(hfx_ctx* c, const double* dD, double cj, double ck
     return hfx_build_with(c, b, dD, cj, ck, dH, dOut, st, stats, shard, nshards);
 }
 
+// Streams of a build's class launches: the launch plans are dealt
+// round-robin over the caller's stream and ns - 1 side streams, so a launch
+// on one stream fills the CUs that the previous launch on another stream
+// frees while its last tasks finish (every class kernel accumulates with
+// atomics, so concurrent launches need no ordering).  Per-launch timing keeps
+// every launch on the caller's stream: its events then bracket only its own
+// kernel.
+static int build_streams(const hfx_ctx* c) {
+    return c->timing ? 1 : std::min<int>(c->nstreams, (int)c->plans.size());
+}
+
+static hipError_t fork_streams(hfx_ctx* c, int ns, hipStream_t st) {
+    if (ns <= 1) return hipSuccess;
+    hipError_t e = hipEventRecord(c->ev_fork, st);   // after all earlier work on the caller's stream
+    for (int s = 0; s < ns - 1 && e == hipSuccess; ++s) e = hipStreamWaitEvent(c->side[s], c->ev_fork, 0);
+    return e;
+}
+
+static hipError_t join_streams(hfx_ctx* c, int ns, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < ns - 1 && e == hipSuccess; ++s) {
+        e = hipEventRecord(c->ev_join[s], c->side[s]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, c->ev_join[s], 0);
+    }
+    return e;
+}
+
+static hipStream_t plan_stream(const hfx_ctx* c, int ns, size_t pi, hipStream_t st) {
+    const int k = (int)(pi % (size_t)ns);
+    return k ? c->side[k - 1] : st;
+}
+
 hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, double cj, double ck,
                           const double* dH, double* dOut, hipStream_t st, hfx_fock_stats* stats, int shard,
                           int nshards) {
@@ -1192,14 +1245,17 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         if (!c->d_Wrep) return hfx_fail(c, HFX_ERR_STATE, "build: private digestion without its copies of W");
         HIPCK(hfx_fill(c->d_Wrep, kXcds * nn, 0.0, st));
     }
+    const int ns = build_streams(c);
+    HIPCK(fork_streams(c, ns, st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
         const int cid = P.cid;
         const bool mx = mixed && !P.fp64_only && c->tune_fp32[cid] && !P.kr;
+        const hipStream_t ps = plan_stream(c, ns, pi, st);
         if (mx)
             HIPCK(hfx_split(c->d_pairs[P.B], KL.d_q, P.d_tasks, P.ntask, c->opt.fp32_tau, bufs.dmax, P.d_split,
-                            st));
+                            ps));
         ClassArgs a;
         a.bra = c->d_pairs[P.B];
         a.ket = KL.d_pairs;
@@ -1237,26 +1293,27 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         // kMaxGroups (2^20 x 1024 lanes < 2^32 work-items; a multiple of 8
         // keeps workgroup i on XCD i mod 8 in step with the task queues)
         constexpr int kMaxGroups = 1 << 20;
-        if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, st));
+        if (c->timing && P.ev0) HIPCK(hipEventRecord(P.ev0, ps));
         // one launch per plan; a mixed build's kernel evaluates each task's
         // kets before its split in FP64 and the rest in FP32
         const int m = mx ? 1 : 0;
         if (P.kr) {
-            HIPCK(hfx_launch_class_kr(cid, P.mode, KL.kp, P.nbl, P.nblocks[0], P.lds(), st, &a));
+            HIPCK(hfx_launch_class_kr(cid, P.mode, KL.kp, P.nbl, P.nblocks[0], P.lds(), ps, &a));
         } else if (P.persist) {
-            HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, m, P.nblocks[m], P.lds(), st, &a));
+            HIPCK(hfx_launch_class(cid, P.alt, P.wave > 0, P.mode, m, P.nblocks[m], P.lds(), ps, &a));
         } else {
             for (int off = 0; off < P.ntask; off += kMaxGroups) {
                 a.task_off = off;
-                HIPCK(hfx_launch_class(cid, P.alt, 0, P.mode, m, std::min(kMaxGroups, P.ntask - off), P.lds(), st,
+                HIPCK(hfx_launch_class(cid, P.alt, 0, P.mode, m, std::min(kMaxGroups, P.ntask - off), P.lds(), ps,
                                        &a));
             }
         }
         if (c->timing && P.ev1) {
-            HIPCK(hipEventRecord(P.ev1, st));
+            HIPCK(hipEventRecord(P.ev1, ps));
             P.pending = true;
         }
     }
+    HIPCK(join_streams(c, ns, st));
     if (any_priv) HIPCK(hfx_reduce_replicas(c->d_Wrep, kXcds, nn, bufs.W, st));
     for (auto& KL : c->ketlists)
         HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]), KL.d_wket, c->d_moff, bufs.W,
@@ -1379,9 +1436,12 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
     }
     HIPCK(hfx_fill_u64(c->d_multi_work, (int)nwork, st));
     size_t wofs = 0;
+    const int ns = build_streams(c);
+    HIPCK(fork_streams(c, ns, st));
     for (size_t pi = 0; pi < c->plans.size(); ++pi) {
         const SubPlan& P = c->plans[pi];
         const KetList& KL = c->ketlists[P.list];
+        const hipStream_t ps = plan_stream(c, ns, pi, st);
         ClassArgs a;
         std::memset(&a, 0, sizeof(a));
         a.bra = c->d_pairs[P.B];
@@ -1423,9 +1483,10 @@ extern "C" hfx_status hfx_build_jk_multi_dev(hfx_ctx* c, int ndens, const double
             b.work = c->d_multi_work + wofs;
             wofs += 8;
             const size_t lds = P.lds_tab + (gmode[pi] == 0 ? (size_t)b.ndens * P.lds_bytes : 0);
-            HIPCK(hfx_launch_class_multi(P.cid, gmode[pi], nblocks, lds, st, &b));
+            HIPCK(hfx_launch_class_multi(P.cid, gmode[pi], nblocks, lds, ps, &b));
         }
     }
+    HIPCK(join_streams(c, ns, st));
     for (auto& KL : c->ketlists)   // each density's ket-block J sums into its J accumulator
         for (int d = 0; d < ndens; ++d)
             HIPCK(hfx_scatter_ket(KL.d_pairs, KL.n, ncart(kPairL[KL.K][0]), ncart(kPairL[KL.K][1]),

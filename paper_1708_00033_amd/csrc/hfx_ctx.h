@@ -151,6 +151,14 @@ struct hfx_ctx {
     // timing
     bool timing = false;
     hipStream_t last_stream = nullptr;
+    // class launches of a build spread over the caller's stream and
+    // nstreams - 1 side streams (created with the context, default
+    // priority), forked from and joined back into the caller's stream
+    static constexpr int kMaxStreams = 4;
+    int nstreams = 2;
+    hipStream_t side[kMaxStreams - 1] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kMaxStreams - 1] = {};
 };
 
 // Per-build scratch of one Fock build: the accumulator W and the

@@ -115,6 +115,7 @@ _sigs = {
     "hfx_set_class_precision": ([_ctx_p, C.c_int, C.c_int], C.c_int),
     "hfx_kernel_timing": ([_ctx_p, C.c_int], C.c_int),
     "hfx_kernel_times": ([_ctx_p, _dp, C.POINTER(C.c_longlong)], C.c_int),
+    "hfx_set_streams": ([_ctx_p, C.c_int], C.c_int),
     "hfx_plan_count": ([_ctx_p, C.POINTER(C.c_int)], C.c_int),
     "hfx_plan_info": ([_ctx_p, C.c_int, C.POINTER(C.c_longlong), _dp], C.c_int),
     "hfx_sad_density": ([_ctx_p, _dp], C.c_int),
@@ -461,6 +462,9 @@ class Context:
 
     def kernel_timing(self, enable: bool = True):
         self._check(hfx_kernel_timing(self.ptr, int(enable)))
+
+    def set_streams(self, n: int):
+        self._check(hfx_set_streams(self.ptr, int(n)))
 
     def plans(self):
         """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, wgs,

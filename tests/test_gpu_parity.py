@@ -361,6 +361,57 @@ def test_scheduling_knobs_do_not_change_results():
     assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item()
 
 
+
+def test_launch_streams_do_not_change_results():
+    """Class launches dealt over 1..4 streams (eager, multi-density and graph-replayed builds) give the
+    one-stream result up to the order of sums; the stream count is range-checked."""
+    import torch
+    hfx = _hfx()
+    m = W.water_cluster(16, 78)
+    ctx = hfx.Context().load(m)
+    D = torch.tensor(W.random_orthonormal_density(m.nbf, m.nocc, 6), device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    for bad in (0, 5):
+        with pytest.raises(RuntimeError):
+            ctx.set_streams(bad)
+    out = torch.empty_like(D)
+    for prec in (hfx.HFX_PREC_FP64, hfx.HFX_PREC_MIXED):
+        ctx.configure(precision=prec)
+        ctx.set_streams(1)
+        ref = torch.empty_like(D)
+        ctx.build_fock_dev(D.data_ptr(), ref.data_ptr(), s)
+        torch.cuda.synchronize()
+        for ns in (2, 3, 4):
+            ctx.set_streams(ns)
+            st = ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), s, stats=True)
+            assert st.quartets_fp64 + st.quartets_fp32 == int(ctx.class_counts()[:, 0].sum())
+            assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item(), (prec, ns)
+    ctx.configure(precision=hfx.HFX_PREC_FP64)
+    ctx.set_streams(1)
+    ref = torch.empty_like(D)
+    ctx.build_fock_dev(D.data_ptr(), ref.data_ptr(), s)
+    DD = torch.stack([D, D.flip(0).flip(1)]).contiguous()
+    J1, K1 = torch.empty_like(DD), torch.empty_like(DD)
+    ctx.build_jk_multi_dev(2, DD.data_ptr(), J1.data_ptr(), K1.data_ptr(), s)
+    ctx.set_streams(3)
+    J3, K3 = torch.empty_like(DD), torch.empty_like(DD)
+    ctx.build_jk_multi_dev(2, DD.data_ptr(), J3.data_ptr(), K3.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert (J3 - J1).abs().max().item() <= 1e-13 * J1.abs().max().item()
+    assert (K3 - K1).abs().max().item() <= 1e-13 * K1.abs().max().item()
+    # captured with three streams: the side streams fork from and join into the capturing stream
+    cs = torch.cuda.Stream()
+    G = torch.zeros_like(D)
+    ctx.graph_capture(D.data_ptr(), G.data_ptr(), cs.cuda_stream)
+    for r in range(3):
+        G.zero_()
+        ctx.build_fock_dev(D.data_ptr(), out.data_ptr(), s)   # eager work between the replays
+        torch.cuda.synchronize()
+        ctx.graph_launch(cs.cuda_stream)
+        torch.cuda.synchronize()
+        assert (G - ref).abs().max().item() <= 1e-13 * ref.abs().max().item(), r
+        assert (out - ref).abs().max().item() <= 1e-13 * ref.abs().max().item(), r
+
 @pytest.mark.parametrize("digest", [0, 1])
 def test_register_tiled_form_all_classes(four_waters, digest):
     """Launch form 3 (ket primitives in registers, blocks of two bras with
