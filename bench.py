@@ -395,7 +395,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--digest", type=int, default=0)
+    ap.add_argument("--digest", type=int, default=3,
+                    help="digestion: 0 LDS rows of F, 1 global atomics, 2 per-XCD copies, 3 LDS rows of F and D")
     ap.add_argument("--task", type=int, default=8192)
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-class autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-cluster batched comparison")
@@ -526,8 +527,8 @@ def main():
 
     # the three digestions of eq. 2 on the same launch form, per class
     digestion = {}
-    for dg, name in ((hfx.HFX_DIGEST_LDS, "lds_staged"), (hfx.HFX_DIGEST_GLOBAL, "global_atomic"),
-                     (hfx.HFX_DIGEST_PRIVATE, "private_per_xcd")):
+    for dg, name in ((hfx.HFX_DIGEST_LDS_D, "lds_staged_f_and_d_rows"), (hfx.HFX_DIGEST_LDS, "lds_staged"),
+                     (hfx.HFX_DIGEST_GLOBAL, "global_atomic"), (hfx.HFX_DIGEST_PRIVATE, "private_per_xcd")):
         ctx.set_class_tuning(-1, 32768, 0, 1, dg)
         ctx.build_fock_dev(D.data_ptr(), F64.data_ptr(), sptr)
         torch.cuda.synchronize()
@@ -542,7 +543,7 @@ def main():
         digestion[name] = {"build_ms": dtd * 1e3, "class_ms": [round(float(x) / 2, 3) for x in msd],
                            "max_abs_dF_vs_autotuned": (Fmx - F64).abs().max().item()}
     digestion["classes"] = list(hfx.CLASS_NAMES)
-    digestion["launch_form"] = "persistent, 32768 quartets per task, no striping (the same for all three)"
+    digestion["launch_form"] = "persistent, 32768 quartets per task, no striping (the same for all four)"
     if tuning is not None:
         autotune.apply(ctx, tuning)
     else:
@@ -577,29 +578,36 @@ def main():
     Fd = (Fmx - F64).abs().max().item()
     dE = float(torch.sum(D * (Fmx - F64)).item())   # E = tr(D (H + F)) at fixed D
 
-    # roofline of the dominant kernel launch of the FP64 build: one class
-    # against one ket list (one kernel symbol at one grid size)
+    # roofline of the dominant kernel of the FP64 build (the kernel symbol and
+    # grid with the most summed time over its launches in a build), measured
+    # on its longest launch: one class against one ket list
     model = class_flop_model()
-    dom = max(plans64, key=lambda p: p["ms"])
-    per_prim, per_q, nint = model[dom["cls"]]
-    flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     import gen_eri   # on the path after class_flop_model(); "A": the class's alternative workgroup size
 
     def launch_shape(p):
         """Kernel symbol and grid of a plan's FP64 launch, as rocprofv3 names them."""
         alt = "A" if p["wgs"] != gen_eri.wg_size(p["cls"]) else ""
+        # kernel template digestion: 0 LDS rows (with or without staged D rows), 1 global atomics
+        # (into one matrix or the per-XCD copies)
+        mode = 0 if p["mode"] in (hfx.HFX_DIGEST_LDS, hfx.HFX_DIGEST_LDS_D) else 1
         if p["persistent"] in (3, 4):
-            return f"k_class_kr<Eval{p['cls']}{alt}, {p['mode']}, {p['ket_nprim']}, {p['bras_per_task']}> " \
+            return f"k_class_kr<Eval{p['cls']}{alt}, {mode}, {p['ket_nprim']}, {p['bras_per_task']}> " \
                    f"grid {p['blocks'] * p['wgs']}"
         form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave"}[p["persistent"]]
-        return f"{form}<Eval{p['cls']}{alt}, {p['mode']}, 0> grid {p['blocks'] * p['wgs']}"
+        return f"{form}<Eval{p['cls']}{alt}, {mode}, 0> grid {p['blocks'] * p['wgs']}"
 
-    kname = launch_shape(dom)
+    shape_ms = {}
+    for p in plans64:
+        shape_ms[launch_shape(p)] = shape_ms.get(launch_shape(p), 0.0) + p["ms"]
+    kname = max(shape_ms, key=shape_ms.get)
     # launches of one class against several ket lists can share a kernel and grid: the
     # profiles key each by its position among them in a build
     same = [q for q in plans64 if launch_shape(q) == kname]
+    dom = max(same, key=lambda p: p["ms"])
+    per_prim, per_q, nint = model[dom["cls"]]
+    flops_launch = dom["prim"] * per_prim + dom["quartets"] * per_q
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     kname_launch = f"{kname} launch {next(i for i, q in enumerate(same) if q is dom) + 1} of {len(same)}"
     total_flops = sum(counts[k, 2] * model[k][0] + counts[k, 0] * model[k][1] for k in range(21))
     traffic = None
@@ -638,7 +646,8 @@ def main():
                    "nbf": ctx.nbf, "shells": ctx.nshell, "quartets_per_build": quartets,
                    "integrals_per_build": int(counts[:, 1].sum()),
                    "primitive_quartets_per_build": int(counts[:, 2].sum()),
-                   "digest": "lds-staged" if args.digest == 0 else "global-atomic", "task_quartets": args.task},
+                   "digest": {0: "lds-staged F rows", 1: "global-atomic", 2: "private per-XCD copies",
+                              3: "lds-staged F and D rows"}[args.digest], "task_quartets": args.task},
         "mixed": {"value": value_mx, "unit": "quartets/s", "ms_per_step": dtmx / args.steps * 1e3,
                   "speedup_vs_fp64": dt64 / dtmx, "fp32_tau": 1e-7, "quartets_fp32": int(stmx.quartets_fp32),
                   "quartets_fp64": int(stmx.quartets_fp64), "max_abs_dF_vs_fp64": Fd,
@@ -647,6 +656,7 @@ def main():
                   "build_flops_model_tflops": total_flops / (dtmx / args.steps) / 1e12,
                   "build_frac_fp64_peak": total_flops / (dtmx / args.steps) / 1e12 / FP64_PEAK_TFLOPS},
         "roofline": {"bound": "alu", "kernel": kname, "launch": kname_launch, "class": hfx.CLASS_NAMES[dom["cls"]],
+                     "kernel_ms_per_build": shape_ms[kname] / max(dom["launches"], 1),
                      "ket_nprim": dom["ket_nprim"], "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic, "counted": counted,

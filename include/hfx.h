@@ -75,12 +75,18 @@ enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 };
 /* Digestion of the integrals into the Fock matrix (eq. 2):
  *   LDS      the bra's rows of the Fock matrix staged in LDS for a task and
  *            flushed once (algorithm 3's private F_I / F_J buffers);
+ *   LDS_D    as LDS, and the bra's rows of the density copied into LDS at
+ *            the start of a task, so that the exchange updates read D from
+ *            LDS instead of gathering it from global memory (both shells'
+ *            rows when they fit in LDS, else shell a's; classes with 600 or
+ *            more integrals per quartet and register-tiled launches read D
+ *            from global memory);
  *   GLOBAL   every update a device-wide atomic into one shared matrix;
  *   PRIVATE  every update an atomic into the copy of the matrix private to
  *            the XCD the wave runs on (algorithm 2's private Fock matrices,
  *            one per XCD: 8 copies of sum nbf_m^2 FP64 in HBM), summed by a
  *            reduction kernel after the class launches. */
-enum { HFX_DIGEST_LDS = 0, HFX_DIGEST_GLOBAL = 1, HFX_DIGEST_PRIVATE = 2 };
+enum { HFX_DIGEST_LDS = 0, HFX_DIGEST_GLOBAL = 1, HFX_DIGEST_PRIVATE = 2, HFX_DIGEST_LDS_D = 3 };
 enum { HFX_GUESS_SAD = 0, HFX_GUESS_CORE = 1, HFX_GUESS_LEARNED = 2 };
 
 /* Learned initial-guess network (see the section "Learned initial guess"). */
@@ -94,7 +100,7 @@ typedef struct {
                               1e-7); the classes with a d-d bra and a d-d or d-p
                               ket stay FP64.  One launch per class evaluates each
                               task's FP64 kets and its FP32 suffix (Q-sorted). */
-    int digest;            /* HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE */
+    int digest;            /* HFX_DIGEST_LDS, _GLOBAL, _PRIVATE or _LDS_D */
     int task_quartets;     /* quartets per workgroup task (default 8192; multiple of 256) */
     int log_level;         /* 0 silent, 1 SCF iterations to stderr */
 } hfx_options;
@@ -290,7 +296,7 @@ hfx_status hfx_configure(hfx_ctx *ctx, const hfx_options *opt);
  * fit), FP64 only -- a mixed build evaluates such a class in FP64; classes
  * or ket lists without register-tiled kernels fall back to 1; 4: as 3 with
  * one bra per task) and the digestion (-1: the context's
- * option; HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE; LDS staging needs
+ * option; HFX_DIGEST_LDS, _GLOBAL, _PRIVATE or _LDS_D; LDS staging needs
  * (n_a + n_b) x nbf x 8 bytes <= 160 KiB and falls back to global
  * otherwise).  Re-plans a loaded system; results are unchanged up to the
  * order of floating-point sums.  Set by the autotuner

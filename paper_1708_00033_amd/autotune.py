@@ -5,8 +5,8 @@ For every quartet class the library exposes four scheduling knobs
 long ket prefixes, the launch form (one workgroup per task, a persistent
 resident grid fed by per-XCD atomic work counters, or such a grid with one
 task per wave for short tasks, or register-tiled grids) and the digestion
-(bra rows staged in LDS, global atomics into one matrix, or into per-XCD
-private copies).  Results do not depend on them.  The tuner times each
+(bra rows of F staged in LDS, with or without the bra rows of D, global
+atomics into one matrix, or into per-XCD private copies).  Results do not depend on them.  The tuner times each
 candidate setting for all classes at once with the library's per-launch HIP
 events, keeps each class's fastest setting, applies it and returns the table
 (JSON-serialisable, keyed by class name).
@@ -23,7 +23,8 @@ from . import hfx
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
     (2048, 0, 0, -1), (2048, 1, 0, -1), (8192, 0, 0, -1), (8192, 1, 0, -1), (32768, 0, 0, -1), (32768, 1, 0, -1),
     (2048, 1, 1, -1), (8192, 1, 1, -1), (8192, 0, 0, 1), (32768, 0, 0, 1), (8192, 1, 2, -1), (32768, 0, 2, -1),
-    (32768, 0, 3, -1), (32768, 0, 4, -1), (8192, 1, 4, -1), (32768, 0, 1, 2), (32768, 0, 1, -1))
+    (32768, 0, 3, -1), (32768, 0, 4, -1), (8192, 1, 4, -1), (32768, 0, 1, 2), (32768, 0, 1, -1),
+    (32768, 0, 1, 0), (8192, 1, 0, 0))
 
 
 # Kept unless another candidate is clearly faster: the persistent form, whose

@@ -24,6 +24,7 @@
 // XCD the wave runs on; the copies are summed after the class launches.
 #pragma once
 #include "hfx_internal.h"
+#include <type_traits>
 
 #define HFX_WG 256
 // integral blocks at least this large are digested with rolled loops
@@ -45,12 +46,14 @@ __device__ __forceinline__ void row_add(double* lds_row, double* W, int grow, in
 // dket: the gathered D'_cd of the ket list ([component][ket position]); W
 // receives the J updates and WK the K updates of MODE 1 (one matrix for a
 // Fock build, separate J and K accumulators for a multi-density build).
-template <int NA, int NB, int NC, int ND, int MODE>
+// DST (LDS digestion): bit 0, the bra's D' rows of shell a come from their
+// LDS copy DI (same columns as FI); bit 1, those of shell b from DJ.
+template <int NA, int NB, int NC, int ND, int MODE, int DST = 0>
 __device__ __forceinline__ void digest(const double* I, double g, const ClassArgs& a, const PairInfo& bra,
                                        int fc, int fd, int spos, const double* dab, double* jab, double* FI,
                                        double* FJ, const double* __restrict__ D, double* W, int N,
                                        int RS, int cb, int db, const double* __restrict__ dket, double* WK,
-                                       double* wket) {
+                                       double* wket, const double* DI = nullptr, const double* DJ = nullptr) {
     const int fa = bra.bfa, fb = bra.bfb;
     const double cj2 = 2.0 * a.cj * g, ckg = -a.ck * g;
     // J, bra block: per-lane running sums over the task (reduced at the end)
@@ -88,7 +91,8 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 #pragma unroll
         for (int n = 0; n < NB; ++n)
 #pragma unroll
-            for (int s = 0; s < ND; ++s) dbd[n * ND + s] = D[(size_t)(fb + n) * N + fd + s];
+            for (int s = 0; s < ND; ++s)
+                dbd[n * ND + s] = (DST & 2) ? DJ[n * RS + fd + s - db] : D[(size_t)(fb + n) * N + fd + s];
 #pragma unroll
         for (int m = 0; m < NA; ++m)
 #pragma unroll
@@ -107,7 +111,8 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 #pragma unroll
         for (int m = 0; m < NA; ++m)
 #pragma unroll
-            for (int l = 0; l < NC; ++l) dac[m * NC + l] = D[(size_t)(fa + m) * N + fc + l];
+            for (int l = 0; l < NC; ++l)
+                dac[m * NC + l] = (DST & 1) ? DI[m * RS + fc + l - cb] : D[(size_t)(fa + m) * N + fc + l];
 #pragma unroll
         for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -126,7 +131,8 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 #pragma unroll
         for (int n = 0; n < NB; ++n)
 #pragma unroll
-            for (int l = 0; l < NC; ++l) dbc[n * NC + l] = D[(size_t)(fb + n) * N + fc + l];
+            for (int l = 0; l < NC; ++l)
+                dbc[n * NC + l] = (DST & 2) ? DJ[n * RS + fc + l - cb] : D[(size_t)(fb + n) * N + fc + l];
 #pragma unroll
         for (int m = 0; m < NA; ++m)
 #pragma unroll
@@ -145,7 +151,8 @@ __device__ __forceinline__ void digest(const double* I, double g, const ClassArg
 #pragma unroll
         for (int m = 0; m < NA; ++m)
 #pragma unroll
-            for (int s = 0; s < ND; ++s) dad[m * ND + s] = D[(size_t)(fa + m) * N + fd + s];
+            for (int s = 0; s < ND; ++s)
+                dad[m * ND + s] = (DST & 1) ? DI[m * RS + fd + s - db] : D[(size_t)(fa + m) * N + fd + s];
 #pragma unroll
         for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -496,11 +503,28 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         cb = wc * a.win;
         db = wd == wc ? cb : wd * a.win - half;
     }
-    // a wave's region is (NA + NB) a.rs doubles (a.rs >= RS for every molecule of a batch)
-    double* FI = lds + LdsLayout<E>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB) * a.rs : 0);
+    // LDS digestion with staged D' rows (classes with small integral
+    // blocks): DI, the bra's rows of shell a (dst bit 0), then DJ, those of
+    // shell b (bit 1), after F_I and F_J
+    constexpr bool CAN_STAGE = MODE == 0 && NI <= HFX_STAGE_D_MAX_NI && !E::PASSES;
+    const int dst = CAN_STAGE ? a.dstage : 0;
+    const int nda = (dst & 1) ? NA : 0, ndb = (dst & 2) ? NB : 0;
+    // a wave's region is (NA + NB + nda + ndb) a.rs doubles (a.rs >= RS for every molecule of a batch)
+    double* FI = lds + LdsLayout<E>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB + nda + ndb) * a.rs : 0);
     double* FJ = FI + NA * RS;
+    double* DI = FJ + NB * RS;
+    double* DJ = DI + nda * RS;
     if constexpr (MODE == 0) {
         for (int i = tid; i < (NA + NB) * RS; i += NT) FI[i] = 0.0;
+        // staged rows over the same columns as F_I / F_J (zero past the molecule's last column)
+        for (int i = tid; i < (nda + ndb) * RS; i += NT) {
+            const bool ra = i < nda * RS;
+            const int ii = ra ? i : i - nda * RS;
+            const int row = (ra ? bra.bfa : bra.bfb) + ii / RS;
+            const int lc = ii % RS;
+            const int col = lc + (lc < half ? cb : db);
+            DI[i] = col < N ? Dm[(size_t)row * N + col] : 0.0;
+        }
         task_sync<WAVE>();
     }
     double dab[NAB], jab[NAB];
@@ -543,33 +567,69 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     const int nw = NT / 64, wv = tid >> 6, ln = tid & 63;
     const int slots64 = (split - s0 + 63) >> 6;
     const int slots = slots64 + ((send - split + 63) >> 6);
-    for (int j = wv; j < slots && !E::PASSES; j += nw) {
-        const bool lo = j < slots64;   // wave-uniform
-        const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
-        if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
-        double I[NI];
-        if (!FP32 || lo) {
-            E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
-                                                 kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
-            ++n64;
-        } else if constexpr (FP32) {
-            // FP32 primitive copies, the FP64 Boys rows rounded
-            float If[NI];
-            E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
-                                                a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
+    // one copy of the ket loop per set of staged rows (the choice is uniform)
+    auto ket_loop = [&](auto dst_tag) {
+        constexpr int DST = decltype(dst_tag)::value;
+        for (int j = wv; j < slots; j += nw) {
+            const bool lo = j < slots64;   // wave-uniform
+            const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
+            if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
+            double I[NI];
+            if (!FP32 || lo) {
+                E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
+                                                     kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
+                ++n64;
+            } else if constexpr (FP32) {
+                float If[NI];
+                E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
+                                                    a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
 #pragma unroll
-            for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
-            ++n32;
+                for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
+                ++n32;
+            }
+            const int4 kb = a.kbf[s];
+            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+            digest<NA, NB, NC, ND, MODE, DST>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
+                                              a.dket, Wm, a.wket, DI, DJ);
         }
-        // the block (either precision) digested in FP64
-        const int4 kb = a.kbf[s];   // ket's first basis functions and shells
-        const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
-        if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
-                                                a.dket, Wm, a.wket);
+    };
+    if constexpr (CAN_STAGE) {
+        if (dst == 3)
+            ket_loop(std::integral_constant<int, 3>{});
+        else if (dst == 1)
+            ket_loop(std::integral_constant<int, 1>{});
         else
-            digest<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db, a.dket,
-                                         Wm, a.wket);
+            ket_loop(std::integral_constant<int, 0>{});
+    } else {
+        // the classes that never stage D' rows keep a plain loop
+        for (int j = wv; j < slots && !E::PASSES; j += nw) {
+            const bool lo = j < slots64;   // wave-uniform
+            const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
+            if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
+            double I[NI];
+            if (!FP32 || lo) {
+                E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
+                                                     kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
+                ++n64;
+            } else if constexpr (FP32) {
+                // FP32 primitive copies, the FP64 Boys rows rounded
+                float If[NI];
+                E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
+                                                    a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
+#pragma unroll
+                for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
+                ++n32;
+            }
+            // the block (either precision) digested in FP64
+            const int4 kb = a.kbf[s];   // ket's first basis functions and shells
+            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+            if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
+                digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS,
+                                                    cb, db, a.dket, Wm, a.wket);
+            else
+                digest<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
+                                             a.dket, Wm, a.wket);
+        }
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
     // outside the task's windows)

@@ -76,7 +76,7 @@ extern "C" hfx_status hfx_default_options(hfx_options* o) {
     o->schwarz_tau = 1e-10;
     o->precision = HFX_PREC_FP64;
     o->fp32_tau = 1e-7;
-    o->digest = HFX_DIGEST_LDS;
+    o->digest = HFX_DIGEST_LDS_D;
     o->task_quartets = 8192;
     o->log_level = 0;
     return HFX_OK;
@@ -103,8 +103,10 @@ static hfx_status check_options(hfx_ctx* c, const hfx_options* o) {
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "precision must be HFX_PREC_FP64 or HFX_PREC_MIXED");
     if (!(o->fp32_tau >= 0.0) || !std::isfinite(o->fp32_tau))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "fp32_tau must be finite and >= 0");
-    if (o->digest != HFX_DIGEST_LDS && o->digest != HFX_DIGEST_GLOBAL && o->digest != HFX_DIGEST_PRIVATE)
-        return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL or HFX_DIGEST_PRIVATE");
+    if (o->digest != HFX_DIGEST_LDS && o->digest != HFX_DIGEST_GLOBAL && o->digest != HFX_DIGEST_PRIVATE &&
+        o->digest != HFX_DIGEST_LDS_D)
+        return hfx_fail(c, HFX_ERR_INVALID_ARG,
+                        "digest must be HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL, HFX_DIGEST_PRIVATE or HFX_DIGEST_LDS_D");
     if (o->task_quartets < 256 || o->task_quartets % 256 != 0 || o->task_quartets > (1 << 24))
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "task_quartets must be a multiple of 256 in [256, 2^24]");
     return HFX_OK;
@@ -364,8 +366,24 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.lds_tab = (size_t)boys_lds_bytes();   // FP64 rows (the mixed kernels' FP32 part reads them too)
     const int digest = c->tune_digest[P.cid] >= 0 ? c->tune_digest[P.cid] : c->opt.digest;
     // 160 KiB of LDS per workgroup, less room for the persistent kernel's static counter
-    P.mode = (digest == HFX_DIGEST_LDS && P.lds_bytes + P.lds_tab <= 160 * 1024 - 256) ? 0 : 1;
+    constexpr size_t kLdsBudget = 160 * 1024 - 256;
+    const bool lds_digest = digest == HFX_DIGEST_LDS || digest == HFX_DIGEST_LDS_D;
+    P.mode = (lds_digest && P.lds_bytes + P.lds_tab <= kLdsBudget) ? 0 : 1;
     P.priv = digest == HFX_DIGEST_PRIVATE;   // global-atomic kernels into the per-XCD copies
+    // D' rows staged too: both shells' rows when they fit, else shell a's
+    // (the larger set); only for classes with small integral blocks
+    P.dstage = 0;
+    P.lds_dst = 0;
+    if (digest == HFX_DIGEST_LDS_D && P.mode == 0 && nint <= HFX_STAGE_D_MAX_NI) {
+        const size_t rows_a = (size_t)ncart(kPairL[B][0]) * c->rs * sizeof(double);
+        if (2 * P.lds_bytes + P.lds_tab <= kLdsBudget) {
+            P.dstage = 3;
+            P.lds_dst = P.lds_bytes;
+        } else if (P.lds_bytes + rows_a + P.lds_tab <= kLdsBudget) {
+            P.dstage = 1;
+            P.lds_dst = rows_a;
+        }
+    }
     // workgroup size: the class's alternative (smaller) size when two such
     // workgroups fit in LDS, else its default (a large group keeps the waves
     // per CU up when LDS admits one workgroup per CU)
@@ -376,6 +394,8 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     if ((form == 3 || form == 4) && hfx_class_has_kr(P.cid, KL.kp) && nbra < (1 << 28)) {
         P.kr = true;
         P.alt = 1;   // the register-tiled kernels use the class's alternative workgroup size
+        P.dstage = 0;   // their digestion reads D' from global memory
+        P.lds_dst = 0;
         P.nbl = form == 3 ? 2 : 1;
         if (P.mode == 0 && P.lds() > 160 * 1024 - 256) P.nbl = 1;
     }
@@ -526,7 +546,7 @@ extern "C" hfx_status hfx_set_class_tuning(hfx_ctx* c, int cid, int task_quartet
     if (xcd_stripe < -1 || xcd_stripe > 1) return hfx_fail(c, HFX_ERR_INVALID_ARG, "xcd_stripe must be -1, 0 or 1");
     if (persistent < 0 || persistent > 4)
         return hfx_fail(c, HFX_ERR_INVALID_ARG, "persistent must be 0, 1, 2, 3 or 4");
-    if (digest < -1 || digest > 2) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0, 1 or 2");
+    if (digest < -1 || digest > 3) return hfx_fail(c, HFX_ERR_INVALID_ARG, "digest must be -1, 0, 1, 2 or 3");
     for (int k = 0; k < 21; ++k)
         if (cid == -1 || cid == k) {
             c->tune_tq[k] = task_quartets;
@@ -1149,7 +1169,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[4] = p.prim;
     info[5] = p.integrals;
     info[6] = p.launches;
-    info[7] = p.priv ? 2 : p.mode;
+    info[7] = p.priv ? HFX_DIGEST_PRIVATE : p.mode == 1 ? HFX_DIGEST_GLOBAL : p.dstage ? HFX_DIGEST_LDS_D : HFX_DIGEST_LDS;
     info[8] = hfx_class_wgs(p.cid, p.alt);
     info[9] = p.kr ? c->tune_persist[p.cid] : (p.persist ? (p.wave ? 2 : 1) : 0);
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
@@ -1270,6 +1290,7 @@ hfx_status hfx_build_with(hfx_ctx* c, const BuildBufs& bufs, const double* dD, d
         a.split = mx ? P.d_split : nullptr;
         a.win = c->win;
         a.rs = c->rs;
+        a.dstage = P.dstage;
         a.moff = c->d_moff;
         a.tasks = P.d_tasks;
         a.boys64 = c->d_boys64;

@@ -43,6 +43,8 @@ struct SubPlan {
     int4* d_tasks = nullptr;
     long long quartets = 0, integrals = 0, prim = 0;
     size_t lds_bytes = 0;     // bra rows F_I, F_J (LDS digestion)
+    size_t lds_dst = 0;       // the bra's staged D' rows (LDS digestion with D rows)
+    int dstage = 0;           // ClassArgs::dstage: bit 0 shell a's D' rows staged, bit 1 shell b's
     size_t lds_tab = 0;       // the class's FP64 Boys rows in LDS
     int mode = 0;             // digestion actually used (LDS may fall back to global)
     // timing (when enabled): events around this launch, summed milliseconds
@@ -52,7 +54,7 @@ struct SubPlan {
     long long launches = 0;
     bool fp64_only = false;   // class built only in FP64 (mixed requests run FP64)
     // LDS of a workgroup: bra rows (one set per wave with one task per wave) and Boys rows
-    size_t lds() const { return (mode == 0 ? lds_bytes * (wave ? wave : nbl) : 0) + lds_tab; }
+    size_t lds() const { return (mode == 0 ? (lds_bytes + lds_dst) * (wave ? wave : nbl) : 0) + lds_tab; }
     bool persist = false;     // persistent launch through per-XCD work counters
     int wave = 0;             // > 0: one task per wave (persistent), this many waves per workgroup
     bool kr = false;          // register-tiled persistent kernel (ket primitives in registers), FP64

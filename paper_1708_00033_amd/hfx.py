@@ -40,7 +40,7 @@ HFX_ERR_STATE = 6
 STATUS_NAMES = {0: "HFX_OK", 1: "HFX_ERR_INVALID_ARG", 2: "HFX_ERR_OOM", 3: "HFX_ERR_DEVICE",
                 4: "HFX_ERR_NOT_CONVERGED", 5: "HFX_ERR_NUMERICAL", 6: "HFX_ERR_STATE"}
 HFX_PREC_FP64, HFX_PREC_MIXED = 0, 1
-HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL, HFX_DIGEST_PRIVATE = 0, 1, 2
+HFX_DIGEST_LDS, HFX_DIGEST_GLOBAL, HFX_DIGEST_PRIVATE, HFX_DIGEST_LDS_D = 0, 1, 2, 3
 HFX_GUESS_SAD, HFX_GUESS_CORE, HFX_GUESS_LEARNED = 0, 1, 2
 GUESS_NFEAT = 164
 GUESS_HEAD_OUT = (225, 30, 4)

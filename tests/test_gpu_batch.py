@@ -33,11 +33,16 @@ def test_batch_build_equals_individual_builds():
     for m, D in zip(mols, Ds):
         F, _ = hfx.Context().load(m).build_fock(D)
         refs.append(F)
-    for digest, persistent in ((0, 0), (1, 0), (0, 1), (0, 2), (1, 2)):
+    for digest, persistent in ((0, 0), (1, 0), (0, 1), (0, 2), (1, 2), (3, 0), (3, 1), (3, 2)):
         bctx = hfx.Context(digest=digest).load_batch(mols)
         bctx.set_class_tuning(-1, 2048, 1, persistent)
-        if persistent == 2 and digest == 0:   # one task per wave, LDS rows per wave, for some classes
+        if persistent == 2 and digest in (0, 3):   # one task per wave, LDS rows per wave, for some classes
             assert any(p["persistent"] == 2 for p in bctx.plans())
+        if digest == 3:   # D rows staged with the F rows (per wave in the per-wave form)
+            plans = bctx.plans()
+            assert any(p["mode"] == 3 for p in plans)
+            if persistent == 2:
+                assert any(p["mode"] == 3 and p["persistent"] == 2 for p in plans)
         nbf, nocc, off, tot = bctx.layout
         assert list(nbf) == [m.nbf for m in mols]
         assert tot == sum(m.nbf ** 2 for m in mols)

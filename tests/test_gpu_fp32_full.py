@@ -113,6 +113,29 @@ def test_fp32_kernels_random_density(four_waters):
     assert np.abs(F - (T + V + G)).max() <= FP32_RTOL * np.abs(G).max()
 
 
+@pytest.mark.parametrize("persistent,digest", [(0, 0), (0, 3), (1, 0), (1, 3), (2, 3)])
+def test_fp32_suffix_per_class_each_launch_form(persistent, digest):
+    """Mixed build with one class at a time in FP32 (the default fp32_tau):
+    its FP32 quartets have Q_ab Q_cd max|D| < 1e-7, so F moves from the FP64
+    build by far less than 1e-9, in every launch form and digestion; a
+    mis-evaluated FP32 suffix shows as an error many orders larger."""
+    hfx = _hfx()
+    m = W.water_cluster(3, 901)
+    D = W.random_symmetric(m.nbf, 71, 0.2)
+    ctx = hfx.Context(digest=digest).load(m)
+    ctx.set_class_tuning(-1, 2048, 1, persistent)
+    F64, _ = ctx.build_fock(D)
+    ctx.configure(precision=hfx.HFX_PREC_MIXED)
+    n32 = 0
+    for k in range(21):
+        ctx.set_class_precision(-1, 0)
+        ctx.set_class_precision(k, 1)
+        F, st = ctx.build_fock(D)
+        n32 += st.quartets_fp32
+        assert np.abs(F - F64).max() < 1e-9, (hfx.CLASS_NAMES[k], st.quartets_fp32)
+    assert n32 > 0
+
+
 @pytest.mark.parametrize("persistent", [0, 2])
 def test_fp32_kernels_batched(persistent):
     """A batch of two clusters, every eligible quartet in FP32, static and

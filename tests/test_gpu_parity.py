@@ -48,7 +48,7 @@ def test_one_electron_and_schwarz(four_waters):
     assert np.allclose(Q, Qo, rtol=1e-11, atol=1e-14)
 
 
-@pytest.mark.parametrize("digest", [0, 1])
+@pytest.mark.parametrize("digest", [0, 1, 3])
 def test_fock_parity_dimer(dimer, digest):
     m, B = dimer
     ctx = _hfx().Context(digest=digest).load(m)
@@ -60,7 +60,7 @@ def test_fock_parity_dimer(dimer, digest):
         assert st.quartets_fp64 == 14706
 
 
-@pytest.mark.parametrize("digest", [0, 1])
+@pytest.mark.parametrize("digest", [0, 1, 3])
 @pytest.mark.parametrize("task", [256, 2048])
 def test_fock_parity_all_classes(four_waters, digest, task):
     m, B = four_waters
@@ -118,7 +118,7 @@ def test_mixed_precision_dimer(dimer):
     assert abs(r["energy"] - r64["energy"]) < 1e-6
 
 
-@pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1), (2, -1)])
+@pytest.mark.parametrize("persistent,digest", [(0, -1), (1, -1), (0, 1), (1, 1), (2, -1), (1, 0), (2, 0)])
 def test_mixed_precision_16_waters(persistent, digest):
     """A mixed build evaluates each task's kets before its split in FP64 and
     the rest in FP32, in one launch; a 16-water cluster puts a large share in
@@ -284,7 +284,7 @@ def test_windowed_lds_digestion_112_waters():
     dD = torch.tensor(D, device="cuda")
     s = torch.cuda.current_stream().cuda_stream
     out = {}
-    for digest in (0, 1):
+    for digest in (0, 1, 3):
         ctx = _hfx().Context(digest=digest).load(m)
         J, K = torch.empty_like(dD), torch.empty_like(dD)
         ctx.build_2e_dev(dD.data_ptr(), 1.0, 0.0, J.data_ptr(), s)
@@ -293,9 +293,13 @@ def test_windowed_lds_digestion_112_waters():
         out[digest] = (J.cpu().numpy(), K.cpu().numpy())
         if digest == 0:
             assert {p["mode"] for p in ctx.plans()} >= {0}
-    (J0, K0), (J1, K1) = out[0], out[1]
+        if digest == 3:   # windowed rows of D staged beside those of F
+            assert {p["mode"] for p in ctx.plans()} >= {3}
+    (J0, K0), (J1, K1), (J3, K3) = out[0], out[1], out[3]
     assert np.abs(J0 - J1).max() <= 1e-12 * np.abs(J1).max()
     assert np.abs(K0 - K1).max() <= 1e-12 * np.abs(K1).max()
+    assert np.abs(J3 - J1).max() <= 1e-12 * np.abs(J1).max()
+    assert np.abs(K3 - K1).max() <= 1e-12 * np.abs(K1).max()
     B = oracle.Basis(m)
     bf = B.shell_bf
     for a, b in [(0, 3), (5, 5), (700, 1115), (1000, 13)]:
