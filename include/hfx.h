@@ -78,9 +78,10 @@ enum { HFX_PREC_FP64 = 0, HFX_PREC_MIXED = 1 };
  *   LDS_D    as LDS, and the bra's rows of the density copied into LDS at
  *            the start of a task, so that the exchange updates read D from
  *            LDS instead of gathering it from global memory (both shells'
- *            rows when they fit in LDS, else shell a's; classes with 600 or
- *            more integrals per quartet and register-tiled launches read D
- *            from global memory);
+ *            rows when they fit in LDS, else shell a's; classes with more
+ *            than 64 integrals per quartet, register-tiled launches and
+ *            column-windowed rows, above 2048 basis functions, read D from
+ *            global memory as LDS does; the default);
  *   GLOBAL   every update a device-wide atomic into one shared matrix;
  *   PRIVATE  every update an atomic into the copy of the matrix private to
  *            the XCD the wave runs on (algorithm 2's private Fock matrices,

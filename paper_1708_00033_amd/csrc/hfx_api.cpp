@@ -371,10 +371,12 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
     P.mode = (lds_digest && P.lds_bytes + P.lds_tab <= kLdsBudget) ? 0 : 1;
     P.priv = digest == HFX_DIGEST_PRIVATE;   // global-atomic kernels into the per-XCD copies
     // D' rows staged too: both shells' rows when they fit, else shell a's
-    // (the larger set); only for classes with small integral blocks
+    // (the larger set); only for classes with small integral blocks and
+    // whole rows (with column windows a task covers one pair of windows, and
+    // copying its rows cost more than the gathers it saved on 512 waters)
     P.dstage = 0;
     P.lds_dst = 0;
-    if (digest == HFX_DIGEST_LDS_D && P.mode == 0 && nint <= HFX_STAGE_D_MAX_NI) {
+    if (digest == HFX_DIGEST_LDS_D && P.mode == 0 && nint <= HFX_STAGE_D_MAX_NI && c->win == 0) {
         const size_t rows_a = (size_t)ncart(kPairL[B][0]) * c->rs * sizeof(double);
         if (2 * P.lds_bytes + P.lds_tab <= kLdsBudget) {
             P.dstage = 3;

@@ -293,8 +293,8 @@ def test_windowed_lds_digestion_112_waters():
         out[digest] = (J.cpu().numpy(), K.cpu().numpy())
         if digest == 0:
             assert {p["mode"] for p in ctx.plans()} >= {0}
-        if digest == 3:   # windowed rows of D staged beside those of F
-            assert {p["mode"] for p in ctx.plans()} >= {3}
+        if digest == 3:   # with column windows the rows of D are not staged
+            assert {p["mode"] for p in ctx.plans()} <= {0, 1}
     (J0, K0), (J1, K1), (J3, K3) = out[0], out[1], out[3]
     assert np.abs(J0 - J1).max() <= 1e-12 * np.abs(J1).max()
     assert np.abs(K0 - K1).max() <= 1e-12 * np.abs(K1).max()
