@@ -68,16 +68,20 @@ extern "C" int hfx_class_resident_blocks_kr(int cid, int mode, int kp, int nbl, 
 extern "C" int hfx_class_wgs(int cid, int alt) { return alt ? kEriClassInfo[cid].wgs_alt : kEriClassInfo[cid].wgs; }
 
 // alt: the class's alternative workgroup size (kEriClassInfo.wgs_alt);
-// wave: one task per wave (a persistent launch, args->work set).
-static int class_variant(int alt, int persistent, int wave, int mode, int mixed) {
-    return (wave ? 16 : 0) + (alt ? 8 : 0) + (persistent ? 4 : 0) + mode * 2 + mixed;
+// wave: one task per wave (a persistent launch, args->work set); dstage:
+// ClassArgs::dstage (0, 1 or 3), the kernel variant with staged D' rows.
+static int class_variant(int alt, int persistent, int wave, int mode, int mixed, int dstage) {
+    const int ds = dstage == 3 ? 2 : dstage == 1 ? 1 : 0;
+    return ds * 32 + (wave ? 16 : 0) + (alt ? 8 : 0) + (persistent ? 4 : 0) + mode * 2 + mixed;
 }
 
 extern "C" hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int nblocks,
                                        size_t lds_bytes, hipStream_t stream, const ClassArgs* args) {
     if (nblocks <= 0) return hipSuccess;
     if (wave && !args->work) return hipErrorInvalidValue;
-    const void* fn = kClassLookup[cid](class_variant(alt, args->work != nullptr, wave, mode, mixed));
+    if (args->dstage != 0 && args->dstage != 1 && args->dstage != 3) return hipErrorInvalidValue;
+    const void* fn = kClassLookup[cid](class_variant(alt, args->work != nullptr, wave, mode, mixed, args->dstage));
+    if (!fn) return hipErrorInvalidValue;
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -87,8 +91,10 @@ extern "C" hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int
 }
 
 // Workgroups of one class kernel that fit on the device at once.
-extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes) {
-    const void* fn = kClassLookup[cid](class_variant(alt, 1, wave, mode, mixed));
+extern "C" int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, int dstage,
+                                         size_t lds_bytes) {
+    const void* fn = kClassLookup[cid](class_variant(alt, 1, wave, mode, mixed, dstage));
+    if (!fn) return 0;
     if (lds_bytes > 64 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess)
         return 0;
@@ -119,13 +125,15 @@ extern "C" hipError_t hfx_launch_class_multi(int cid, int mode, int nblocks, siz
 
 // Largest per-lane private segment (scratch) in bytes and largest register
 // count over every kernel variant of class cid (launch form, digestion,
-// precision, workgroup size), read from the code object's metadata without a
-// launch.
+// staged D' rows, precision, workgroup size), read from the code object's
+// metadata without a launch.
 extern "C" hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs) {
     long long sc = 0;
     int rg = 0;
-    for (int v = 0; v < 32 + 12 + 2; ++v) {
-        const void* fn = v < 32 ? kClassLookup[cid](v) : (v < 44 ? kClassLookupKr[cid](v - 32) : kMultiLookup[cid](v - 44));
+    for (int v = 0; v < 128 + 12 + 2; ++v) {
+        const void* fn = v < 128   ? kClassLookup[cid](v)
+                         : v < 140 ? kClassLookupKr[cid](v - 128)
+                                   : kMultiLookup[cid](v - 140);
         if (!fn) continue;
         hipFuncAttributes fa;
         const hipError_t e = hipFuncGetAttributes(&fa, fn);

@@ -24,7 +24,6 @@
 // XCD the wave runs on; the copies are summed after the class launches.
 #pragma once
 #include "hfx_internal.h"
-#include <type_traits>
 
 #define HFX_WG 256
 // integral blocks at least this large are digested with rolled loops
@@ -470,7 +469,9 @@ __device__ __forceinline__ void task_sync() {
 // One task (one bra, a range of its kets) on the lanes of the workgroup or
 // (WAVE) of one wave, whose bra rows are the wave's own LDS region.
 // Evaluated quartets go to the lane's running counts cnt64 / cnt32.
-template <class E, int MODE, int FP32, bool WAVE = false>
+// DST: the bra's D' rows staged in LDS for the LDS digestion (bit 0 shell
+// a's, bit 1 shell b's), a kernel variant of the classes with small blocks.
+template <class E, int MODE, int FP32, bool WAVE = false, int DST = 0>
 __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, const double* t64, unsigned& cnt64,
                                            unsigned& cnt32) {
     static_assert(!(FP32 && E::PASSES), "classes evaluated in passes are FP64 only");
@@ -503,12 +504,10 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
         cb = wc * a.win;
         db = wd == wc ? cb : wd * a.win - half;
     }
-    // LDS digestion with staged D' rows (classes with small integral
-    // blocks): DI, the bra's rows of shell a (dst bit 0), then DJ, those of
-    // shell b (bit 1), after F_I and F_J
-    constexpr bool CAN_STAGE = MODE == 0 && NI <= HFX_STAGE_D_MAX_NI && !E::PASSES;
-    const int dst = CAN_STAGE ? a.dstage : 0;
-    const int nda = (dst & 1) ? NA : 0, ndb = (dst & 2) ? NB : 0;
+    // LDS digestion with staged D' rows: DI, the bra's rows of shell a (DST
+    // bit 0), then DJ, those of shell b (bit 1), after F_I and F_J
+    static_assert(DST == 0 || (MODE == 0 && NI <= HFX_STAGE_D_MAX_NI && !E::PASSES), "no staged D' rows");
+    constexpr int nda = (DST & 1) ? NA : 0, ndb = (DST & 2) ? NB : 0;
     // a wave's region is (NA + NB + nda + ndb) a.rs doubles (a.rs >= RS for every molecule of a batch)
     double* FI = lds + LdsLayout<E>::ROWS + (WAVE ? (int)(threadIdx.x >> 6) * (NA + NB + nda + ndb) * a.rs : 0);
     double* FJ = FI + NA * RS;
@@ -567,69 +566,33 @@ __device__ __forceinline__ void class_task(const ClassArgs& a, const int ti, con
     const int nw = NT / 64, wv = tid >> 6, ln = tid & 63;
     const int slots64 = (split - s0 + 63) >> 6;
     const int slots = slots64 + ((send - split + 63) >> 6);
-    // one copy of the ket loop per set of staged rows (the choice is uniform)
-    auto ket_loop = [&](auto dst_tag) {
-        constexpr int DST = decltype(dst_tag)::value;
-        for (int j = wv; j < slots; j += nw) {
-            const bool lo = j < slots64;   // wave-uniform
-            const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
-            if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
-            double I[NI];
-            if (!FP32 || lo) {
-                E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
-                                                     kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
-                ++n64;
-            } else if constexpr (FP32) {
-                float If[NI];
-                E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
-                                                    a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
+    for (int j = wv; j < slots && !E::PASSES; j += nw) {
+        const bool lo = j < slots64;   // wave-uniform
+        const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
+        if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
+        double I[NI];
+        if (!FP32 || lo) {
+            E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
+                                                 kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
+            ++n64;
+        } else if constexpr (FP32) {
+            // FP32 primitive copies, the FP64 Boys rows rounded
+            float If[NI];
+            E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
+                                                a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
 #pragma unroll
-                for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
-                ++n32;
-            }
-            const int4 kb = a.kbf[s];
-            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+            for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
+            ++n32;
+        }
+        // the block (either precision) digested in FP64
+        const int4 kb = a.kbf[s];   // ket's first basis functions and shells
+        const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
+        if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
+            digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
+                                                a.dket, Wm, a.wket);
+        else
             digest<NA, NB, NC, ND, MODE, DST>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
                                               a.dket, Wm, a.wket, DI, DJ);
-        }
-    };
-    if constexpr (CAN_STAGE) {
-        if (dst == 3)
-            ket_loop(std::integral_constant<int, 3>{});
-        else if (dst == 1)
-            ket_loop(std::integral_constant<int, 1>{});
-        else
-            ket_loop(std::integral_constant<int, 0>{});
-    } else {
-        // the classes that never stage D' rows keep a plain loop
-        for (int j = wv; j < slots && !E::PASSES; j += nw) {
-            const bool lo = j < slots64;   // wave-uniform
-            const int s = lo ? s0 + (j << 6) + ln : split + ((j - slots64) << 6) + ln;
-            if (s >= (lo ? split : send)) continue;   // the part's last, partial slot
-            double I[NI];
-            if (!FP32 || lo) {
-                E::template run<double, BOYS_LROW64>((const double*)(a.prim + bra.prim_off), bra.nprim, a.kprim + s,
-                                                     kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, I);
-                ++n64;
-            } else if constexpr (FP32) {
-                // FP32 primitive copies, the FP64 Boys rows rounded
-                float If[NI];
-                E::template run<float, BOYS_LROW64>(a.prim32 + (size_t)bra.prim_off * HFX_PRIM_FIELDS, bra.nprim,
-                                                    a.kprim32 + s, kfs, kps, a.knprim, bra.AB, a.ket[s].AB, t64, If);
-#pragma unroll
-                for (int i = 0; i < NI; ++i) I[i] = (double)If[i];
-                ++n32;
-            }
-            // the block (either precision) digested in FP64
-            const int4 kb = a.kbf[s];   // ket's first basis functions and shells
-            const double g = sbra * (kb.z != kb.w ? 2.0 : 1.0) * ((kb.z == bra.a && kb.w == bra.b) ? 1.0 : 2.0);
-            if constexpr (NI >= HFX_ROLLED_DIGEST_MIN)
-                digest_rolled<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS,
-                                                    cb, db, a.dket, Wm, a.wket);
-            else
-                digest<NA, NB, NC, ND, MODE>(I, g, a, bra, kb.x, kb.y, s, dab, jab, FI, FJ, Dm, Wm, N, RS, cb, db,
-                                             a.dket, Wm, a.wket);
-        }
     }
     // bra J block: wave reduction, one global add per wave (column bfb may lie
     // outside the task's windows)
@@ -966,7 +929,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_multi(const ClassArgs a) {
 
 // Static launch: workgroup i runs task task_off + i (a plan's tasks may span
 // several launches: a grid is limited to 2^32 work-items).
-template <class E, int MODE, int FP32>
+template <class E, int MODE, int FP32, int DST = 0>
 __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ unsigned long long wg_count[2];   // the workgroup's counts: one global add each
@@ -976,7 +939,7 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
     if (threadIdx.x == 0) wg_count[0] = wg_count[1] = 0;
     load_boys_lds<E>(a, lds);   // ends with a barrier
     unsigned cnt64 = 0, cnt32 = 0;
-    class_task<E, MODE, FP32>(a, ti, lds, cnt64, cnt32);
+    class_task<E, MODE, FP32, false, DST>(a, ti, lds, cnt64, cnt32);
     const unsigned long long s64 = (unsigned long long)wave_sum((double)cnt64);
     const unsigned long long s32 = (unsigned long long)wave_sum((double)cnt32);
     if ((threadIdx.x & 63) == 0) {
@@ -997,7 +960,7 @@ __global__ __launch_bounds__(E::WGS) void k_class(const ClassArgs a) {
 // no XCD idles while another still has work (the dynamic load balancing of
 // ddi_dlbnext in algorithms 1-3).  A separate kernel so that the static
 // form keeps its register allocation.
-template <class E, int MODE, int FP32>
+template <class E, int MODE, int FP32, int DST = 0>
 __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     __shared__ int next_entry;
@@ -1014,7 +977,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, FP32>(a, 8 * k + x, lds, cnt64, cnt32);
+        class_task<E, MODE, FP32, false, DST>(a, 8 * k + x, lds, cnt64, cnt32);
     }
     flush_counts(a, cnt64, cnt32);
 }
@@ -1024,7 +987,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_persist(const ClassArgs a) {
 // k_class_persist) and digests into its own LDS bra rows, so short tasks
 // (small molecules of a batch) occupy 64 lanes instead of a workgroup.  The
 // Boys rows are shared by the workgroup's waves.
-template <class E, int MODE, int FP32>
+template <class E, int MODE, int FP32, int DST = 0>
 __global__ __launch_bounds__(E::WGS) void k_class_wave(const ClassArgs a) {
     extern __shared__ __align__(16) double lds[];
     load_boys_lds<E>(a, lds);
@@ -1039,7 +1002,7 @@ __global__ __launch_bounds__(E::WGS) void k_class_wave(const ClassArgs a) {
             ++q;
             continue;
         }
-        class_task<E, MODE, FP32, true>(a, 8 * k + x, lds, cnt64, cnt32);
+        class_task<E, MODE, FP32, true, DST>(a, 8 * k + x, lds, cnt64, cnt32);
     }
     flush_counts(a, cnt64, cnt32);
 }
@@ -1086,9 +1049,29 @@ template <class E>
 struct ClassKernelsOne {
     static constexpr int NI = hfx_ncart(E::LA) * hfx_ncart(E::LB) * hfx_ncart(E::LC) * hfx_ncart(E::LD);
     static constexpr bool kOnlyFp64Global = NI >= HFX_ROLLED_DIGEST_MIN;
+    static constexpr bool kStage = NI <= HFX_STAGE_D_MAX_NI && !E::PASSES;
+    // LDS digestion with staged D' rows (DST 1: shell a's, 3: both shells'):
+    // form 0 static, 1 persistent, 2 one task per wave
+    template <int DST>
+    static const void* staged(int form, int mixed) {
+        static const void* t[6] = {(const void*)k_class<E, 0, 0, DST>,         (const void*)k_class<E, 0, 1, DST>,
+                                   (const void*)k_class_persist<E, 0, 0, DST>, (const void*)k_class_persist<E, 0, 1, DST>,
+                                   (const void*)k_class_wave<E, 0, 0, DST>,    (const void*)k_class_wave<E, 0, 1, DST>};
+        return t[2 * form + mixed];
+    }
     // variant = 4 persistent + 2 mode + mixed (FP64 prefix and FP32 suffix of
-    // every task); bit 4: one task per wave (persistent)
+    // every task); bit 4: one task per wave (persistent); bits 5-6: staged
+    // D' rows (1: shell a's, 2: both shells'; LDS digestion only)
     static const void* get(int variant) {
+        if (const int ds = (variant >> 5) & 3) {
+            if constexpr (kStage) {
+                if (variant & 2) return nullptr;
+                const int form = (variant & 16) ? 2 : (variant & 4) ? 1 : 0;
+                return ds == 1 ? staged<1>(form, variant & 1) : staged<3>(form, variant & 1);
+            } else {
+                return nullptr;
+            }
+        }
         if (variant & 16) {
             if constexpr (kOnlyFp64Global) {
                 return (variant & 2) ? (const void*)k_class_wave<E, 1, 0> : (const void*)k_class_wave<E, 0, 0>;
@@ -1118,9 +1101,9 @@ template <class E, class EA>
 struct ClassKernels {
     static const void* get(int variant) {
         if constexpr (EA::WGS != E::WGS) {
-            if (variant & 8) return ClassKernelsOne<EA>::get(variant & 23);
+            if (variant & 8) return ClassKernelsOne<EA>::get(variant & 119);
         }
-        return ClassKernelsOne<E>::get(variant & 23);
+        return ClassKernelsOne<E>::get(variant & 119);
     }
 };
 

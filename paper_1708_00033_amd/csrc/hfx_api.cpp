@@ -484,7 +484,7 @@ static hfx_status plan_sub(hfx_ctx* c, int B, int li, const std::vector<PairInfo
         P.nblocks[0] = P.nblocks[1] = ((nb + 7) / 8) * 8;
     }
     for (int mx = 0; mx < (P.kr ? 0 : (P.fp64_only ? 1 : 2)); ++mx) {
-        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, P.lds());
+        int nb = hfx_class_resident_blocks(P.cid, P.alt, P.wave > 0, P.mode, mx, P.dstage, P.lds());
         if (nb <= 0) return hfx_fail(c, HFX_ERR_DEVICE, "occupancy query of a class kernel failed");
         nb = std::min(nb, P.ntask);
         P.nblocks[mx] = ((nb + 7) / 8) * 8;   // whole rounds over the 8 XCDs

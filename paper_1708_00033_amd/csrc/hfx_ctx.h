@@ -222,7 +222,7 @@ hipError_t hfx_pad_rest(const int* dim, int nmol, int NP, double pad, double* ds
 // eri_dispatch.hip
 hipError_t hfx_launch_class(int cid, int alt, int wave, int mode, int mixed, int nblocks, size_t lds_bytes,
                             hipStream_t stream, const ClassArgs* args);
-int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, size_t lds_bytes);
+int hfx_class_resident_blocks(int cid, int alt, int wave, int mode, int mixed, int dstage, size_t lds_bytes);
 int hfx_class_wgs(int cid, int alt);
 hipError_t hfx_class_kernel_resources(int cid, long long* scratch_bytes, int* regs);
 int hfx_class_has_kr(int cid, int kp);
