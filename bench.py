@@ -594,7 +594,7 @@ def main():
             return f"k_class_kr<Eval{p['cls']}{alt}, {mode}, {p['ket_nprim']}, {p['bras_per_task']}> " \
                    f"grid {p['blocks'] * p['wgs']}"
         form = {0: "k_class", 1: "k_class_persist", 2: "k_class_wave"}[p["persistent"]]
-        return f"{form}<Eval{p['cls']}{alt}, {mode}, 0> grid {p['blocks'] * p['wgs']}"
+        return f"{form}<Eval{p['cls']}{alt}, {mode}, 0, {p['dstage']}> grid {p['blocks'] * p['wgs']}"
 
     shape_ms = {}
     for p in plans64:

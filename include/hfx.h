@@ -333,11 +333,12 @@ hfx_status hfx_kernel_times(hfx_ctx *ctx, double *ms, long long *launches);
 hfx_status hfx_set_streams(hfx_ctx *ctx, int n);
 
 /* Launches of a build: one per (quartet class, ket primitive count).
- * info[12] = {class index, ket primitives per pair, workgroup tasks, unique
+ * info[13] = {class index, ket primitives per pair, workgroup tasks, unique
  * quartets, primitive quartets, integrals, timed launches, digestion used
  * (HFX_DIGEST_*),
  * work-items per workgroup, launch form (0..4 as in hfx_set_class_tuning),
- * workgroups of the FP64 kernel, bras per task}; *ms = summed event time of
+ * workgroups of the FP64 kernel, bras per task, staged D' rows: 0 none, 1
+ * shell a's, 3 both shells'}; *ms = summed event time of
  * the timed launches. */
 hfx_status hfx_plan_count(const hfx_ctx *ctx, int *n);
 hfx_status hfx_plan_info(hfx_ctx *ctx, int i, long long *info, double *ms);

@@ -1176,6 +1176,7 @@ extern "C" hfx_status hfx_plan_info(hfx_ctx* c, int i, long long* info, double* 
     info[9] = p.kr ? c->tune_persist[p.cid] : (p.persist ? (p.wave ? 2 : 1) : 0);
     info[10] = p.persist ? p.nblocks[0] : p.ntask;   // the FP64 kernel's grid
     info[11] = p.nbl;
+    info[12] = p.dstage;
     if (ms) *ms = p.ms;
     return HFX_OK;
 }

@@ -468,18 +468,18 @@ class Context:
 
     def plans(self):
         """Per launch: dict(cls, ket_nprim, tasks, quartets, prim, integrals, launches, mode, wgs,
-        persistent, blocks, ms)."""
+        persistent, blocks, bras_per_task, dstage, ms)."""
         n = C.c_int()
         self._check(hfx_plan_count(self.ptr, C.byref(n)))
         out = []
         for i in range(n.value):
-            info = (C.c_longlong * 12)()
+            info = (C.c_longlong * 13)()
             ms = C.c_double()
             self._check(hfx_plan_info(self.ptr, i, info, C.byref(ms)))
             out.append(dict(cls=int(info[0]), ket_nprim=int(info[1]), tasks=int(info[2]), quartets=int(info[3]),
                             prim=int(info[4]), integrals=int(info[5]), launches=int(info[6]), mode=int(info[7]),
                             wgs=int(info[8]), persistent=int(info[9]), blocks=int(info[10]),
-                            bras_per_task=int(info[11]), ms=ms.value))
+                            bras_per_task=int(info[11]), dstage=int(info[12]), ms=ms.value))
         return out
 
     def kernel_times(self):
