@@ -20,7 +20,7 @@ struct PrimPair {
 };
 #define HFX_PRIM_FIELDS 10   // elements of one PrimPair (an FP32 copy has the same layout in floats)
 // LDS digestion with the bra's D' rows staged in LDS: classes with at most
-// this many integrals per quartet (one more copy of the ket loop each)
+// this many integrals per quartet (two more kernel variants per launch form)
 #define HFX_STAGE_D_MAX_NI 64
 
 // One shell pair in canonical orientation: shells a (higher l) and b, their
@@ -69,7 +69,7 @@ struct ClassArgs {
     long long dstride, kstride;
     double* WK;
     int win, rs;                        // column window (0: whole rows) and LDS bra-row length (doubles)
-    int dstage;                         // LDS digestion: bit 0 the bra's D' rows of shell a staged in LDS, bit 1 those of b
+    int dstage;                         // staged D' rows (0, 1: shell a's, 3: both): selects the kernel variant
     int task_off;                       // static launch: workgroup i runs task task_off + i
     unsigned long long* __restrict__ work;  // persistent launch: 8 per-XCD queue counters (zeroed before the
                                             // launch); null: one task per workgroup
